@@ -1,0 +1,188 @@
+/*
+ * spgemm.h -- C ABI of the one-GPU, memory-constrained, sort-free SpGEMM
+ * library for MI355X (gfx950).
+ *
+ * The library computes C = A*B over (+, *) with A (m x k), B (k x n) and C
+ * in compressed sparse column (CSC) form, following "Communication-Avoiding
+ * and Memory-Constrained Sparse Matrix-Matrix Multiplication at Extreme
+ * Scale" (Hussain, Selvitopi, Buluc, Azad; arXiv 2010.08526):
+ *   - the product is Gustavson's column formula, C(:,j) = sum over k with
+ *     B(k,j) != 0 of A(:,k)*B(k,j) (Sec. II-C);
+ *   - a symbolic pass counts the nonzeros of the output before any value is
+ *     formed (Alg. 3, LocalSymbolic);
+ *   - the output is formed in b batches of whole columns, b chosen from the
+ *     available memory (Sec. IV-A, Eq. 2, Alg. 3 and Alg. 4);
+ *   - local multiplication and merging use hash tables and never sort
+ *     (Sec. IV-D, sort-free local SpGEMM and sort-free hash merging);
+ *   - the inner dimension may be split into layers whose partial products
+ *     are merged afterwards (Sec. III-B, Alg. 2, Merge-Layer/Merge-Fiber).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns an int status (spgemm_status); nothing throws
+ *     across the ABI.  Argument checks (NULLs, shapes, dtypes, sizes) run on
+ *     the host before anything is launched.
+ *   - Pointers inside spgemm_csc and all array arguments named *_out or
+ *     c_* point to DEVICE memory unless the name ends in _host.  All device
+ *     memory is owned by the caller; the library never allocates device
+ *     memory.  Scratch memory is passed in as `ws` (device, at least
+ *     `ws_bytes` bytes, 256-byte aligned) and sized by
+ *     spgemm_workspace_size().
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Device work is
+ *     enqueued asynchronously on it; calls return before it completes unless
+ *     documented otherwise.  Calls on different streams must use different
+ *     workspaces.
+ *   - Row indices inside a column may come in any order but must be unique;
+ *     outputs are written in hash-table order (unsorted), except where noted.
+ *     Structure is structural: an output entry exists wherever some product
+ *     term exists, even if its terms cancel to zero.
+ *   - Values of A and B share one dtype; outputs take that dtype.  Float32
+ *     inputs are accumulated in float64 inside the library and rounded once.
+ */
+#ifndef SPGEMM_H_
+#define SPGEMM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPGEMM_OK = 0,
+  SPGEMM_E_INVAL = -1,     /* NULL pointer, negative size, bad range, bad op */
+  SPGEMM_E_SHAPE = -2,     /* inner dimensions or part shapes disagree */
+  SPGEMM_E_DTYPE = -3,     /* unknown dtype or mixed dtypes */
+  SPGEMM_E_BUDGET = -4,    /* memory budget cannot hold inputs, reserve or one column */
+  SPGEMM_E_WORKSPACE = -5, /* ws NULL, misaligned or smaller than required */
+  SPGEMM_E_HIP = -6,       /* a HIP call or launch failed; see spgemm_last_hip_error() */
+  SPGEMM_E_OVERFLOW = -7,  /* a size does not fit the index types (rows > INT32_MAX, ...) */
+  SPGEMM_E_DEVICE = -8     /* a device-side check failed (reported by spgemm_ws_status) */
+} spgemm_status;
+
+typedef enum { SPGEMM_F32 = 0, SPGEMM_F64 = 1 } spgemm_dtype;
+
+/* A CSC matrix.  colptr[ncols+1] (int64, colptr[0] = 0, nondecreasing,
+ * colptr[ncols] = nnz), rowidx[nnz] (int32, 0 <= row < nrows, unique within
+ * a column, any order), values[nnz] of `dtype` (may be NULL where only the
+ * pattern is read).  All three arrays are device memory. */
+typedef struct spgemm_csc {
+  int64_t nrows, ncols, nnz;
+  const int64_t *colptr;
+  const int32_t *rowidx;
+  const void *values;
+  int32_t dtype;
+} spgemm_csc;
+
+/* Operations for spgemm_workspace_size(). */
+typedef enum {
+  SPGEMM_OP_SYMBOLIC = 0,
+  SPGEMM_OP_NUMERIC = 1,
+  SPGEMM_OP_MERGE = 2,
+  SPGEMM_OP_COLPTR = 3,
+  SPGEMM_OP_MASKED_XTY = 4,
+  SPGEMM_OP_TRANSPOSE = 5
+} spgemm_op;
+
+/* Workspace bytes needed by one call of `op`.  Host only; never syncs.
+ *   SYMBOLIC, NUMERIC: A, B and columns [c0,c1) as passed to that call;
+ *                      n_layers as passed (>= 1).
+ *   MERGE:             A = any one part (its nrows and ncols), B unused,
+ *                      n_layers = number of parts.
+ *   COLPTR:            c1 - c0 = number of counts; A, B unused (may be NULL).
+ *   MASKED_XTY:        A = X, B = Y (M has Y's column count).
+ *   TRANSPOSE:         A = the matrix to transpose.
+ * The result depends only on shapes, never on device data. */
+int spgemm_workspace_size(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t c1,
+                          int32_t n_layers, size_t *bytes_host);
+
+/* Symbolic pass (Alg. 3, LocalSymbolic, for one process; flops per Sec. II-A).
+ * For every output column j in [c0,c1) of C = A*B:
+ *   flops_out[j-c0] = sum over k in B(:,j) of nnz(A(:,k))   (int64; may be NULL),
+ *   nnz_out[j-c0]   = number of distinct rows of C(:,j)      when n_layers == 1.
+ * With n_layers = L > 1 the inner dimension [0,k) is split into L contiguous
+ * ranges of width w = ceil(k/L) (layer l covers [l*w, min(k,(l+1)*w)), some
+ * possibly empty; Sec. III-B, Alg. 2) and nnz_out holds (L+1) rows of
+ * (c1-c0) int64 each: row l = nnz of column j of the layer product
+ * A(:,K_l)*B(K_l,:), row L = nnz of C(:,j).  Counts come from hash tables,
+ * not from bounds.  Asynchronous on `stream`. */
+int spgemm_symbolic(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t c1, int32_t n_layers,
+                    int64_t *flops_out, int64_t *nnz_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Batch planner (Eq. 2 and Alg. 3 with one process; Alg. 4 ColSplit).  Host
+ * only; reads nothing from the device.
+ * nnz_host: the symbolic counts copied to the host, same layout as nnz_out
+ * (ncols columns; (L+1) rows if n_layers > 1).  Memory of output column j:
+ *   L == 1: r*u_j + 8
+ *   L  > 1: r*(sum over l of u_j^l) + 8*L  +  r*u_j + 8
+ * with r = 4 + value_bytes (int32 row + value) and 8 bytes of column pointer
+ * per column per stored matrix; with layers both the partials and the merged
+ * output of a batch are resident.  The memory available to outputs is
+ *   avail = budget_bytes - input_bytes - reserve_bytes.
+ * The result is the smallest number b of contiguous column batches whose
+ * memory each fits in avail (never below ceil(total/avail), the Eq. 2 bound),
+ * split so that the largest batch is as small as possible (greedy packing
+ * from the left under that smallest cap).  Outputs:
+ *   bounds_host[0..b]  column bounds (bounds_host[0] = 0, bounds_host[b] = ncols),
+ *   *nbatches_host     = b,
+ *   batch_nnz_host     (may be NULL) [b * rows] totals of each count row per
+ *                      batch (rows = L+1 if L > 1 else 1), batch-major.
+ * bounds_host needs max_batches+1 entries, batch_nnz_host max_batches*rows.
+ * Errors: SPGEMM_E_BUDGET when avail <= 0, when one column alone exceeds
+ * avail, or when more than max_batches batches would be needed. */
+int spgemm_plan_batches(const int64_t *nnz_host, int64_t ncols, int32_t n_layers, int32_t value_bytes,
+                        uint64_t input_bytes, uint64_t budget_bytes, uint64_t reserve_bytes, int32_t max_batches,
+                        int64_t *bounds_host, int32_t *nbatches_host, int64_t *batch_nnz_host);
+
+/* Column pointers from counts: colptr_out[0] = 0 and
+ * colptr_out[i+1] = counts[0] + ... + counts[i] for i < n (an exclusive
+ * scan, int64).  counts and colptr_out are device arrays of n and n+1
+ * entries.  Asynchronous. */
+int spgemm_colptr(const int64_t *counts, int64_t n, int64_t *colptr_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Numeric pass: sort-free hash SpGEMM (Sec. IV-D).  Forms columns [c0,c1) of
+ * the layer product A(:,K_layer)*B(K_layer,:) (n_layers = 1, layer = 0: the
+ * full product) into c_rowidx/c_values at c_colptr[j-c0] .. c_colptr[j-c0+1],
+ * which must come from the matching symbolic counts (spgemm_colptr of the
+ * layer's row).  c_colptr has c1-c0+1 entries and may start at any offset.
+ * Rows within each output column are in hash-table order.  `flops` is the
+ * symbolic flops_out of the same columns (may be NULL).  Asynchronous; a
+ * mismatch between counts and the product sets the workspace status
+ * (spgemm_ws_status). */
+int spgemm_numeric(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t c1, int32_t layer,
+                   int32_t n_layers, const int64_t *flops, const int64_t *c_colptr, int32_t *c_rowidx,
+                   void *c_values, void *ws, size_t ws_bytes, void *stream);
+
+/* Sort-free hash merge (Sec. IV-D, sort-free hash merging; Merge in Alg. 1
+ * and Alg. 2): C(:,j) = sum over parts of parts[p](:,j), entries with equal
+ * row added.  parts is a HOST array of n_parts descriptors (device arrays
+ * inside), all with the same nrows, ncols and dtype, 1 <= n_parts <= 4096.
+ * c_colptr (ncols+1) comes from the union counts (row L of the symbolic
+ * output for the batch).  Output rows in hash-table order.  Asynchronous. */
+int spgemm_merge(const spgemm_csc *parts, int32_t n_parts, const int64_t *c_colptr, int32_t *c_rowidx,
+                 void *c_values, void *ws, size_t ws_bytes, void *stream);
+
+/* Synchronizes `stream` and reports the device-side status word of a
+ * workspace used by the calls above: SPGEMM_OK, or SPGEMM_E_DEVICE if a
+ * kernel found counts that disagree with the product or an index out of
+ * range.  Clears the word.  The only call here that blocks the host. */
+int spgemm_ws_status(void *ws, void *stream);
+
+/* Testing hook, process-wide, not thread-safe: from now on every column is
+ * placed in bin `bin` or a later one (bins are ordered by table capacity,
+ * 0 = smallest, 5 = heavy), so each kernel can be exercised on small
+ * inputs.  0 restores the natural choice.  Affects results only through
+ * output order.  SPGEMM_E_INVAL if bin is outside [0, 5]. */
+int spgemm_debug_min_bin(int32_t bin);
+
+/* Text of a status code (static storage). */
+const char *spgemm_status_string(int status);
+
+/* hipError_t code of the last failed HIP call in this thread (0 if none). */
+int spgemm_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPGEMM_H_ */

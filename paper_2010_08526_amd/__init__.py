@@ -1,0 +1,336 @@
+"""Python binding of libspgemm (the C ABI in include/spgemm.h).
+
+Argument marshalling only: every step of the product runs in the library's
+HIP kernels or its host-side planner.  torch supplies device memory and
+streams.  torch is imported before the library is loaded so that both use
+one HIP runtime.  There is no fallback: if the library is missing the
+import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_lib", "libspgemm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_2010_08526_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---------------------------------------------------------------- constants
+OK, E_INVAL, E_SHAPE, E_DTYPE, E_BUDGET, E_WORKSPACE, E_HIP, E_OVERFLOW, E_DEVICE = 0, -1, -2, -3, -4, -5, -6, -7, -8
+F32, F64 = 0, 1
+OP_SYMBOLIC, OP_NUMERIC, OP_MERGE, OP_COLPTR, OP_MASKED_XTY, OP_TRANSPOSE = range(6)
+MAX_PARTS = 4096
+
+_DTYPE = {torch.float32: F32, torch.float64: F64}
+
+
+class spgemm_csc(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("colptr", ctypes.c_void_p), ("rowidx", ctypes.c_void_p), ("values", ctypes.c_void_p),
+                ("dtype", ctypes.c_int32)]
+
+
+_P = ctypes.POINTER(spgemm_csc)
+_vp, _i64, _i32, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+
+_lib.spgemm_workspace_size.argtypes = [ctypes.c_int, _P, _P, _i64, _i64, _i32, ctypes.POINTER(_sz)]
+_lib.spgemm_symbolic.argtypes = [_P, _P, _i64, _i64, _i32, _vp, _vp, _vp, _sz, _vp]
+_lib.spgemm_plan_batches.argtypes = [_vp, _i64, _i32, _i32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, _i32,
+                                     _vp, ctypes.POINTER(_i32), _vp]
+_lib.spgemm_colptr.argtypes = [_vp, _i64, _vp, _vp, _sz, _vp]
+_lib.spgemm_numeric.argtypes = [_P, _P, _i64, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.spgemm_merge.argtypes = [_P, _i32, _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.spgemm_ws_status.argtypes = [_vp, _vp]
+_lib.spgemm_status_string.restype = ctypes.c_char_p
+_lib.spgemm_status_string.argtypes = [ctypes.c_int]
+_lib.spgemm_last_hip_error.restype = ctypes.c_int
+
+
+class SpgemmError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        self.status = status
+        msg = status_string(status)
+        if status == E_HIP:
+            msg += f" (hipError {int(_lib.spgemm_last_hip_error())})"
+        super().__init__(f"{where}: {msg}" if where else msg)
+
+
+def status_string(status: int) -> str:
+    return _lib.spgemm_status_string(int(status)).decode()
+
+
+def _check(rc: int, where: str):
+    if rc != OK:
+        raise SpgemmError(rc, where)
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else int(t.data_ptr())
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return int(torch.cuda.current_stream().cuda_stream) if torch.cuda.is_available() else None
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+@dataclass
+class CSC:
+    """A CSC matrix in torch tensors: colptr int64[ncols+1], rowidx int32[nnz],
+    values float32/float64[nnz] (or None)."""
+
+    nrows: int
+    ncols: int
+    colptr: torch.Tensor
+    rowidx: torch.Tensor
+    values: torch.Tensor | None
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowidx.numel())
+
+
+def desc(M, dtype: int | None = None) -> spgemm_csc:
+    """C descriptor of any object with nrows/ncols/colptr/rowidx/values."""
+    v = M.values
+    if dtype is None:
+        dtype = _DTYPE.get(v.dtype, -1) if v is not None else F32
+    return spgemm_csc(int(M.nrows), int(M.ncols), int(M.rowidx.numel()), _ptr(M.colptr), _ptr(M.rowidx), _ptr(v),
+                      int(dtype))
+
+
+# ------------------------------------------------------------ thin wrappers
+def workspace_size(op: int, A=None, B=None, c0: int = 0, c1: int = 0, n_layers: int = 1) -> int:
+    out = _sz(0)
+    a = ctypes.byref(desc(A)) if A is not None else None
+    b = ctypes.byref(desc(B)) if B is not None else None
+    _check(_lib.spgemm_workspace_size(op, a, b, c0, c1, n_layers, ctypes.byref(out)), "spgemm_workspace_size")
+    return int(out.value)
+
+
+def alloc_workspace(nbytes: int, device=None) -> torch.Tensor:
+    """A 256-byte aligned device buffer (torch's allocator aligns to 512)."""
+    t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device or "cuda")
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
+def symbolic(A, B, c0: int, c1: int, n_layers: int, flops_out, nnz_out, ws: torch.Tensor, stream=None):
+    _check(_lib.spgemm_symbolic(ctypes.byref(desc(A)), ctypes.byref(desc(B)), c0, c1, n_layers, _ptr(flops_out),
+                                _ptr(nnz_out), _ptr(ws), ws.numel(), _stream(stream)), "spgemm_symbolic")
+
+
+def plan_batches(nnz_host, ncols: int, n_layers: int, value_bytes: int, input_bytes: int, budget_bytes: int,
+                 reserve_bytes: int = 0, max_batches: int = 1 << 16):
+    """Returns (bounds: list[int], batch_nnz: np.ndarray[b, rows])."""
+    nnz_host = np.ascontiguousarray(np.asarray(nnz_host, dtype=np.int64))
+    rows = n_layers + 1 if n_layers > 1 else 1
+    bounds = np.zeros(max_batches + 1, np.int64)
+    tot = np.zeros(max_batches * rows, np.int64)
+    nb = _i32(0)
+    _check(_lib.spgemm_plan_batches(nnz_host.ctypes.data, ncols, n_layers, value_bytes, int(input_bytes),
+                                    int(budget_bytes), int(reserve_bytes), max_batches, bounds.ctypes.data,
+                                    ctypes.byref(nb), tot.ctypes.data), "spgemm_plan_batches")
+    b = int(nb.value)
+    return bounds[:b + 1].tolist(), tot[:b * rows].reshape(b, rows)
+
+
+def colptr(counts: torch.Tensor, out: torch.Tensor, ws: torch.Tensor, stream=None):
+    n = counts.numel()
+    _check(_lib.spgemm_colptr(_ptr(counts), n, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)), "spgemm_colptr")
+
+
+def numeric(A, B, c0: int, c1: int, layer: int, n_layers: int, flops, c_colptr, c_rowidx, c_values,
+            ws: torch.Tensor, stream=None):
+    _check(_lib.spgemm_numeric(ctypes.byref(desc(A)), ctypes.byref(desc(B)), c0, c1, layer, n_layers, _ptr(flops),
+                               _ptr(c_colptr), _ptr(c_rowidx), _ptr(c_values), _ptr(ws), ws.numel(), _stream(stream)),
+           "spgemm_numeric")
+
+
+def merge(parts, c_colptr, c_rowidx, c_values, ws: torch.Tensor, stream=None):
+    arr = (spgemm_csc * len(parts))(*[desc(p) for p in parts])
+    _check(_lib.spgemm_merge(arr, len(parts), _ptr(c_colptr), _ptr(c_rowidx), _ptr(c_values), _ptr(ws), ws.numel(),
+                             _stream(stream)), "spgemm_merge")
+
+
+def ws_status(ws: torch.Tensor, stream=None) -> int:
+    """Synchronizes and returns the device-side status of a workspace."""
+    return int(_lib.spgemm_ws_status(_ptr(ws), _stream(stream)))
+
+
+def check_ws(ws: torch.Tensor, where: str = "device check", stream=None):
+    _check(ws_status(ws, stream), where)
+
+
+# ------------------------------------------------------------ batch driver
+def layer_bounds(kdim: int, n_layers: int) -> list[tuple[int, int]]:
+    """The inner-dimension ranges the library uses for n_layers layers."""
+    w = -(-kdim // n_layers) if n_layers > 0 else kdim
+    return [(min(kdim, l * w), min(kdim, l * w + w)) for l in range(n_layers)]
+
+
+@dataclass
+class Plan:
+    """Result of the symbolic pass and the planner for one product."""
+
+    flops: torch.Tensor  # int64 [n] per output column (device)
+    nnz: torch.Tensor  # int64 [rows, n] (device)
+    nnz_host: np.ndarray  # int64 [rows, n]
+    bounds: list
+    batch_nnz: np.ndarray  # [b, rows]
+    n_layers: int
+    budget_bytes: int
+    input_bytes: int
+    reserve_bytes: int
+
+    @property
+    def nbatches(self) -> int:
+        return len(self.bounds) - 1
+
+    @property
+    def total_flops(self) -> int:
+        return int(self.flops.sum())
+
+
+class Engine:
+    """Holds workspaces and output buffers for repeated products of one shape.
+
+    run(A, B) performs: symbolic pass -> counts to host -> batch planner ->
+    per batch (numeric per layer [-> merge]) -> consume(c0, c1, C_batch).
+    """
+
+    def __init__(self, A, B, n_layers: int = 1, budget_bytes: int | None = None, max_batches: int = 1 << 16,
+                 device="cuda"):
+        if A.ncols != B.nrows:
+            raise SpgemmError(E_SHAPE, "Engine")
+        self.A, self.B, self.L = A, B, int(n_layers)
+        self.device = device
+        self.max_batches = max_batches
+        self.vbytes = 4 if A.values is None or A.values.dtype == torch.float32 else 8
+        self.vdtype = torch.float32 if self.vbytes == 4 else torch.float64
+        n = B.ncols
+        self.ws_sym = alloc_workspace(workspace_size(OP_SYMBOLIC, A, B, 0, n, self.L), device)
+        self.ws_num = alloc_workspace(workspace_size(OP_NUMERIC, A, B, 0, n, self.L), device)
+        mparts = CSC(A.nrows, n, A.colptr, A.rowidx, A.values)
+        self.ws_mrg = alloc_workspace(workspace_size(OP_MERGE, mparts, None, 0, 0, max(1, self.L)), device) \
+            if self.L > 1 else None
+        self.ws_scan = alloc_workspace(workspace_size(OP_COLPTR, None, None, 0, n + 1), device)
+        rows = self.L + 1 if self.L > 1 else 1
+        self.flops = torch.empty(n, dtype=torch.int64, device=device)
+        self.nnz = torch.empty((rows, n), dtype=torch.int64, device=device)
+        r = 4 + self.vbytes
+        self.input_bytes = r * (A.nnz + B.nnz) + 8 * (A.ncols + B.ncols + 2)
+        self.reserve_bytes = sum(int(w.numel()) for w in (self.ws_sym, self.ws_num, self.ws_mrg, self.ws_scan)
+                                 if w is not None) + 8 * 4 * (n + 1) * rows
+        if budget_bytes is None:
+            free, _ = torch.cuda.mem_get_info()
+            budget_bytes = int(free * 0.9) + self.input_bytes + self.reserve_bytes
+        self.budget_bytes = int(budget_bytes)
+        self._bufs = None
+
+    # -- passes --------------------------------------------------------------
+    def plan(self, stream=None) -> Plan:
+        A, B, n = self.A, self.B, self.B.ncols
+        symbolic(A, B, 0, n, self.L, self.flops, self.nnz, self.ws_sym, stream)
+        nnz_host = self.nnz.cpu().numpy()
+        bounds, tot = plan_batches(nnz_host.reshape(-1), n, self.L, self.vbytes, self.input_bytes, self.budget_bytes,
+                                   self.reserve_bytes, self.max_batches)
+        return Plan(self.flops, self.nnz, nnz_host, bounds, tot, self.L, self.budget_bytes, self.input_bytes,
+                    self.reserve_bytes)
+
+    def _buffers(self, plan: Plan):
+        widths = [b - a for a, b in zip(plan.bounds[:-1], plan.bounds[1:])]
+        wmax = max(widths) if widths else 0
+        L = self.L
+        if L == 1:
+            need = (wmax, int(plan.batch_nnz[:, 0].max()) if plan.nbatches else 0, 0)
+        else:
+            need = (wmax, int(plan.batch_nnz[:, L].max()), int(plan.batch_nnz[:, :L].sum(1).max()))
+        if self._bufs is None or any(x > y for x, y in zip(need, self._bufs["need"])):
+            dev = self.device
+            bufs = {"need": need,
+                    "ccp": torch.empty(need[0] + 1, dtype=torch.int64, device=dev),
+                    "cri": torch.empty(max(1, need[1]), dtype=torch.int32, device=dev),
+                    "cv": torch.empty(max(1, need[1]), dtype=self.vdtype, device=dev)}
+            if L > 1:
+                bufs["dcp"] = torch.empty((L, need[0] + 1), dtype=torch.int64, device=dev)
+                bufs["dri"] = torch.empty(max(1, need[2]), dtype=torch.int32, device=dev)
+                bufs["dv"] = torch.empty(max(1, need[2]), dtype=self.vdtype, device=dev)
+            self._bufs = bufs
+        return self._bufs
+
+    def run_batch(self, plan: Plan, i: int, stream=None) -> CSC:
+        """Forms batch i; the returned CSC views buffers reused by the next call."""
+        A, B, L = self.A, self.B, self.L
+        c0, c1 = plan.bounds[i], plan.bounds[i + 1]
+        w = c1 - c0
+        bufs = self._buffers(plan)
+        ccp, cri, cv = bufs["ccp"][:w + 1], bufs["cri"], bufs["cv"]
+        if L == 1:
+            colptr(self.nnz[0, c0:c1], ccp, self.ws_scan, stream)
+            numeric(A, B, c0, c1, 0, 1, self.flops[c0:c1], ccp, cri, cv, self.ws_num, stream)
+            nnzc = int(plan.batch_nnz[i, 0])
+        else:
+            parts = []
+            off = 0
+            for l in range(L):
+                dcp = bufs["dcp"][l, :w + 1]
+                colptr(self.nnz[l, c0:c1], dcp, self.ws_scan, stream)
+                cnt = int(plan.batch_nnz[i, l])
+                dri = bufs["dri"][off:off + cnt]
+                dv = bufs["dv"][off:off + cnt]
+                numeric(A, B, c0, c1, l, L, self.flops[c0:c1], dcp, dri, dv, self.ws_num, stream)
+                parts.append(CSC(A.nrows, w, dcp, dri, dv))
+                off += cnt
+            colptr(self.nnz[L, c0:c1], ccp, self.ws_scan, stream)
+            merge(parts, ccp, cri, cv, self.ws_mrg, stream)
+            nnzc = int(plan.batch_nnz[i, L])
+        return CSC(A.nrows, w, ccp, cri[:nnzc], cv[:nnzc])
+
+    def check(self, stream=None):
+        for w in (self.ws_sym, self.ws_num, self.ws_mrg):
+            if w is not None:
+                check_ws(w, "device-side check", stream)
+
+    def run(self, consume=None, stream=None):
+        """All batches; consume(c0, c1, C_batch) per batch, or the whole C."""
+        plan = self.plan(stream)
+        out = [] if consume is None else None
+        for i in range(plan.nbatches):
+            Cb = self.run_batch(plan, i, stream)
+            if consume is None:
+                out.append(CSC(Cb.nrows, Cb.ncols, Cb.colptr.clone(), Cb.rowidx.clone(), Cb.values.clone()))
+            else:
+                consume(plan.bounds[i], plan.bounds[i + 1], Cb)
+        self.check(stream)
+        if consume is not None:
+            return plan
+        return _concat(out, self.A.nrows), plan
+
+
+def _concat(batches, nrows):
+    ncols = sum(b.ncols for b in batches)
+    cps = []
+    off = 0
+    for b in batches:
+        cps.append(b.colptr[:-1] + off)
+        off += b.nnz
+    dev = batches[0].rowidx.device if batches else "cuda"
+    cps.append(torch.tensor([off], dtype=torch.int64, device=dev))
+    return CSC(nrows, ncols, torch.cat(cps), torch.cat([b.rowidx for b in batches]),
+               torch.cat([b.values for b in batches]))
+
+
+def spgemm(A, B, *, layers: int = 1, budget_bytes: int | None = None, consume=None, stream=None):
+    """C = A B (plus-times).  With ``consume`` the batches are handed to it and
+    discarded; otherwise C is returned (all batches concatenated)."""
+    eng = Engine(A, B, layers, budget_bytes)
+    res = eng.run(consume, stream)
+    return res if consume is not None else res[0]

@@ -1,0 +1,80 @@
+// Internal declarations shared by the host-only translation unit (host.cpp)
+// and the HIP translation unit (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/spgemm.h"
+
+namespace spg {
+
+// ----------------------------------------------------------------------------
+// Hash-table bins.  A column is placed in the first bin whose capacity
+// covers its bound on distinct output rows: min(flops, nrows) in the
+// symbolic pass, the exact count from the symbolic pass in the numeric pass
+// and the merge.  Tables are sized to at least twice the capacity (load
+// factor <= 0.5, linear probing).
+//   wave bins : one 64-lane wavefront per column, table private to it (LDS)
+//   block bins: one workgroup per column, table shared by its waves (LDS)
+//   last bin  : "heavy" -- symbolic uses an LDS bitmap over row windows,
+//               numeric and merge use dense float64 accumulators in global
+//               memory (the workspace), several workgroups per column.
+// ----------------------------------------------------------------------------
+constexpr int kNumBins = 6;
+// symbolic (keys only, 4 bytes per slot)
+constexpr int64_t kSymCap[kNumBins - 1] = {32, 128, 512, 2048, 16384};
+// numeric / merge (int32 key + float64 value, 12 bytes per slot)
+constexpr int64_t kNumCap[kNumBins - 1] = {32, 128, 512, 2048, 5120};
+
+constexpr int kMaxParts = 4096;  // merge: parts per call
+constexpr size_t kPartDescBytes = 24;  // device-side copy of one part's pointers
+constexpr int64_t kBitmapRows = 1 << 20;  // heavy symbolic: rows per LDS bitmap window (128 KiB)
+constexpr int64_t kHeavySeg = 16384;  // heavy numeric: rows per compaction segment
+constexpr int kMaxAdeg = 1 << 25;  // per-column degree of the left operand handled per chunk
+
+// Workspace header: one 4 KiB block at offset 0.
+struct WsHeader {
+  int32_t status;  // 0 = ok; nonzero = a device-side check failed
+  int32_t pad0;
+  uint64_t clean_tag;  // nonzero iff the heavy accumulator region is known to be all zero
+  int32_t bin_count[kNumBins];
+  int32_t pad1[2];
+};
+constexpr size_t kHeaderBytes = 4096;
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Number of heavy accumulator slots (columns accumulated at once) for m rows:
+// about 1 GiB of float64 values plus one flag byte per row and slot.
+inline int64_t heavy_slots(int64_t m) {
+  if (m <= 0) return 1;
+  int64_t s = (int64_t(1) << 30) / (9 * m);
+  if (s < 8) s = 8;
+  if (s > 256) s = 256;
+  return s;
+}
+
+struct WsLayout {
+  size_t bins = 0;        // int32 [kNumBins][ncol]
+  size_t heavy_vals = 0;  // double [slots][m]
+  size_t heavy_flags = 0; // uint8 [slots][m]
+  size_t heavy_segcnt = 0;// int64 [slots][nseg]
+  size_t scan = 0;        // int64 block sums
+  size_t parts = 0;       // merge: part descriptors
+  size_t total = 0;
+  int64_t slots = 0, nseg = 0, ncol = 0, m = 0;
+};
+
+// Computes the layout; returns SPGEMM_OK or an error status.
+int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t c1, int32_t n_layers,
+              WsLayout *out);
+
+// Host-side argument checks shared by the entry points.
+int check_csc(const spgemm_csc *M, bool need_values);
+int check_ws(const void *ws, size_t ws_bytes, size_t need);
+int dtype_bytes(int32_t dtype);
+
+void set_hip_error(int code);
+
+}  // namespace spg

@@ -1,0 +1,1069 @@
+// HIP kernels and GPU-facing entry points of the SpGEMM library (gfx950).
+//
+// C = A*B over (+, *) in CSC, one output column at a time (Gustavson's
+// column formula, Sec. II-C).  Three passes, each sort-free (Sec. IV-D):
+//   symbolic: per-column flops and exact distinct-row counts (Alg. 3,
+//             LocalSymbolic) from hash tables of row keys;
+//   numeric : hash-table accumulation of A(i,k)*B(k,j) and compaction of
+//             the table into the output column in table order;
+//   merge   : hash-table addition of the same column of several partial
+//             products (Merge-Layer / Merge-Fiber, Alg. 1 and Alg. 2).
+// Columns are binned by their bound on distinct rows; see internal.hpp.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace spg {
+
+// ============================================================================
+// Per-wave scratch for the load-balanced traversal.
+// ============================================================================
+struct SegScratch {
+  int mark[kWave];
+  int64_t off[kWave];   // element base of the lane's segment minus its exclusive prefix
+  double scale[kWave];  // B(k,j) of the lane's segment
+};
+
+struct PartDesc {  // one merge input, stored in the workspace
+  const int64_t *cp;
+  const int32_t *ri;
+  const void *v;
+};
+
+struct MergeScratch {
+  int mark[kWave];
+  const int32_t *ri[kWave];
+  const void *v[kWave];
+};
+
+template <class VT>
+struct ProductArgs {
+  const int64_t *Acp;
+  const int32_t *Ari;
+  const VT *Av;
+  const int64_t *Bcp;
+  const int32_t *Bri;
+  const VT *Bv;
+  int64_t klo, khi, kdim, m, nnzA;
+};
+
+// Traversal of the rounds of one chunk of segments.  Rounds r with
+// (r + r_base) % r_stride == r_rank are processed, so that a group of
+// r_stride waves can share one column; r_stride = 1 processes every round.
+// The owner of round fb's first element comes from a ballot (the highest
+// lane whose segment starts at or before fb), so rounds are independent.
+template <class Body>
+__device__ __forceinline__ void flatten_rounds(int len, int excl, int total, int *mark, int64_t r_base,
+                                               int64_t r_rank, int64_t r_stride, Body &&body) {
+  const int l = lane();
+  int64_t r0 = (r_rank - r_base) % r_stride;
+  if (r0 < 0) r0 += r_stride;
+  for (int64_t r = r0; r * kWave < total; r += r_stride) {
+    const int fb = (int)(r * kWave);
+    const uint64_t started = __ballot(len > 0 && excl <= fb);
+    const int carry = started ? 64 - __clzll((long long)started) : 0;
+    if (len > 0 && excl > fb && excl < fb + kWave) mark[excl - fb] = l + 1;
+    wave_sync();
+    const int mk = mark[l];
+    mark[l] = 0;
+    const int own = max(wave_incl_max(mk), carry);
+    const int e = fb + l;
+    if (e < total) body(own - 1, e);
+    wave_sync();
+  }
+}
+
+// Visits every product term A(i,k)*B(k,j) of output column `col` with
+// k in [klo, khi): ins(i, A(i,k)*B(k,j)) (values in float64).  Chunks of 64
+// entries of B(:,col) are split among waves: chunk c is read by waves with
+// (c % c_stride) == c_rank when c_stride > 1 and r_stride == 1; with
+// r_stride > 1 every wave reads every chunk and the rounds are split.
+template <bool VALUES, class VT, class Ins>
+__device__ __forceinline__ void traverse_product(const ProductArgs<VT> &a, int64_t col, int64_t c_rank,
+                                                 int64_t c_stride, int64_t r_rank, int64_t r_stride,
+                                                 SegScratch &sc, int32_t *status, Ins &&ins) {
+  const int l = lane();
+  const int64_t pbeg = a.Bcp[col], pend = a.Bcp[col + 1];
+  int64_t rounds_before = 0;
+  for (int64_t base = pbeg + c_rank * kWave; base < pend; base += c_stride * kWave) {
+    const int64_t p = base + l;
+    int len = 0;
+    int64_t off = 0;
+    double b = 0.0;
+    if (p < pend) {
+      const int32_t k = a.Bri[p];
+      if ((uint64_t)(uint32_t)k >= (uint64_t)a.kdim || k < 0) {
+        flag_error(status, 1);
+      } else if (k >= a.klo && k < a.khi) {
+        const int64_t a0 = a.Acp[k];
+        const int64_t d = a.Acp[k + 1] - a0;
+        if (d < 0 || d >= kMaxAdeg) {
+          flag_error(status, 2);
+        } else {
+          len = (int)d;
+          off = a0;
+          if (VALUES) b = (double)a.Bv[p];
+        }
+      }
+    }
+    const int incl = wave_incl_add(len);
+    const int excl = incl - len;
+    const int total = readlane(incl, 63);
+    if (total == 0) continue;
+    sc.off[l] = off - excl;
+    if (VALUES) sc.scale[l] = b;
+    wave_sync();
+    flatten_rounds(len, excl, total, sc.mark, rounds_before, r_rank, r_stride, [&](int o, int e) {
+      const int64_t q = sc.off[o] + e;
+      if ((uint64_t)q >= (uint64_t)a.nnzA) {
+        flag_error(status, 5);
+        return;
+      }
+      const int32_t row = a.Ari[q];
+      if ((uint32_t)row >= (uint32_t)a.m) {
+        flag_error(status, 3);
+        return;
+      }
+      if (VALUES) {
+        ins(row, (double)a.Av[q] * sc.scale[o]);
+      } else {
+        ins(row, 0.0);
+      }
+    });
+    rounds_before += (total + kWave - 1) / kWave;
+    wave_sync();
+  }
+}
+
+// Visits every stored entry of column `col` of the parts: ins(i, value).
+// Parts are taken 64 at a time (one per lane); rounds are numbered across
+// chunks and split among r_stride waves.
+template <class VT, class Ins>
+__device__ __forceinline__ void traverse_merge(const PartDesc *P, int nparts, int64_t m, int64_t col,
+                                               int64_t r_rank, int64_t r_stride, MergeScratch &sc,
+                                               int32_t *status, Ins &&ins) {
+  const int l = lane();
+  int64_t rounds_before = 0;
+  for (int c0 = 0; c0 < nparts; c0 += kWave) {
+    const int p = c0 + l;
+    int len = 0;
+    const int32_t *ri = nullptr;
+    const VT *v = nullptr;
+    if (p < nparts) {
+      const int64_t a0 = P[p].cp[col];
+      const int64_t d = P[p].cp[col + 1] - a0;
+      if (d < 0 || d >= kMaxAdeg) {
+        flag_error(status, 2);
+      } else {
+        len = (int)d;
+        ri = P[p].ri + a0;
+        v = (const VT *)P[p].v + a0;
+      }
+    }
+    const int incl = wave_incl_add(len);
+    const int excl = incl - len;
+    const int total = readlane(incl, 63);
+    if (total == 0) continue;
+    sc.ri[l] = ri - excl;
+    sc.v[l] = (const void *)(v - excl);
+    wave_sync();
+    flatten_rounds(len, excl, total, sc.mark, rounds_before, r_rank, r_stride, [&](int o, int e) {
+      const int32_t row = sc.ri[o][e];
+      if ((uint32_t)row >= (uint32_t)m) {
+        flag_error(status, 3);
+        return;
+      }
+      ins(row, (double)((const VT *)sc.v[o])[e]);
+    });
+    rounds_before += (total + kWave - 1) / kWave;
+    wave_sync();
+  }
+}
+
+// ============================================================================
+// LDS hash tables (open addressing, linear probing, key kEmpty = free).
+// ============================================================================
+__device__ __forceinline__ int32_t lds_load(int32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+
+// Inserts `key`; returns true if this call created it.
+__device__ __forceinline__ bool ht_insert_key(int32_t *keys, uint32_t T, int32_t key) {
+  uint32_t h = hash_slot(key, T);
+  for (uint32_t probe = 0; probe < T; probe++) {
+    const int32_t k = lds_load(&keys[h]);
+    if (k == key) return false;
+    if (k == kEmpty) {
+      const int32_t old = atomicCAS(&keys[h], kEmpty, key);
+      if (old == kEmpty) return true;
+      if (old == key) return false;
+    }
+    h = (h + 1 == T) ? 0 : h + 1;
+  }
+  return false;  // unreachable with tables at most half full
+}
+
+// Adds `v` to the slot of `key`, creating it if needed.
+__device__ __forceinline__ void ht_accumulate(int32_t *keys, double *vals, uint32_t T, int32_t key, double v) {
+  uint32_t h = hash_slot(key, T);
+  for (uint32_t probe = 0; probe < T; probe++) {
+    const int32_t k = lds_load(&keys[h]);
+    if (k == key) {
+      atomicAdd(&vals[h], v);
+      return;
+    }
+    if (k == kEmpty) {
+      const int32_t old = atomicCAS(&keys[h], kEmpty, key);
+      if (old == kEmpty || old == key) {
+        atomicAdd(&vals[h], v);
+        return;
+      }
+    }
+    h = (h + 1 == T) ? 0 : h + 1;
+  }
+}
+
+// ============================================================================
+// Small kernels: header init, fills.
+// ============================================================================
+__global__ void k_init_header(WsHeader *h, int keep_clean) {
+  if (threadIdx.x == 0) {
+    h->status = 0;
+    for (int b = 0; b < kNumBins; b++) h->bin_count[b] = 0;
+    if (!keep_clean) h->clean_tag = 0;
+  }
+}
+
+__global__ void k_set_tag(WsHeader *h, uint64_t tag) {
+  if (threadIdx.x == 0) h->clean_tag = tag;
+}
+
+__global__ void k_fill_zero(uint4 *p, int64_t n16) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ void k_zero_i64(int64_t *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+struct PartsChunk {
+  PartDesc d[kWave];
+};
+__global__ void k_store_parts(PartDesc *dst, PartsChunk src, int n) {
+  if ((int)threadIdx.x < n) dst[threadIdx.x] = src.d[threadIdx.x];
+}
+
+// ============================================================================
+// Binning: per output column, its bound on distinct rows and its bin.
+//   SYM: bound = min(flops, m); writes flops_out (optional); columns with no
+//        product term get nnz 0 here and no bin.
+//   NUM: bound = exact count from c_colptr; empty columns get no bin.
+// One wavefront per column, 16 columns per wave, one block-level append per
+// bin and block.
+// ============================================================================
+template <bool SYM>
+__device__ __forceinline__ int bin_of(int64_t bound) {
+#pragma unroll
+  for (int b = 0; b < kNumBins - 1; b++) {
+    if (bound <= (SYM ? kSymCap[b] : kNumCap[b])) return b;
+  }
+  return kNumBins - 1;
+}
+
+constexpr int kBinColsPerWave = 16;
+
+template <bool SYM>
+__global__ __launch_bounds__(256) void k_bin(const int64_t *Acp, const int64_t *Bcp, const int32_t *Bri,
+                                             int64_t c0, int64_t ncol, int64_t klo, int64_t khi, int64_t kdim,
+                                             int64_t m, const int64_t *c_colptr, int64_t *flops_out,
+                                             int64_t *nnz_out, int32_t *bins, WsHeader *hdr, int min_bin) {
+  __shared__ int s_cnt[kNumBins];
+  __shared__ int s_base[kNumBins];
+  __shared__ int s_bin[4 * kBinColsPerWave];
+  __shared__ int s_pos[4 * kBinColsPerWave];
+  const int w = threadIdx.x / kWave, l = lane();
+  if (threadIdx.x < kNumBins) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int t = 0; t < kBinColsPerWave; t++) {
+    const int slot = w * kBinColsPerWave + t;
+    const int64_t jj = ((int64_t)blockIdx.x * 4 + w) * kBinColsPerWave + t;
+    int bin = -1;
+    if (jj < ncol) {
+      int64_t bound;
+      if (SYM) {
+        const int64_t col = c0 + jj;
+        int64_t f = 0;
+        for (int64_t p = Bcp[col] + l; p < Bcp[col + 1]; p += kWave) {
+          const int32_t k = Bri[p];
+          if (k < 0 || (int64_t)k >= kdim) {
+            flag_error(&hdr->status, 1);
+          } else if (k >= klo && k < khi) {
+            f += Acp[k + 1] - Acp[k];
+          }
+        }
+        f = wave_sum_i64(f);
+        if (l == 0 && flops_out) flops_out[jj] = f;
+        bound = f < m ? f : m;
+        if (bound == 0 && l == 0) nnz_out[jj] = 0;
+      } else {
+        bound = c_colptr[jj + 1] - c_colptr[jj];
+      }
+      if (bound > 0) bin = max(bin_of<SYM>(bound), min_bin);
+    }
+    if (l == 0) {
+      s_bin[slot] = bin;
+      s_pos[slot] = bin >= 0 ? atomicAdd(&s_cnt[bin], 1) : 0;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kNumBins) {
+    const int c = s_cnt[threadIdx.x];
+    s_base[threadIdx.x] = c ? atomicAdd(&hdr->bin_count[threadIdx.x], c) : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4 * kBinColsPerWave) {
+    const int slot = threadIdx.x;
+    const int bin = s_bin[slot];
+    if (bin >= 0) {
+      const int64_t jj = ((int64_t)blockIdx.x * 4 + slot / kBinColsPerWave) * kBinColsPerWave + slot % kBinColsPerWave;
+      bins[(int64_t)bin * ncol + s_base[bin] + s_pos[slot]] = (int32_t)jj;
+    }
+  }
+}
+
+// ============================================================================
+// Symbolic kernels.
+// ============================================================================
+// One wavefront per column, TBL-slot table private to the wave.
+template <int TBL>
+__global__ __launch_bounds__(256) void k_sym_wave(ProductArgs<float> a, int64_t c0, const int32_t *list, int count,
+                                                  int64_t *nnz_out, int32_t *status) {
+  __shared__ int32_t s_keys[4][TBL];
+  __shared__ SegScratch s_sc[4];
+  const int w = threadIdx.x / kWave, l = lane();
+  const int idx = blockIdx.x * 4 + w;
+  if (idx >= count) return;
+  int32_t *keys = s_keys[w];
+  SegScratch &sc = s_sc[w];
+  for (int s = l; s < TBL; s += kWave) keys[s] = kEmpty;
+  sc.mark[l] = 0;
+  wave_sync();
+  const int32_t jj = list[idx];
+  int cnt = 0;
+  traverse_product<false, float>(a, c0 + jj, 0, 1, 0, 1, sc, status, [&](int32_t row, double) {
+    cnt += ht_insert_key(keys, TBL, row) ? 1 : 0;
+  });
+  cnt = wave_sum_i32(cnt);
+  if (l == 0) nnz_out[jj] = cnt;
+}
+
+// One workgroup per column, TBL-slot table shared by its waves.
+template <int TBL, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_sym_block(ProductArgs<float> a, int64_t c0, const int32_t *list,
+                                                       int64_t *nnz_out, int32_t *status) {
+  constexpr int NW = THREADS / kWave;
+  __shared__ int32_t s_keys[TBL];
+  __shared__ SegScratch s_sc[NW];
+  __shared__ int s_cnt;
+  const int w = threadIdx.x / kWave, l = lane();
+  for (int s = threadIdx.x; s < TBL; s += THREADS) s_keys[s] = kEmpty;
+  s_sc[w].mark[l] = 0;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  const int32_t jj = list[blockIdx.x];
+  int cnt = 0;
+  traverse_product<false, float>(a, c0 + jj, w, NW, 0, 1, s_sc[w], status, [&](int32_t row, double) {
+    cnt += ht_insert_key(s_keys, TBL, row) ? 1 : 0;
+  });
+  cnt = wave_sum_i32(cnt);
+  if (l == 0) atomicAdd(&s_cnt, cnt);
+  __syncthreads();
+  if (threadIdx.x == 0) nnz_out[jj] = s_cnt;
+}
+
+// Heavy columns: exact count with an LDS bitmap over windows of kBitmapRows
+// rows (one pass over the column's terms per window).
+constexpr int kBmWords = (int)(kBitmapRows / 32);
+__global__ __launch_bounds__(1024) void k_sym_bitmap(ProductArgs<float> a, int64_t c0, const int32_t *list,
+                                                     int64_t *nnz_out, int32_t *status) {
+  constexpr int NW = 1024 / kWave;
+  __shared__ uint32_t s_bm[kBmWords];
+  __shared__ SegScratch s_sc[NW];
+  __shared__ unsigned long long s_cnt;
+  const int w = threadIdx.x / kWave, l = lane();
+  s_sc[w].mark[l] = 0;
+  if (threadIdx.x == 0) s_cnt = 0;
+  const int32_t jj = list[blockIdx.x];
+  for (int64_t r0 = 0; r0 < a.m; r0 += kBitmapRows) {
+    for (int s = threadIdx.x; s < kBmWords; s += 1024) s_bm[s] = 0;
+    __syncthreads();
+    traverse_product<false, float>(a, c0 + jj, w, NW, 0, 1, s_sc[w], status, [&](int32_t row, double) {
+      const int64_t r = (int64_t)row - r0;
+      if (r >= 0 && r < kBitmapRows) atomicOr(&s_bm[r >> 5], 1u << (r & 31));
+    });
+    __syncthreads();
+    int c = 0;
+    for (int s = threadIdx.x; s < kBmWords; s += 1024) c += __popc(s_bm[s]);
+    c = wave_sum_i32(c);
+    if (l == 0) atomicAdd(&s_cnt, (unsigned long long)c);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) nnz_out[jj] = (int64_t)s_cnt;
+}
+
+// ============================================================================
+// Numeric and merge kernels (float64 accumulation, output in VT).
+// ============================================================================
+// Source selector: the product terms of A*B, or the entries of the parts.
+template <class VT>
+struct ProductSrc {
+  ProductArgs<VT> a;
+  int64_t c0;
+  template <class Ins>
+  __device__ __forceinline__ void visit(int64_t jj, int64_t c_rank, int64_t c_stride, int64_t r_rank,
+                                        int64_t r_stride, void *scratch, int32_t *status, Ins &&ins) const {
+    traverse_product<true, VT>(a, c0 + jj, c_rank, c_stride, r_rank, r_stride, *(SegScratch *)scratch, status, ins);
+  }
+  static constexpr size_t kScratch = sizeof(SegScratch);
+};
+
+template <class VT>
+struct MergeSrc {
+  const PartDesc *P;
+  int nparts;
+  int64_t m;
+  template <class Ins>
+  __device__ __forceinline__ void visit(int64_t jj, int64_t c_rank, int64_t c_stride, int64_t r_rank,
+                                        int64_t r_stride, void *scratch, int32_t *status, Ins &&ins) const {
+    // one chunk holds every part; the waves of a group split its rounds
+    traverse_merge<VT>(P, nparts, m, jj, c_rank + r_rank * c_stride, c_stride * r_stride, *(MergeScratch *)scratch,
+                       status, ins);
+  }
+  static constexpr size_t kScratch = sizeof(MergeScratch);
+};
+
+constexpr size_t kScratchBytes = sizeof(SegScratch) > sizeof(MergeScratch) ? sizeof(SegScratch) : sizeof(MergeScratch);
+
+template <class VT>
+__device__ __forceinline__ void init_mark(void *scratch) {
+  ((int *)scratch)[lane()] = 0;  // both scratch layouts start with mark[64]
+}
+
+// Writes the occupied slots [s_lo, s_hi) of a table to the output column in
+// slot order; `counter` reserves output positions (wave-wide).
+template <class VT>
+__device__ __forceinline__ void compact_range(const int32_t *keys, const double *vals, int s_lo, int s_hi,
+                                              int64_t base, int64_t cap, int *counter, int32_t *out_ri,
+                                              VT *out_v) {
+  const int l = lane();
+  for (int s0 = s_lo; s0 < s_hi; s0 += kWave) {
+    const int s = s0 + l;
+    const int32_t key = s < s_hi ? keys[s] : kEmpty;
+    const bool occ = key != kEmpty;
+    const uint64_t mask = __ballot(occ);
+    if (!mask) continue;
+    int pos0 = 0;
+    if (l == 0) pos0 = atomicAdd(counter, __popcll(mask));
+    pos0 = readlane(pos0, 0);
+    const int64_t pos = pos0 + mbcnt(mask);
+    if (occ && pos < cap) {
+      out_ri[base + pos] = key;
+      out_v[base + pos] = (VT)vals[s];
+    }
+  }
+}
+
+template <int TBL, class VT, class Src>
+__global__ __launch_bounds__(256) void k_num_wave(Src src, const int32_t *list, int count, const int64_t *c_colptr,
+                                                  int32_t *out_ri, VT *out_v, int32_t *status) {
+  __shared__ int32_t s_keys[4][TBL];
+  __shared__ double s_vals[4][TBL];
+  __shared__ __align__(16) char s_sc[4][kScratchBytes];
+  __shared__ int s_written[4];
+  const int w = threadIdx.x / kWave, l = lane();
+  const int idx = blockIdx.x * 4 + w;
+  if (idx >= count) return;
+  int32_t *keys = s_keys[w];
+  double *vals = s_vals[w];
+  for (int s = l; s < TBL; s += kWave) {
+    keys[s] = kEmpty;
+    vals[s] = 0.0;
+  }
+  init_mark<VT>(s_sc[w]);
+  if (l == 0) s_written[w] = 0;
+  wave_sync();
+  const int32_t jj = list[idx];
+  src.visit(jj, 0, 1, 0, 1, s_sc[w], status, [&](int32_t row, double v) { ht_accumulate(keys, vals, TBL, row, v); });
+  wave_sync();
+  const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
+  compact_range<VT>(keys, vals, 0, TBL, base, cap, &s_written[w], out_ri, out_v);
+  wave_sync();
+  if (l == 0 && s_written[w] != cap) flag_error(status, 4);
+}
+
+template <int TBL, int THREADS, class VT, class Src>
+__global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *list, const int64_t *c_colptr,
+                                                       int32_t *out_ri, VT *out_v, int32_t *status) {
+  constexpr int NW = THREADS / kWave;
+  __shared__ int32_t s_keys[TBL];
+  __shared__ double s_vals[TBL];
+  __shared__ __align__(16) char s_sc[NW][kScratchBytes];
+  __shared__ int s_written;
+  const int w = threadIdx.x / kWave;
+  for (int s = threadIdx.x; s < TBL; s += THREADS) {
+    s_keys[s] = kEmpty;
+    s_vals[s] = 0.0;
+  }
+  init_mark<VT>(s_sc[w]);
+  if (threadIdx.x == 0) s_written = 0;
+  __syncthreads();
+  const int32_t jj = list[blockIdx.x];
+  src.visit(jj, w, NW, 0, 1, s_sc[w], status, [&](int32_t row, double v) { ht_accumulate(s_keys, s_vals, TBL, row, v); });
+  __syncthreads();
+  const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
+  constexpr int PER = (TBL + NW - 1) / NW;
+  compact_range<VT>(s_keys, s_vals, w * PER, min(TBL, (w + 1) * PER), base, cap, &s_written, out_ri, out_v);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_written != cap) flag_error(status, 4);
+}
+
+// Heavy columns: dense float64 accumulators in the workspace, one per slot;
+// blocks (slot, part) share a column.  vals/flags are zero on entry and are
+// reset by k_heavy_write.
+template <class Src>
+__global__ __launch_bounds__(256) void k_heavy_acc(Src src, const int32_t *list, int first, int nslots, int parts,
+                                                   int64_t m, double *vals, uint8_t *flags, int32_t *status) {
+  constexpr int NW = 4;
+  __shared__ __align__(16) char s_sc[NW][kScratchBytes];
+  const int w = threadIdx.x / kWave;
+  const int slot = blockIdx.x / parts, part = blockIdx.x % parts;
+  if (slot >= nslots) return;
+  init_mark<float>(s_sc[w]);
+  wave_sync();
+  const int32_t jj = list[first + slot];
+  double *dv = vals + (int64_t)slot * m;
+  uint8_t *df = flags + (int64_t)slot * m;
+  // chunks of B(:,j) are shared by all waves of the group; rounds are split
+  src.visit(jj, 0, 1, (int64_t)part * NW + w, (int64_t)parts * NW, s_sc[w], status, [&](int32_t row, double v) {
+    atomicAdd(&dv[row], v);
+    df[row] = 1;
+  });
+}
+
+// Occupied rows per segment of kHeavySeg rows.
+__global__ __launch_bounds__(256) void k_heavy_count(int nslots, int64_t m, int64_t nseg, const uint8_t *flags,
+                                                     int64_t *segcnt) {
+  __shared__ int s_cnt;
+  const int64_t slot = blockIdx.x / nseg, seg = blockIdx.x % nseg;
+  if (slot >= nslots) return;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  const uint8_t *f = flags + slot * m;
+  const int64_t r0 = seg * kHeavySeg, r1 = min(m, r0 + kHeavySeg);
+  int c = 0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) c += f[r];
+  c = wave_sum_i32(c);
+  if (lane() == 0) atomicAdd(&s_cnt, c);
+  __syncthreads();
+  if (threadIdx.x == 0) segcnt[slot * nseg + seg] = s_cnt;
+}
+
+// Ordered compaction of one segment of a heavy column; resets its slots.
+template <class VT>
+__global__ __launch_bounds__(256) void k_heavy_write(const int32_t *list, int first, int nslots, int64_t m,
+                                                     int64_t nseg, double *vals, uint8_t *flags,
+                                                     const int64_t *segcnt, const int64_t *c_colptr,
+                                                     int32_t *out_ri, VT *out_v, int32_t *status) {
+  constexpr int PER = 16;  // rows per thread per tile
+  constexpr int TILE = 256 * PER;
+  __shared__ int64_t s_base;
+  __shared__ int s_wsum[4];
+  const int64_t slot = blockIdx.x / nseg, seg = blockIdx.x % nseg;
+  if (slot >= nslots) return;
+  const int w = threadIdx.x / kWave, l = lane();
+  const int32_t jj = list[first + slot];
+  const int64_t cbase = c_colptr[jj], cap = c_colptr[jj + 1] - cbase;
+  if (threadIdx.x == 0) {
+    int64_t pre = 0;
+    for (int64_t s = 0; s < seg; s++) pre += segcnt[slot * nseg + s];
+    s_base = pre;
+    if (seg == nseg - 1 && pre + segcnt[slot * nseg + seg] != cap) flag_error(status, 4);
+  }
+  __syncthreads();
+  int64_t pos = s_base;
+  double *dv = vals + slot * m;
+  uint8_t *df = flags + slot * m;
+  const int64_t r0 = seg * kHeavySeg, r1 = min(m, r0 + kHeavySeg);
+  for (int64_t t0 = r0; t0 < r1; t0 += TILE) {
+    const int64_t my0 = t0 + (int64_t)threadIdx.x * PER;
+    uint8_t f[PER];
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+      f[i] = (my0 + i < r1) ? df[my0 + i] : 0;
+      c += f[i];
+    }
+    // exclusive scan of c over the block
+    const int incl = wave_incl_add(c);
+    if (l == 63) s_wsum[w] = incl;
+    __syncthreads();
+    int wbase = 0, tot = 0;
+    for (int q = 0; q < 4; q++) {
+      if (q < w) wbase += s_wsum[q];
+      tot += s_wsum[q];
+    }
+    int64_t o = pos + wbase + incl - c;
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+      if (f[i]) {
+        const int64_t r = my0 + i;
+        if (o < cap) {
+          out_ri[cbase + o] = (int32_t)r;
+          out_v[cbase + o] = (VT)dv[r];
+        }
+        o++;
+        dv[r] = 0.0;
+        df[r] = 0;
+      }
+    }
+    pos += tot;
+    __syncthreads();
+  }
+}
+
+// ============================================================================
+// Exclusive scan of int64 counts into column pointers.
+// ============================================================================
+constexpr int kScanPer = 32, kScanThreads = 256, kScanBlock = kScanPer * kScanThreads;
+
+__device__ __forceinline__ int64_t wave_incl_add_i64(int64_t v) {
+  const int l = lane();
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int64_t t = __shfl_up(v, o, kWave);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+// Exclusive block scan (256 threads); returns this thread's exclusive prefix
+// and writes the block total to *total.
+__device__ __forceinline__ int64_t block_excl_i64(int64_t v, int64_t *s_w, int64_t *total) {
+  const int w = threadIdx.x / kWave, l = lane();
+  const int64_t incl = wave_incl_add_i64(v);
+  if (l == kWave - 1) s_w[w] = incl;
+  __syncthreads();
+  int64_t wb = 0, tot = 0;
+  for (int q = 0; q < kScanThreads / kWave; q++) {
+    if (q < w) wb += s_w[q];
+    tot += s_w[q];
+  }
+  __syncthreads();
+  *total = tot;
+  return wb + incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int64_t *x, int64_t n, int64_t *bsum) {
+  __shared__ int64_t s_w[kScanThreads / kWave];
+  const int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
+  int64_t s = 0;
+  for (int i = 0; i < kScanPer; i++) {
+    const int64_t idx = b0 + (int64_t)i * kScanThreads + threadIdx.x;
+    if (idx < n) s += x[idx];
+  }
+  int64_t tot;
+  block_excl_i64(s, s_w, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_bsums(int64_t *bsum, int64_t nb) {
+  __shared__ int64_t s_w[kScanThreads / kWave];
+  int64_t carry = 0;
+  for (int64_t c0 = 0; c0 < nb; c0 += kScanThreads) {
+    const int64_t i = c0 + threadIdx.x;
+    const int64_t v = i < nb ? bsum[i] : 0;
+    int64_t tot;
+    const int64_t ex = block_excl_i64(v, s_w, &tot);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += tot;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_final(const int64_t *x, int64_t n, const int64_t *bsum,
+                                                             int64_t *out) {
+  __shared__ int64_t s_w[kScanThreads / kWave];
+  const int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
+  const int64_t t0 = b0 + (int64_t)threadIdx.x * kScanPer;  // contiguous items per thread
+  int64_t v[kScanPer];
+  int64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPer; i++) {
+    v[i] = (t0 + i < n) ? x[t0 + i] : 0;
+    s += v[i];
+  }
+  int64_t tot;
+  int64_t run = bsum[blockIdx.x] + block_excl_i64(s, s_w, &tot);
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPer; i++) {
+    run += v[i];
+    if (t0 + i < n) out[t0 + i + 1] = run;
+  }
+}
+
+// ============================================================================
+// Host side.
+// ============================================================================
+static int hip_fail(hipError_t e) {
+  set_hip_error((int)e);
+  return SPGEMM_E_HIP;
+}
+#define HIPCHK(x)                                \
+  do {                                           \
+    hipError_t e_ = (x);                         \
+    if (e_ != hipSuccess) return hip_fail(e_);   \
+  } while (0)
+#define LAUNCHCHK()                                         \
+  do {                                                      \
+    hipError_t e_ = hipGetLastError();                      \
+    if (e_ != hipSuccess) return hip_fail(e_);              \
+  } while (0)
+
+// Testing hook: every column goes to at least this bin (0 = natural bins).
+static int g_min_bin = 0;
+
+struct HostPinned {
+  WsHeader *hdr = nullptr;
+};
+static thread_local HostPinned g_pin;
+
+static int read_header(WsHeader *dev, hipStream_t st, WsHeader *out) {
+  if (!g_pin.hdr) HIPCHK(hipHostMalloc((void **)&g_pin.hdr, sizeof(WsHeader), hipHostMallocDefault));
+  HIPCHK(hipMemcpyAsync(g_pin.hdr, dev, sizeof(WsHeader), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *out = *g_pin.hdr;
+  return SPGEMM_OK;
+}
+
+static int device_cus() {
+  static int cus = 0;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  });
+  return cus;
+}
+
+static inline unsigned grid_of(int64_t n, int64_t per) { return (unsigned)((n + per - 1) / per); }
+
+template <class VT>
+static ProductArgs<VT> product_args(const spgemm_csc *A, const spgemm_csc *B, int64_t klo, int64_t khi) {
+  ProductArgs<VT> a;
+  a.Acp = A->colptr;
+  a.Ari = A->rowidx;
+  a.Av = (const VT *)A->values;
+  a.Bcp = B->colptr;
+  a.Bri = B->rowidx;
+  a.Bv = (const VT *)B->values;
+  a.klo = klo;
+  a.khi = khi;
+  a.kdim = A->ncols;
+  a.m = A->nrows;
+  a.nnzA = A->nnz;
+  return a;
+}
+
+// One symbolic pass over inner range [klo, khi) writing one row of counts.
+static int symbolic_pass(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t ncol, int64_t klo,
+                         int64_t khi, int64_t *flops_out, int64_t *nnz_row, const WsLayout &L, char *ws,
+                         hipStream_t st) {
+  WsHeader *hdr = (WsHeader *)ws;
+  int32_t *bins = (int32_t *)(ws + L.bins);
+  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, 0);
+  LAUNCHCHK();
+  const int64_t per_block = 4 * kBinColsPerWave;
+  hipLaunchKernelGGL(k_bin<true>, dim3(grid_of(ncol, per_block)), dim3(256), 0, st, A->colptr, B->colptr, B->rowidx,
+                     c0, ncol, klo, khi, (int64_t)A->ncols, A->nrows, (const int64_t *)nullptr, flops_out, nnz_row,
+                     bins, hdr, g_min_bin);
+  LAUNCHCHK();
+  WsHeader h;
+  int rc = read_header(hdr, st, &h);
+  if (rc) return rc;
+  ProductArgs<float> a = product_args<float>(A, B, klo, khi);
+  int32_t *status = &hdr->status;
+  for (int b = 0; b < kNumBins; b++) {
+    const int cnt = h.bin_count[b];
+    if (!cnt) continue;
+    const int32_t *list = bins + (int64_t)b * ncol;
+    switch (b) {
+      case 0: hipLaunchKernelGGL(k_sym_wave<64>, dim3(grid_of(cnt, 4)), dim3(256), 0, st, a, c0, list, cnt, nnz_row, status); break;
+      case 1: hipLaunchKernelGGL(k_sym_wave<256>, dim3(grid_of(cnt, 4)), dim3(256), 0, st, a, c0, list, cnt, nnz_row, status); break;
+      case 2: hipLaunchKernelGGL(k_sym_wave<1024>, dim3(grid_of(cnt, 4)), dim3(256), 0, st, a, c0, list, cnt, nnz_row, status); break;
+      case 3: hipLaunchKernelGGL((k_sym_block<4096, 256>), dim3(cnt), dim3(256), 0, st, a, c0, list, nnz_row, status); break;
+      case 4: hipLaunchKernelGGL((k_sym_block<32768, 1024>), dim3(cnt), dim3(1024), 0, st, a, c0, list, nnz_row, status); break;
+      default: hipLaunchKernelGGL(k_sym_bitmap, dim3(cnt), dim3(1024), 0, st, a, c0, list, nnz_row, status); break;
+    }
+    LAUNCHCHK();
+  }
+  return SPGEMM_OK;
+}
+
+static uint64_t clean_tag_of(const WsLayout &L) {
+  return 0x5eed0000f00dull ^ ((uint64_t)L.slots << 40) ^ (uint64_t)L.m ^ ((uint64_t)L.heavy_vals << 20);
+}
+
+// Numeric-style pass (product or merge) given bins already filled.
+template <class VT, class Src>
+static int accumulate_pass(const Src &src, const WsHeader &h, const WsLayout &L, char *ws, const int64_t *c_colptr,
+                           int32_t *out_ri, VT *out_v, hipStream_t st) {
+  WsHeader *hdr = (WsHeader *)ws;
+  int32_t *bins = (int32_t *)(ws + L.bins);
+  int32_t *status = &hdr->status;
+  const int64_t ncol = L.ncol;
+  for (int b = 0; b < kNumBins - 1; b++) {
+    const int cnt = h.bin_count[b];
+    if (!cnt) continue;
+    const int32_t *list = bins + (int64_t)b * ncol;
+    switch (b) {
+      case 0: hipLaunchKernelGGL((k_num_wave<64, VT, Src>), dim3(grid_of(cnt, 4)), dim3(256), 0, st, src, list, cnt, c_colptr, out_ri, out_v, status); break;
+      case 1: hipLaunchKernelGGL((k_num_wave<256, VT, Src>), dim3(grid_of(cnt, 4)), dim3(256), 0, st, src, list, cnt, c_colptr, out_ri, out_v, status); break;
+      case 2: hipLaunchKernelGGL((k_num_wave<1024, VT, Src>), dim3(grid_of(cnt, 4)), dim3(256), 0, st, src, list, cnt, c_colptr, out_ri, out_v, status); break;
+      case 3: hipLaunchKernelGGL((k_num_block<4096, 256, VT, Src>), dim3(cnt), dim3(256), 0, st, src, list, c_colptr, out_ri, out_v, status); break;
+      default: hipLaunchKernelGGL((k_num_block<10240, 1024, VT, Src>), dim3(cnt), dim3(1024), 0, st, src, list, c_colptr, out_ri, out_v, status); break;
+    }
+    LAUNCHCHK();
+  }
+  const int heavy = h.bin_count[kNumBins - 1];
+  if (heavy > 0) {
+    if (L.slots <= 0) return SPGEMM_E_INVAL;
+    double *vals = (double *)(ws + L.heavy_vals);
+    uint8_t *flags = (uint8_t *)(ws + L.heavy_flags);
+    int64_t *segcnt = (int64_t *)(ws + L.heavy_segcnt);
+    const uint64_t tag = clean_tag_of(L);
+    if (h.clean_tag != tag) {
+      const int64_t bytes = (int64_t)(L.heavy_segcnt - L.heavy_vals);
+      hipLaunchKernelGGL(k_fill_zero, dim3(4 * device_cus()), dim3(256), 0, st, (uint4 *)(ws + L.heavy_vals), bytes / 16);
+      LAUNCHCHK();
+      hipLaunchKernelGGL(k_set_tag, dim3(1), dim3(64), 0, st, hdr, tag);
+      LAUNCHCHK();
+    }
+    const int32_t *list = bins + (int64_t)(kNumBins - 1) * ncol;
+    for (int first = 0; first < heavy; first += (int)L.slots) {
+      const int ns = (int)std::min<int64_t>(L.slots, heavy - first);
+      int parts = (int)std::max<int64_t>(1, std::min<int64_t>(64, (4 * device_cus() + ns - 1) / ns));
+      hipLaunchKernelGGL((k_heavy_acc<Src>), dim3(ns * parts), dim3(256), 0, st, src, list, first, ns, parts, L.m, vals,
+                         flags, status);
+      LAUNCHCHK();
+      hipLaunchKernelGGL(k_heavy_count, dim3((unsigned)(ns * L.nseg)), dim3(256), 0, st, ns, L.m, L.nseg, flags, segcnt);
+      LAUNCHCHK();
+      hipLaunchKernelGGL((k_heavy_write<VT>), dim3((unsigned)(ns * L.nseg)), dim3(256), 0, st, list, first, ns, L.m,
+                         L.nseg, vals, flags, segcnt, c_colptr, out_ri, out_v, status);
+      LAUNCHCHK();
+    }
+  }
+  return SPGEMM_OK;
+}
+
+template <class VT>
+static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t ncol, int64_t klo,
+                         int64_t khi, const int64_t *c_colptr, int32_t *c_rowidx, void *c_values, const WsLayout &L,
+                         char *ws, hipStream_t st) {
+  WsHeader *hdr = (WsHeader *)ws;
+  int32_t *bins = (int32_t *)(ws + L.bins);
+  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, 1);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_bin<false>, dim3(grid_of(ncol, 4 * kBinColsPerWave)), dim3(256), 0, st, A->colptr, B->colptr,
+                     B->rowidx, c0, ncol, klo, khi, (int64_t)A->ncols, A->nrows, c_colptr, (int64_t *)nullptr,
+                     (int64_t *)nullptr, bins, hdr, g_min_bin);
+  LAUNCHCHK();
+  WsHeader h;
+  int rc = read_header(hdr, st, &h);
+  if (rc) return rc;
+  ProductSrc<VT> src;
+  src.a = product_args<VT>(A, B, klo, khi);
+  src.c0 = c0;
+  return accumulate_pass<VT>(src, h, L, ws, c_colptr, c_rowidx, (VT *)c_values, st);
+}
+
+template <class VT>
+static int merge_typed(const spgemm_csc *parts, int32_t n_parts, const int64_t *c_colptr, int32_t *c_rowidx,
+                       void *c_values, const WsLayout &L, char *ws, hipStream_t st) {
+  WsHeader *hdr = (WsHeader *)ws;
+  int32_t *bins = (int32_t *)(ws + L.bins);
+  PartDesc *pd = (PartDesc *)(ws + L.parts);
+  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, 1);
+  LAUNCHCHK();
+  for (int c = 0; c < n_parts; c += kWave) {
+    PartsChunk hc;
+    memset(&hc, 0, sizeof(hc));
+    const int nc = std::min(kWave, n_parts - c);
+    for (int p = 0; p < nc; p++) hc.d[p] = PartDesc{parts[c + p].colptr, parts[c + p].rowidx, parts[c + p].values};
+    hipLaunchKernelGGL(k_store_parts, dim3(1), dim3(64), 0, st, pd + c, hc, nc);
+    LAUNCHCHK();
+  }
+  hipLaunchKernelGGL(k_bin<false>, dim3(grid_of(L.ncol, 4 * kBinColsPerWave)), dim3(256), 0, st,
+                     (const int64_t *)nullptr, (const int64_t *)nullptr, (const int32_t *)nullptr, (int64_t)0, L.ncol,
+                     (int64_t)0, (int64_t)0, (int64_t)0, L.m, c_colptr, (int64_t *)nullptr, (int64_t *)nullptr, bins,
+                     hdr, g_min_bin);
+  LAUNCHCHK();
+  WsHeader h;
+  int rc = read_header(hdr, st, &h);
+  if (rc) return rc;
+  MergeSrc<VT> src;
+  src.P = pd;
+  src.nparts = n_parts;
+  src.m = L.m;
+  return accumulate_pass<VT>(src, h, L, ws, c_colptr, c_rowidx, (VT *)c_values, st);
+}
+
+static_assert(sizeof(PartDesc) == kPartDescBytes, "part descriptor size");
+static_assert(sizeof(WsHeader) <= 2048, "header too large");
+
+}  // namespace spg
+
+using namespace spg;
+
+extern "C" {
+
+int spgemm_symbolic(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t c1, int32_t n_layers,
+                    int64_t *flops_out, int64_t *nnz_out, void *ws, size_t ws_bytes, void *stream) {
+  int st = check_csc(A, false);
+  if (!st) st = check_csc(B, false);
+  if (st) return st;
+  if (A->ncols != B->nrows) return SPGEMM_E_SHAPE;
+  if (c0 < 0 || c1 < c0 || c1 > B->ncols || n_layers < 1) return SPGEMM_E_INVAL;
+  if (c1 > c0 && !nnz_out) return SPGEMM_E_INVAL;
+  WsLayout L;
+  st = ws_layout(SPGEMM_OP_SYMBOLIC, A, B, c0, c1, n_layers, &L);
+  if (st) return st;
+  st = check_ws(ws, ws_bytes, L.total);
+  if (st) return st;
+  const int64_t ncol = c1 - c0;
+  hipStream_t s = (hipStream_t)stream;
+  char *w = (char *)ws;
+  if (ncol == 0) {
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)w, 0);
+    LAUNCHCHK();
+    return SPGEMM_OK;
+  }
+  const int64_t kdim = A->ncols;
+  if (n_layers == 1) return symbolic_pass(A, B, c0, ncol, 0, kdim, flops_out, nnz_out, L, w, s);
+  const int64_t width = (kdim + n_layers - 1) / n_layers;
+  for (int32_t l = 0; l < n_layers; l++) {
+    const int64_t klo = std::min<int64_t>(kdim, (int64_t)l * width), khi = std::min<int64_t>(kdim, klo + width);
+    int rc = symbolic_pass(A, B, c0, ncol, klo, khi, nullptr, nnz_out + (int64_t)l * ncol, L, w, s);
+    if (rc) return rc;
+  }
+  return symbolic_pass(A, B, c0, ncol, 0, kdim, flops_out, nnz_out + (int64_t)n_layers * ncol, L, w, s);
+}
+
+int spgemm_numeric(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t c1, int32_t layer,
+                   int32_t n_layers, const int64_t *flops, const int64_t *c_colptr, int32_t *c_rowidx,
+                   void *c_values, void *ws, size_t ws_bytes, void *stream) {
+  (void)flops;
+  int st = check_csc(A, true);
+  if (!st) st = check_csc(B, true);
+  if (st) return st;
+  if (A->dtype != B->dtype) return SPGEMM_E_DTYPE;
+  if (A->ncols != B->nrows) return SPGEMM_E_SHAPE;
+  if (c0 < 0 || c1 < c0 || c1 > B->ncols || n_layers < 1 || layer < 0 || layer >= n_layers) return SPGEMM_E_INVAL;
+  WsLayout L;
+  st = ws_layout(SPGEMM_OP_NUMERIC, A, B, c0, c1, n_layers, &L);
+  if (st) return st;
+  st = check_ws(ws, ws_bytes, L.total);
+  if (st) return st;
+  const int64_t ncol = c1 - c0;
+  if (ncol > 0 && !c_colptr) return SPGEMM_E_INVAL;
+  if (ncol == 0) {
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, (hipStream_t)stream, (WsHeader *)ws, 1);
+    LAUNCHCHK();
+    return SPGEMM_OK;
+  }
+  const int64_t kdim = A->ncols;
+  const int64_t width = (kdim + n_layers - 1) / n_layers;
+  const int64_t klo = std::min<int64_t>(kdim, (int64_t)layer * width), khi = std::min<int64_t>(kdim, klo + width);
+  hipStream_t s = (hipStream_t)stream;
+  if (A->dtype == SPGEMM_F32)
+    return numeric_typed<float>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, (char *)ws, s);
+  return numeric_typed<double>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, (char *)ws, s);
+}
+
+int spgemm_merge(const spgemm_csc *parts, int32_t n_parts, const int64_t *c_colptr, int32_t *c_rowidx,
+                 void *c_values, void *ws, size_t ws_bytes, void *stream) {
+  if (!parts || n_parts < 1 || n_parts > kMaxParts) return SPGEMM_E_INVAL;
+  for (int p = 0; p < n_parts; p++) {
+    int st = check_csc(&parts[p], true);
+    if (st) return st;
+    if (parts[p].nrows != parts[0].nrows || parts[p].ncols != parts[0].ncols) return SPGEMM_E_SHAPE;
+    if (parts[p].dtype != parts[0].dtype) return SPGEMM_E_DTYPE;
+  }
+  WsLayout L;
+  int st = ws_layout(SPGEMM_OP_MERGE, &parts[0], nullptr, 0, 0, n_parts, &L);
+  if (st) return st;
+  st = check_ws(ws, ws_bytes, L.total);
+  if (st) return st;
+  if (L.ncol > 0 && !c_colptr) return SPGEMM_E_INVAL;
+  if (L.ncol == 0) {
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, (hipStream_t)stream, (WsHeader *)ws, 1);
+    LAUNCHCHK();
+    return SPGEMM_OK;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (parts[0].dtype == SPGEMM_F32) return merge_typed<float>(parts, n_parts, c_colptr, c_rowidx, c_values, L, (char *)ws, s);
+  return merge_typed<double>(parts, n_parts, c_colptr, c_rowidx, c_values, L, (char *)ws, s);
+}
+
+int spgemm_colptr(const int64_t *counts, int64_t n, int64_t *colptr_out, void *ws, size_t ws_bytes, void *stream) {
+  if (n < 0 || !colptr_out || (n > 0 && !counts)) return SPGEMM_E_INVAL;
+  WsLayout L;
+  int st = ws_layout(SPGEMM_OP_COLPTR, nullptr, nullptr, 0, n, 1, &L);
+  if (st) return st;
+  st = check_ws(ws, ws_bytes, L.total);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  char *w = (char *)ws;
+  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)w, 0);
+  LAUNCHCHK();
+  if (n == 0) {
+    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, s, colptr_out, (int64_t)1);
+    LAUNCHCHK();
+    return SPGEMM_OK;
+  }
+  int64_t *bsum = (int64_t *)(w + L.scan);
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n, bsum);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kScanThreads), 0, s, bsum, nb);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n, bsum, colptr_out);
+  LAUNCHCHK();
+  return SPGEMM_OK;
+}
+
+int spgemm_debug_min_bin(int32_t bin) {
+  if (bin < 0 || bin >= kNumBins) return SPGEMM_E_INVAL;
+  g_min_bin = bin;
+  return SPGEMM_OK;
+}
+
+int spgemm_ws_status(void *ws, void *stream) {
+  if (!ws) return SPGEMM_E_WORKSPACE;
+  WsHeader h;
+  hipStream_t s = (hipStream_t)stream;
+  int rc = read_header((WsHeader *)ws, s, &h);
+  if (rc) return rc;
+  if (h.status != 0) {
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)ws, 1);
+    return SPGEMM_E_DEVICE;
+  }
+  return SPGEMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,40 @@
+"""Helpers for the GPU parity tests: compare a device CSC with the oracle."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle
+
+# float64 runs: 1e-12 relative to sum |a*b| per entry; float32 runs: 1e-5.
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
+
+
+def host_sorted(C):
+    """(colptr, rowidx sorted per column, values) of a device CSC, on the host."""
+    cp = C.colptr.cpu().numpy().astype(np.int64)
+    cp = cp - cp[0]
+    ri = C.rowidx.cpu().numpy()
+    v = C.values.cpu().numpy().astype(np.float64)
+    col = np.repeat(np.arange(cp.size - 1), np.diff(cp))
+    order = np.lexsort((ri, col))
+    return cp, ri[order], v[order]
+
+
+def assert_matches(C, P, dtype, what=""):
+    """Structure bit-exact (column pointers and per-column sorted rows) and
+    values within TOL[dtype] * sum |a*b| (the oracle's absum)."""
+    cp, ri, v = host_sorted(C)
+    assert cp.size == P.colptr.size, f"{what}: column count"
+    assert np.array_equal(cp, P.colptr), f"{what}: column pointers differ"
+    assert np.array_equal(ri, P.rowidx), f"{what}: row sets differ"
+    tol = TOL[dtype] * P.absum
+    err = np.abs(v - P.values)
+    bad = np.nonzero(err > tol)[0]
+    assert bad.size == 0, f"{what}: {bad.size} values off, worst {float((err / np.maximum(P.absum, 1e-300)).max()):.3e}"
+    # every column's rows unique (a lost or duplicated hash insert shows here)
+    assert np.all((np.diff(ri) > 0) | (np.diff(np.repeat(np.arange(cp.size - 1), np.diff(cp))) != 0))
+
+
+def to_dev(M, device="cuda"):
+    return M.to(device)

@@ -1,0 +1,171 @@
+"""Host-only checks of the C ABI: no GPU needed, no device work launched.
+
+Every call here either runs purely on the host (planner, sizing, status
+text) or fails argument validation before anything is enqueued.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2010_08526_amd as S
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "spgemm.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(spgemm_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 9
+    lib = ctypes.CDLL(S.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings():
+    for code in range(-8, 1):
+        assert S.status_string(code) and S.status_string(code) != "unknown status"
+    assert S.status_string(-99) == "unknown status"
+
+
+# ---------------------------------------------------------------- planner
+def _mem(nnz_rows, L, vbytes):
+    r = 4 + vbytes
+    if L == 1:
+        return (r * nnz_rows[0] + 8).tolist()
+    return (r * nnz_rows[:L].sum(0) + 8 * L + r * nnz_rows[L] + 8).tolist()
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_planner_matches_oracle_rule(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(0, 300))
+    L = int(rng.choice([1, 1, 2, 4, 16]))
+    rows = L + 1 if L > 1 else 1
+    vb = int(rng.choice([4, 8]))
+    nnz = rng.integers(0, 5000, (rows, n)).astype(np.int64)
+    if L > 1:  # union count <= sum of layer counts
+        nnz[L] = np.minimum(nnz[L], nnz[:L].sum(0))
+    mem = _mem(nnz, L, vb)
+    inp, res = int(rng.integers(0, 1000)), int(rng.integers(0, 1000))
+    lo = max(mem) if mem else 1
+    avail = int(rng.integers(lo, lo + sum(mem) + 2))
+    bounds, tot = S.plan_batches(nnz.reshape(-1), n, L, vb, inp, inp + res + avail, res, 100000)
+    assert bounds == oracle.plan_batches(mem, avail)
+    for i in range(len(bounds) - 1):
+        assert np.array_equal(tot[i], nnz[:, bounds[i]:bounds[i + 1]].sum(1))
+
+
+def test_planner_errors():
+    nnz = np.array([10, 20, 30], np.int64)
+    with pytest.raises(S.SpgemmError) as e:
+        S.plan_batches(nnz, 3, 1, 4, 100, 100, 0)  # nothing left for outputs
+    assert e.value.status == S.E_BUDGET
+    with pytest.raises(S.SpgemmError) as e:
+        S.plan_batches(nnz, 3, 1, 4, 0, 200, 0)  # column 2 needs 8*30+8 = 248 > 200
+    assert e.value.status == S.E_BUDGET
+    with pytest.raises(S.SpgemmError) as e:
+        S.plan_batches(nnz, 3, 1, 4, 0, 300, 0, max_batches=1)
+    assert e.value.status == S.E_BUDGET
+    with pytest.raises(S.SpgemmError) as e:
+        S.plan_batches(nnz, 3, 1, 5, 0, 300, 0)
+    assert e.value.status == S.E_DTYPE
+    b, tot = S.plan_batches(nnz, 3, 1, 4, 0, 10 ** 6, 0)
+    assert b == [0, 3] and tot.tolist() == [[60]]
+    b, tot = S.plan_batches(np.zeros(0, np.int64), 0, 1, 4, 0, 100, 0)
+    assert b == [0, 0]
+
+
+def test_planner_fits_exactly_at_the_boundary():
+    nnz = np.array([1, 1, 1, 1], np.int64)  # 16 bytes per column with float32
+    b, _ = S.plan_batches(nnz, 4, 1, 4, 0, 64, 0)
+    assert b == [0, 4]
+    b, _ = S.plan_batches(nnz, 4, 1, 4, 0, 63, 0)
+    assert b == [0, 2, 4]
+
+
+# ------------------------------------------------------------- validation
+class FakeCSC:
+    """Descriptor with non-null fake device addresses; validation never reads them."""
+
+    def __init__(self, nrows, ncols, nnz, dtype=S.F32, values=True):
+        self.d = S.spgemm_csc(nrows, ncols, nnz, 0x1000, 0x2000, 0x3000 if values else None, dtype)
+
+
+def _sym(A, B, c0=0, c1=None, L=1, nnz_out=0x5000, ws=None, ws_bytes=1 << 30):
+    c1 = B.d.ncols if c1 is None else c1
+    return S._lib.spgemm_symbolic(ctypes.byref(A.d) if A else None, ctypes.byref(B.d) if B else None, c0, c1, L,
+                                  None, nnz_out, ws, ws_bytes, None)
+
+
+def test_symbolic_validation_before_launch():
+    A, B = FakeCSC(10, 8, 5), FakeCSC(8, 7, 5)
+    assert _sym(None, B) == S.E_INVAL
+    assert _sym(A, FakeCSC(9, 7, 5)) == S.E_SHAPE
+    assert _sym(A, B, c0=3, c1=2) == S.E_INVAL
+    assert _sym(A, B, c1=8) == S.E_INVAL
+    assert _sym(A, B, L=0) == S.E_INVAL
+    assert _sym(A, B, nnz_out=None) == S.E_INVAL
+    assert _sym(A, B, ws=None) == S.E_WORKSPACE
+    assert _sym(A, B, ws=0x10010) == S.E_WORKSPACE  # not 256-byte aligned
+    assert _sym(A, B, ws=0x10000, ws_bytes=16) == S.E_WORKSPACE
+    assert _sym(FakeCSC(1 << 31, 8, 5), B) == S.E_OVERFLOW
+    bad = FakeCSC(10, 8, -1)
+    assert _sym(bad, B) == S.E_INVAL
+
+
+def test_numeric_and_merge_validation_before_launch():
+    A, B = FakeCSC(10, 8, 5), FakeCSC(8, 7, 5, dtype=S.F64)
+    lib = S._lib
+    r = lib.spgemm_numeric(ctypes.byref(A.d), ctypes.byref(B.d), 0, 7, 0, 1, None, 0x1, 0x1, 0x1, 0x10000, 1 << 30,
+                           None)
+    assert r == S.E_DTYPE  # mixed dtypes
+    B2 = FakeCSC(8, 7, 5)
+    r = lib.spgemm_numeric(ctypes.byref(A.d), ctypes.byref(B2.d), 0, 7, 2, 2, None, 0x1, 0x1, 0x1, 0x10000, 1 << 30,
+                           None)
+    assert r == S.E_INVAL  # layer >= n_layers
+    noval = FakeCSC(10, 8, 5, values=False)
+    r = lib.spgemm_numeric(ctypes.byref(noval.d), ctypes.byref(B2.d), 0, 7, 0, 1, None, 0x1, 0x1, 0x1, 0x10000,
+                           1 << 30, None)
+    assert r == S.E_INVAL  # numeric needs values
+    r = lib.spgemm_numeric(ctypes.byref(A.d), ctypes.byref(FakeCSC(8, 7, 5, dtype=7).d), 0, 7, 0, 1, None, 0x1, 0x1,
+                           0x1, 0x10000, 1 << 30, None)
+    assert r == S.E_DTYPE
+    parts = (S.spgemm_csc * 2)(FakeCSC(10, 4, 3).d, FakeCSC(10, 5, 3).d)
+    assert lib.spgemm_merge(parts, 2, 0x1, 0x1, 0x1, 0x10000, 1 << 30, None) == S.E_SHAPE
+    assert lib.spgemm_merge(parts, 0, 0x1, 0x1, 0x1, 0x10000, 1 << 30, None) == S.E_INVAL
+    assert lib.spgemm_merge(parts, 4097, 0x1, 0x1, 0x1, 0x10000, 1 << 30, None) == S.E_INVAL
+    parts = (S.spgemm_csc * 2)(FakeCSC(10, 4, 3).d, FakeCSC(10, 4, 3, dtype=S.F64).d)
+    assert lib.spgemm_merge(parts, 2, 0x1, 0x1, 0x1, 0x10000, 1 << 30, None) == S.E_DTYPE
+    assert lib.spgemm_colptr(0x1, -1, 0x1, 0x10000, 1 << 20, None) == S.E_INVAL
+    assert lib.spgemm_colptr(0x1, 10, None, 0x10000, 1 << 20, None) == S.E_INVAL
+    assert lib.spgemm_colptr(0x1, 10, 0x1, 0x10000, 8, None) == S.E_WORKSPACE
+    assert lib.spgemm_ws_status(None, None) == S.E_WORKSPACE
+
+
+def test_workspace_size_depends_on_shapes():
+    A, B = FakeCSC(1000, 800, 5), FakeCSC(800, 700, 5)
+    out = ctypes.c_size_t()
+    for op in (S.OP_SYMBOLIC, S.OP_NUMERIC):
+        assert S._lib.spgemm_workspace_size(op, ctypes.byref(A.d), ctypes.byref(B.d), 0, 700, 1, ctypes.byref(out)) == 0
+        assert out.value >= 4096 and out.value % 256 == 0
+    # heavy accumulators appear only when a column can exceed the LDS bins
+    S._lib.spgemm_workspace_size(S.OP_NUMERIC, ctypes.byref(A.d), ctypes.byref(B.d), 0, 700, 1, ctypes.byref(out))
+    small = out.value
+    Abig = FakeCSC(1 << 20, 800, 5)
+    S._lib.spgemm_workspace_size(S.OP_NUMERIC, ctypes.byref(Abig.d), ctypes.byref(B.d), 0, 700, 1, ctypes.byref(out))
+    assert out.value > small + (1 << 29)
+    assert S._lib.spgemm_workspace_size(99, ctypes.byref(A.d), ctypes.byref(B.d), 0, 700, 1, ctypes.byref(out)) == S.E_INVAL
+    assert S._lib.spgemm_workspace_size(S.OP_NUMERIC, ctypes.byref(A.d), ctypes.byref(B.d), 0, 701, 1,
+                                        ctypes.byref(out)) == S.E_INVAL
+    assert S._lib.spgemm_workspace_size(S.OP_COLPTR, None, None, 0, 1 << 20, 1, ctypes.byref(out)) == 0
