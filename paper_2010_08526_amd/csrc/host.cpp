@@ -69,7 +69,15 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
         L->parts = off;
         off = align_up(off + kPartDescBytes * (size_t)n_layers);
       }
-      if (op != SPGEMM_OP_SYMBOLIC && A->nrows > kNumCap[kNumBins - 2]) {
+      if (op == SPGEMM_OP_NUMERIC && A->nrows > kNumCap[kNumBins - 2] && num_slabs(A->nrows) <= kMaxSlabs) {
+        L->P = num_slabs(A->nrows);
+        L->slab_off = off;
+        off = align_up(off + sizeof(int32_t) * (size_t)(L->P + 1) * (size_t)A->ncols);
+        L->slab_ri = off;
+        off = align_up(off + sizeof(int32_t) * (size_t)A->nnz);
+        L->slab_v = off;
+        off = align_up(off + sizeof(double) * (size_t)A->nnz);
+      } else if (op != SPGEMM_OP_SYMBOLIC && A->nrows > kNumCap[kNumBins - 2]) {
         L->slots = heavy_slots(A->nrows);
         L->nseg = (A->nrows + kHeavySeg - 1) / kHeavySeg;
         L->heavy_vals = off;

@@ -30,8 +30,21 @@ constexpr int64_t kNumCap[kNumBins - 1] = {32, 128, 512, 2048, 5120};
 constexpr int kMaxParts = 4096;  // merge: parts per call
 constexpr size_t kPartDescBytes = 24;  // device-side copy of one part's pointers
 constexpr int64_t kBitmapRows = 1 << 20;  // heavy symbolic: rows per LDS bitmap window (128 KiB)
-constexpr int64_t kHeavySeg = 16384;  // heavy numeric: rows per compaction segment
+constexpr int64_t kHeavySeg = 16384;  // global heavy path: rows per compaction segment
 constexpr int kMaxAdeg = 1 << 25;  // per-column degree of the left operand handled per chunk
+
+// Heavy numeric columns: the left operand's entries are bucketed by row slab
+// of 2^kSlabShift rows; a heavy column is formed one group of consecutive
+// slabs at a time in LDS: a hash table when the group holds at most
+// kGroupCap distinct rows, else a single slab in a dense array.
+constexpr int kSlabShift = 13;
+constexpr int64_t kSlabRows = int64_t(1) << kSlabShift;
+constexpr int kMaxSlabs = 1024;  // rows up to kMaxSlabs * kSlabRows use slabs
+constexpr int kGroupSlots = 10240;
+constexpr int kGroupCap = 5120;
+constexpr int kWinSlabs = (int)(kBitmapRows / kSlabRows);  // slabs per counting window
+
+inline int64_t num_slabs(int64_t m) { return (m + kSlabRows - 1) / kSlabRows; }
 
 // Workspace header: one 4 KiB block at offset 0.
 struct WsHeader {
@@ -62,6 +75,10 @@ struct WsLayout {
   size_t heavy_segcnt = 0;// int64 [slots][nseg]
   size_t scan = 0;        // int64 block sums
   size_t parts = 0;       // merge: part descriptors
+  size_t slab_off = 0;    // numeric: int32 [kcols][P+1] slab offsets of the left operand
+  size_t slab_ri = 0;     // numeric: int32 [nnzA] slabbed rows
+  size_t slab_v = 0;      // numeric: 8-byte [nnzA] slabbed values
+  int64_t P = 0;          // numeric: slabs (0 = heavy columns use global accumulators)
   size_t total = 0;
   int64_t slots = 0, nseg = 0, ncol = 0, m = 0;
 };

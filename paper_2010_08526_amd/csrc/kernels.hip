@@ -58,36 +58,142 @@ struct ProductArgs {
 // r_stride waves can share one column; r_stride = 1 processes every round.
 // The owner of round fb's first element comes from a ballot (the highest
 // lane whose segment starts at or before fb), so rounds are independent.
-template <class Body>
+// Rounds are taken kPipe at a time: owners first, then every gather
+// (load(o, e, row, val)), then every insert (ins(row, val)), so that a
+// wavefront keeps kPipe independent global loads in flight.
+constexpr int kPipe = 8;
+
+template <class Load, class Ins>
 __device__ __forceinline__ void flatten_rounds(int len, int excl, int total, int *mark, int64_t r_base,
-                                               int64_t r_rank, int64_t r_stride, Body &&body) {
+                                               int64_t r_rank, int64_t r_stride, uint32_t m, int32_t *status,
+                                               Load &&load, Ins &&ins) {
   const int l = lane();
   int64_t r0 = (r_rank - r_base) % r_stride;
   if (r0 < 0) r0 += r_stride;
-  for (int64_t r = r0; r * kWave < total; r += r_stride) {
-    const int fb = (int)(r * kWave);
-    const uint64_t started = __ballot(len > 0 && excl <= fb);
-    const int carry = started ? 64 - __clzll((long long)started) : 0;
-    if (len > 0 && excl > fb && excl < fb + kWave) mark[excl - fb] = l + 1;
-    wave_sync();
-    const int mk = mark[l];
-    mark[l] = 0;
-    const int own = max(wave_incl_max(mk), carry);
-    const int e = fb + l;
-    if (e < total) body(own - 1, e);
-    wave_sync();
+  for (int64_t r = r0; r * kWave < total; r += kPipe * r_stride) {
+    int own_[kPipe], e_[kPipe];
+#pragma unroll
+    for (int u = 0; u < kPipe; u++) {
+      const int64_t rr = r + u * r_stride;
+      own_[u] = -1;
+      e_[u] = 0;
+      if (rr * kWave < total) {
+        const int fb = (int)(rr * kWave);
+        const int last = min(fb + kWave - 1, total - 1);
+        const uint64_t started = __ballot(len > 0 && excl <= fb);
+        const int carry = started ? 64 - __clzll((long long)started) : 0;
+        int own;
+        if (__ballot(len > 0 && excl <= last) == started) {
+          own = carry;  // no segment starts inside this round: one owner
+        } else {
+          if (len > 0 && excl > fb && excl < fb + kWave) mark[excl - fb] = l + 1;
+          wave_sync();
+          const int mk = mark[l];
+          mark[l] = 0;
+          own = max(wave_incl_max(mk), carry);
+          wave_sync();
+        }
+        const int e = fb + l;
+        if (e < total) {
+          own_[u] = own - 1;
+          e_[u] = e;
+        }
+      }
+    }
+    int32_t row_[kPipe];
+    double v_[kPipe];
+    // gathers: nothing below depends on a loaded value until every load is issued
+#pragma unroll
+    for (int u = 0; u < kPipe; u++) {
+      row_[u] = -1;
+      v_[u] = 0.0;
+      if (own_[u] >= 0) load(own_[u], e_[u], row_[u], v_[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kPipe; u++) {
+      if (own_[u] >= 0) {
+        if ((uint32_t)row_[u] < m)
+          ins(row_[u], v_[u]);
+        else
+          flag_error(status, 3);
+      }
+    }
   }
 }
+
+// Long segments (at least kLongSeg elements) bypass the owner search: the
+// whole wavefront streams them in blocks of kBlk elements, element
+// blk*kBlk + t*64 + lane for t < kVec, so every load instruction reads 64
+// consecutive entries and each lane keeps kVec loads in flight.  Blocks are
+// numbered from unit_base and split among r_stride waves like rounds.
+constexpr int kLongSeg = 256;
+constexpr int kVec = 8;
+constexpr int kBlk = kWave * kVec;
+
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  return __longlong_as_double((long long)readlane64((int64_t)__double_as_longlong(v), l));
+}
+
+template <bool VALUES, class VT, class Ins>
+__device__ __forceinline__ void stream_segment(const int32_t *__restrict__ ri, const VT *__restrict__ v,
+                                               double scale, int len, int64_t unit_base, int64_t r_rank,
+                                               int64_t r_stride, uint32_t m, int32_t *status, Ins &&ins) {
+  const int l = lane();
+  const int64_t nblk = (len + kBlk - 1) / kBlk;
+  int64_t b0 = (r_rank - unit_base) % r_stride;
+  if (b0 < 0) b0 += r_stride;
+  for (int64_t blk = b0; blk < nblk; blk += r_stride) {
+    const int e0 = (int)blk * kBlk + l;
+    int32_t row[kVec];
+    double val[kVec];
+#pragma unroll
+    for (int t = 0; t < kVec; t++) {
+      const int e = e0 + t * kWave;
+      row[t] = 0;
+      val[t] = 0.0;
+      if (e < len) {
+        row[t] = ri[e];
+        if (VALUES) val[t] = (double)v[e] * scale;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kVec; t++) {
+      if (e0 + t * kWave < len) {
+        if ((uint32_t)row[t] < m)
+          ins(row[t], val[t]);
+        else
+          flag_error(status, 3);
+      }
+    }
+  }
+}
+
+// Row-slab view of the left operand: entries of each column k in [klo,khi)
+// grouped by slab (row >> kSlabShift); slab s of column k occupies
+// [Acp[k] + off[(k-klo)*(P+1)+s], Acp[k] + off[(k-klo)*(P+1)+s+1]) of the
+// slabbed row/value copies.  sa, sb select the slab range [sa, sb).
+struct SlabSel {
+  const int32_t *off;
+  int P, sa, sb;
+};
 
 // Visits every product term A(i,k)*B(k,j) of output column `col` with
 // k in [klo, khi): ins(i, A(i,k)*B(k,j)) (values in float64).  Chunks of 64
 // entries of B(:,col) are split among waves: chunk c is read by waves with
 // (c % c_stride) == c_rank when c_stride > 1 and r_stride == 1; with
-// r_stride > 1 every wave reads every chunk and the rounds are split.
-template <bool VALUES, class VT, class Ins>
+// r_stride > 1 every wave reads every chunk and the rounds are split.  With
+// SLAB, only the terms whose row lies in the selected slabs are visited
+// (a.Ari/a.Av then point at the slabbed copies).
+template <bool VALUES, class VT, bool SLAB = false, class Ins>
 __device__ __forceinline__ void traverse_product(const ProductArgs<VT> &a, int64_t col, int64_t c_rank,
                                                  int64_t c_stride, int64_t r_rank, int64_t r_stride,
-                                                 SegScratch &sc, int32_t *status, Ins &&ins) {
+                                                 SegScratch &sc, int32_t *status, Ins &&ins,
+                                                 SlabSel sl = SlabSel{nullptr, 0, 0, 0}) {
   const int l = lane();
   const int64_t pbeg = a.Bcp[col], pend = a.Bcp[col + 1];
   int64_t rounds_before = 0;
@@ -102,43 +208,83 @@ __device__ __forceinline__ void traverse_product(const ProductArgs<VT> &a, int64
         flag_error(status, 1);
       } else if (k >= a.klo && k < a.khi) {
         const int64_t a0 = a.Acp[k];
-        const int64_t d = a.Acp[k + 1] - a0;
+        int64_t d;
+        if (SLAB) {
+          const int32_t *o = sl.off + (int64_t)(k - a.klo) * (sl.P + 1);
+          const int32_t s0 = o[sl.sa];
+          d = o[sl.sb] - s0;
+          off = a0 + s0;
+        } else {
+          d = a.Acp[k + 1] - a0;
+          off = a0;
+        }
         if (d < 0 || d >= kMaxAdeg) {
           flag_error(status, 2);
+          off = 0;
         } else {
           len = (int)d;
-          off = a0;
           if (VALUES) b = (double)a.Bv[p];
         }
       }
     }
-    const int incl = wave_incl_add(len);
-    const int excl = incl - len;
+    // short segments: load-balanced rounds
+    const bool lg = len >= kLongSeg;
+    const int ls = lg ? 0 : len;
+    const int incl = wave_incl_add(ls);
+    const int excl = incl - ls;
     const int total = readlane(incl, 63);
-    if (total == 0) continue;
-    sc.off[l] = off - excl;
-    if (VALUES) sc.scale[l] = b;
-    wave_sync();
-    flatten_rounds(len, excl, total, sc.mark, rounds_before, r_rank, r_stride, [&](int o, int e) {
-      const int64_t q = sc.off[o] + e;
-      if ((uint64_t)q >= (uint64_t)a.nnzA) {
+    if (total > 0) {
+      sc.off[l] = off - excl;
+      if (VALUES) sc.scale[l] = b;
+      wave_sync();
+      flatten_rounds(
+          ls, excl, total, sc.mark, rounds_before, r_rank, r_stride, (uint32_t)a.m, status,
+          [&](int o, int e, int32_t &row, double &v) {
+            int64_t q = sc.off[o] + e;
+            if ((uint64_t)q >= (uint64_t)a.nnzA) {
+              flag_error(status, 5);
+              q = 0;  // row 0 of a bounded read; the status word records the fault
+            }
+            row = a.Ari[q];
+            if (VALUES) v = (double)a.Av[q] * sc.scale[o];
+          },
+          ins);
+      rounds_before += (total + kWave - 1) / kWave;
+      wave_sync();
+    }
+    // long segments: streamed one at a time by the whole wave
+    uint64_t lm = __ballot(lg);
+    while (lm) {
+      const int L = __builtin_ctzll(lm);
+      lm &= lm - 1;
+      const int64_t so = readlane64(off, L);
+      const int sn = readlane(len, L);
+      const double sb = VALUES ? readlane_f64(b, L) : 0.0;
+      if (so < 0 || so + sn > a.nnzA) {
         flag_error(status, 5);
-        return;
+        continue;
       }
-      const int32_t row = a.Ari[q];
-      if ((uint32_t)row >= (uint32_t)a.m) {
-        flag_error(status, 3);
-        return;
-      }
-      if (VALUES) {
-        ins(row, (double)a.Av[q] * sc.scale[o]);
-      } else {
-        ins(row, 0.0);
-      }
-    });
-    rounds_before += (total + kWave - 1) / kWave;
-    wave_sync();
+      stream_segment<VALUES, VT>(a.Ari + so, VALUES ? a.Av + so : nullptr, sb, sn, rounds_before, r_rank, r_stride,
+                                 (uint32_t)a.m, status, ins);
+      rounds_before += (sn + kBlk - 1) / kBlk;
+    }
   }
+}
+
+// A whole workgroup of nw waves on one column: columns with many chunks of
+// B(:,col) split the chunks among the waves; columns with few chunks (a
+// handful of long segments is typical of heavy columns) split the rounds of
+// every chunk instead, so that no wave idles.  (Splitting fewer chunks among
+// groups of waves loses more to uneven chunks than it saves in re-reads.)
+template <bool VALUES, class VT, bool SLAB = false, class Ins>
+__device__ __forceinline__ void traverse_product_block(const ProductArgs<VT> &a, int64_t col, int w, int nw,
+                                                       SegScratch &sc, int32_t *status, Ins &&ins,
+                                                       SlabSel sl = SlabSel{nullptr, 0, 0, 0}) {
+  const int64_t nchunks = (a.Bcp[col + 1] - a.Bcp[col] + kWave - 1) / kWave;
+  if (nchunks >= 2 * nw)
+    traverse_product<VALUES, VT, SLAB>(a, col, w, nw, 0, 1, sc, status, ins, sl);
+  else
+    traverse_product<VALUES, VT, SLAB>(a, col, 0, 1, w, nw, sc, status, ins, sl);
 }
 
 // Visits every stored entry of column `col` of the parts: ins(i, value).
@@ -166,23 +312,35 @@ __device__ __forceinline__ void traverse_merge(const PartDesc *P, int nparts, in
         v = (const VT *)P[p].v + a0;
       }
     }
-    const int incl = wave_incl_add(len);
-    const int excl = incl - len;
+    const bool lg = len >= kLongSeg;
+    const int ls = lg ? 0 : len;
+    const int incl = wave_incl_add(ls);
+    const int excl = incl - ls;
     const int total = readlane(incl, 63);
-    if (total == 0) continue;
-    sc.ri[l] = ri - excl;
-    sc.v[l] = (const void *)(v - excl);
-    wave_sync();
-    flatten_rounds(len, excl, total, sc.mark, rounds_before, r_rank, r_stride, [&](int o, int e) {
-      const int32_t row = sc.ri[o][e];
-      if ((uint32_t)row >= (uint32_t)m) {
-        flag_error(status, 3);
-        return;
-      }
-      ins(row, (double)((const VT *)sc.v[o])[e]);
-    });
-    rounds_before += (total + kWave - 1) / kWave;
-    wave_sync();
+    if (total > 0) {
+      sc.ri[l] = ri - excl;
+      sc.v[l] = (const void *)(v - excl);
+      wave_sync();
+      flatten_rounds(
+          ls, excl, total, sc.mark, rounds_before, r_rank, r_stride, (uint32_t)m, status,
+          [&](int o, int e, int32_t &row, double &v) {
+            row = sc.ri[o][e];
+            v = (double)((const VT *)sc.v[o])[e];
+          },
+          ins);
+      rounds_before += (total + kWave - 1) / kWave;
+      wave_sync();
+    }
+    uint64_t lm = __ballot(lg);
+    while (lm) {
+      const int L = __builtin_ctzll(lm);
+      lm &= lm - 1;
+      const int32_t *sri = (const int32_t *)readlane64((int64_t)ri, L);
+      const VT *sv = (const VT *)readlane64((int64_t)v, L);
+      const int sn = readlane(len, L);
+      stream_segment<true, VT>(sri, sv, 1.0, sn, rounds_before, r_rank, r_stride, (uint32_t)m, status, ins);
+      rounds_before += (sn + kBlk - 1) / kBlk;
+    }
   }
 }
 
@@ -377,7 +535,7 @@ __global__ __launch_bounds__(THREADS) void k_sym_block(ProductArgs<float> a, int
   __syncthreads();
   const int32_t jj = list[blockIdx.x];
   int cnt = 0;
-  traverse_product<false, float>(a, c0 + jj, w, NW, 0, 1, s_sc[w], status, [&](int32_t row, double) {
+  traverse_product_block<false, float>(a, c0 + jj, w, NW, s_sc[w], status, [&](int32_t row, double) {
     cnt += ht_insert_key(s_keys, TBL, row) ? 1 : 0;
   });
   cnt = wave_sum_i32(cnt);
@@ -400,15 +558,16 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(ProductArgs<float> a, int64
   if (threadIdx.x == 0) s_cnt = 0;
   const int32_t jj = list[blockIdx.x];
   for (int64_t r0 = 0; r0 < a.m; r0 += kBitmapRows) {
-    for (int s = threadIdx.x; s < kBmWords; s += 1024) s_bm[s] = 0;
+    const int words = (int)((min((int64_t)kBitmapRows, a.m - r0) + 31) / 32);
+    for (int s = threadIdx.x; s < words; s += 1024) s_bm[s] = 0;
     __syncthreads();
-    traverse_product<false, float>(a, c0 + jj, w, NW, 0, 1, s_sc[w], status, [&](int32_t row, double) {
+    traverse_product_block<false, float>(a, c0 + jj, w, NW, s_sc[w], status, [&](int32_t row, double) {
       const int64_t r = (int64_t)row - r0;
       if (r >= 0 && r < kBitmapRows) atomicOr(&s_bm[r >> 5], 1u << (r & 31));
     });
     __syncthreads();
     int c = 0;
-    for (int s = threadIdx.x; s < kBmWords; s += 1024) c += __popc(s_bm[s]);
+    for (int s = threadIdx.x; s < words; s += 1024) c += __popc(s_bm[s]);
     c = wave_sum_i32(c);
     if (l == 0) atomicAdd(&s_cnt, (unsigned long long)c);
     __syncthreads();
@@ -427,7 +586,10 @@ struct ProductSrc {
   template <class Ins>
   __device__ __forceinline__ void visit(int64_t jj, int64_t c_rank, int64_t c_stride, int64_t r_rank,
                                         int64_t r_stride, void *scratch, int32_t *status, Ins &&ins) const {
-    traverse_product<true, VT>(a, c0 + jj, c_rank, c_stride, r_rank, r_stride, *(SegScratch *)scratch, status, ins);
+    if (c_stride > 1 && r_stride == 1)
+      traverse_product_block<true, VT>(a, c0 + jj, (int)c_rank, (int)c_stride, *(SegScratch *)scratch, status, ins);
+    else
+      traverse_product<true, VT>(a, c0 + jj, c_rank, c_stride, r_rank, r_stride, *(SegScratch *)scratch, status, ins);
   }
   static constexpr size_t kScratch = sizeof(SegScratch);
 };
@@ -530,6 +692,191 @@ __global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *l
   compact_range<VT>(s_keys, s_vals, w * PER, min(TBL, (w + 1) * PER), base, cap, &s_written, out_ri, out_v);
   __syncthreads();
   if (threadIdx.x == 0 && s_written != cap) flag_error(status, 4);
+}
+
+// ----------------------------------------------------------------------------
+// Heavy columns, LDS path.  First the left operand's columns k in [klo,khi)
+// are bucketed by row slab (a counting sort on row >> kSlabShift inside each
+// column; one wavefront per column).
+// ----------------------------------------------------------------------------
+template <class VT>
+__global__ __launch_bounds__(256) void k_slab_split(const int64_t *Acp, const int32_t *Ari, const VT *Av,
+                                                    int64_t klo, int64_t khi, int P, int32_t *soff,
+                                                    int32_t *s_ri, VT *s_v) {
+  __shared__ int s_hist[4][kMaxSlabs + 1];
+  const int w = threadIdx.x / kWave, l = lane();
+  const int64_t k = klo + (int64_t)blockIdx.x * 4 + w;
+  if (k >= khi) return;
+  int *h = s_hist[w];
+  for (int t = l; t <= P; t += kWave) h[t] = 0;
+  wave_sync();
+  const int64_t a0 = Acp[k], a1 = Acp[k + 1];
+  for (int64_t p = a0 + l; p < a1; p += kWave) {
+    const uint32_t sl = min((uint32_t)Ari[p] >> kSlabShift, (uint32_t)(P - 1));
+    atomicAdd(&h[sl], 1);
+  }
+  wave_sync();
+  int32_t *o = soff + (k - klo) * (int64_t)(P + 1);
+  int carry = 0;
+  for (int t0 = 0; t0 < P; t0 += kWave) {
+    const int t = t0 + l;
+    const int c = t < P ? h[t] : 0;
+    const int incl = wave_incl_add(c);
+    if (t < P) {
+      o[t] = carry + incl - c;
+      h[t] = carry + incl - c;
+    }
+    carry += readlane(incl, 63);
+  }
+  if (l == 0) o[P] = carry;
+  wave_sync();
+  for (int64_t p = a0 + l; p < a1; p += kWave) {
+    const int32_t row = Ari[p];
+    const uint32_t sl = min((uint32_t)row >> kSlabShift, (uint32_t)(P - 1));
+    const int pos = atomicAdd(&h[sl], 1);
+    s_ri[a0 + pos] = row;
+    s_v[a0 + pos] = Av[p];
+  }
+}
+
+// One workgroup per heavy column.  For each window of kBitmapRows rows: an
+// LDS bitmap pass counts the distinct rows of every slab; consecutive slabs
+// are grouped while their counts sum to at most kGroupCap; each group is
+// accumulated over the slabbed operand in an LDS hash table (or, for a
+// single slab with more than kGroupCap rows, a dense LDS array) and written
+// out at the column's running offset.  Output groups follow row order; rows
+// inside a hash group are in table order.
+constexpr int kHeavyThreads = 1024;
+constexpr int kBigBytes = 131072;
+static_assert(kGroupSlots * 12 <= kBigBytes, "group table does not fit");
+static_assert(kSlabRows * 8 + kSlabRows / 8 <= kBigBytes, "dense slab does not fit");
+static_assert(kBitmapRows / 8 <= kBigBytes, "bitmap does not fit");
+
+template <class VT>
+__global__ __launch_bounds__(kHeavyThreads) void k_heavy_slab(ProductArgs<VT> a, ProductArgs<VT> sa, SlabSel sel,
+                                                              int64_t c0, const int32_t *list,
+                                                              const int64_t *c_colptr, int32_t *out_ri, VT *out_v,
+                                                              int32_t *status) {
+  constexpr int NW = kHeavyThreads / kWave;
+  __shared__ __align__(16) unsigned char s_big[kBigBytes];
+  __shared__ int s_cnt[kWinSlabs];
+  __shared__ SegScratch s_sc[NW];
+  __shared__ int s_wsum[NW];
+  __shared__ int s_written;
+  const int w = threadIdx.x / kWave, l = lane();
+  s_sc[w].mark[l] = 0;
+  const int32_t jj = list[blockIdx.x];
+  const int64_t col = c0 + jj;
+  const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
+  int64_t running = 0;
+  for (int64_t r0 = 0; r0 < a.m; r0 += kBitmapRows) {
+    const int64_t wrows = min((int64_t)kBitmapRows, a.m - r0);
+    const int words = (int)((wrows + 31) / 32);
+    const int nsl = (int)((wrows + kSlabRows - 1) / kSlabRows);
+    const int slab0 = (int)(r0 >> kSlabShift);
+    // ---- count distinct rows per slab
+    uint32_t *bm = (uint32_t *)s_big;
+    for (int t = threadIdx.x; t < words; t += kHeavyThreads) bm[t] = 0;
+    __syncthreads();
+    traverse_product_block<false, VT>(a, col, w, NW, s_sc[w], status, [&](int32_t row, double) {
+      const int64_t r = (int64_t)row - r0;
+      if (r >= 0 && r < wrows) atomicOr(&bm[r >> 5], 1u << (r & 31));
+    });
+    __syncthreads();
+    constexpr int WPS = (int)(kSlabRows / 32);  // words per slab
+    for (int t = w; t < nsl; t += NW) {
+      int c = 0;
+      for (int q = l; q < WPS; q += kWave) {
+        const int wi = t * WPS + q;
+        c += wi < words ? __popc(bm[wi]) : 0;
+      }
+      c = wave_sum_i32(c);
+      if (l == 0) s_cnt[t] = c;
+    }
+    __syncthreads();
+    // ---- groups of slabs (every thread derives the same grouping)
+    int t = 0;
+    while (t < nsl) {
+      if (s_cnt[t] == 0) {
+        t++;
+        continue;
+      }
+      int t2 = t + 1, gcnt = s_cnt[t];
+      const bool dense = gcnt > kGroupCap;
+      if (!dense) {
+        while (t2 < nsl && gcnt + s_cnt[t2] <= kGroupCap) gcnt += s_cnt[t2++];
+      }
+      SlabSel g = sel;
+      g.sa = slab0 + t;
+      g.sb = slab0 + t2;
+      const int64_t gbase = base + running;
+      if (dense) {
+        double *acc = (double *)s_big;
+        uint32_t *bits = (uint32_t *)(s_big + kSlabRows * 8);
+        const int64_t rb = r0 + (int64_t)t * kSlabRows;
+        for (int q = threadIdx.x; q < (int)kSlabRows; q += kHeavyThreads) acc[q] = 0.0;
+        for (int q = threadIdx.x; q < (int)(kSlabRows / 32); q += kHeavyThreads) bits[q] = 0;
+        __syncthreads();
+        traverse_product_block<true, VT, true>(sa, col, w, NW, s_sc[w], status, [&](int32_t row, double v) {
+          const int64_t r = (int64_t)row - rb;
+          if (r >= 0 && r < kSlabRows) {
+            atomicAdd(&acc[r], v);
+            atomicOr(&bits[r >> 5], 1u << (r & 31));
+          }
+        }, g);
+        __syncthreads();
+        // ordered compaction: thread q < kSlabRows/32 owns word q
+        const int q = threadIdx.x;
+        const uint32_t word = q < (int)(kSlabRows / 32) ? bits[q] : 0u;
+        const int c = __popc(word);
+        const int incl = wave_incl_add(c);
+        if (l == kWave - 1) s_wsum[w] = incl;
+        __syncthreads();
+        int wb = 0, wt = 0;
+        for (int z = 0; z < NW; z++) {
+          if (z < w) wb += s_wsum[z];
+          wt += s_wsum[z];
+        }
+        if (threadIdx.x == 0 && wt != gcnt) flag_error(status, 6);
+        int64_t o = wb + incl - c;
+        uint32_t bw = word;
+        while (bw) {
+          const int b = __ffs(bw) - 1;
+          bw &= bw - 1;
+          const int r = q * 32 + b;
+          if (running + o < cap) {
+            out_ri[gbase + o] = (int32_t)(rb + r);
+            out_v[gbase + o] = (VT)acc[r];
+          }
+          o++;
+        }
+        __syncthreads();
+      } else {
+        int32_t *keys = (int32_t *)s_big;
+        double *vals = (double *)(s_big + kGroupSlots * 4);
+        for (int q = threadIdx.x; q < kGroupSlots; q += kHeavyThreads) {
+          keys[q] = kEmpty;
+          vals[q] = 0.0;
+        }
+        if (threadIdx.x == 0) s_written = 0;
+        __syncthreads();
+        traverse_product_block<true, VT, true>(sa, col, w, NW, s_sc[w], status, [&](int32_t row, double v) {
+          ht_accumulate(keys, vals, kGroupSlots, row, v);
+        }, g);
+        __syncthreads();
+        constexpr int PER = (kGroupSlots + NW - 1) / NW;
+        const int64_t room = cap - running;
+        compact_range<VT>(keys, vals, w * PER, min(kGroupSlots, (w + 1) * PER), gbase, min(room, (int64_t)gcnt),
+                          &s_written, out_ri, out_v);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_written != gcnt) flag_error(status, 6);
+      }
+      running += gcnt;
+      t = t2;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && running != cap) flag_error(status, 4);
 }
 
 // Heavy columns: dense float64 accumulators in the workspace, one per slot;
@@ -822,7 +1169,7 @@ static uint64_t clean_tag_of(const WsLayout &L) {
 // Numeric-style pass (product or merge) given bins already filled.
 template <class VT, class Src>
 static int accumulate_pass(const Src &src, const WsHeader &h, const WsLayout &L, char *ws, const int64_t *c_colptr,
-                           int32_t *out_ri, VT *out_v, hipStream_t st) {
+                           int32_t *out_ri, VT *out_v, hipStream_t st, bool heavy_global = true) {
   WsHeader *hdr = (WsHeader *)ws;
   int32_t *bins = (int32_t *)(ws + L.bins);
   int32_t *status = &hdr->status;
@@ -841,7 +1188,7 @@ static int accumulate_pass(const Src &src, const WsHeader &h, const WsLayout &L,
     LAUNCHCHK();
   }
   const int heavy = h.bin_count[kNumBins - 1];
-  if (heavy > 0) {
+  if (heavy > 0 && heavy_global) {
     if (L.slots <= 0) return SPGEMM_E_INVAL;
     double *vals = (double *)(ws + L.heavy_vals);
     uint8_t *flags = (uint8_t *)(ws + L.heavy_flags);
@@ -889,7 +1236,29 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
   ProductSrc<VT> src;
   src.a = product_args<VT>(A, B, klo, khi);
   src.c0 = c0;
-  return accumulate_pass<VT>(src, h, L, ws, c_colptr, c_rowidx, (VT *)c_values, st);
+  const bool slabs = L.P > 0;
+  rc = accumulate_pass<VT>(src, h, L, ws, c_colptr, c_rowidx, (VT *)c_values, st, !slabs);
+  if (rc) return rc;
+  const int heavy = h.bin_count[kNumBins - 1];
+  if (slabs && heavy > 0) {
+    int32_t *soff = (int32_t *)(ws + L.slab_off);
+    int32_t *s_ri = (int32_t *)(ws + L.slab_ri);
+    VT *s_v = (VT *)(ws + L.slab_v);
+    if (khi > klo) {
+      hipLaunchKernelGGL(k_slab_split<VT>, dim3(grid_of(khi - klo, 4)), dim3(256), 0, st, A->colptr, A->rowidx,
+                         (const VT *)A->values, klo, khi, (int)L.P, soff, s_ri, s_v);
+      LAUNCHCHK();
+    }
+    ProductArgs<VT> sa = src.a;
+    sa.Ari = s_ri;
+    sa.Av = s_v;
+    SlabSel sel{soff, (int)L.P, 0, 0};
+    const int32_t *list = bins + (int64_t)(kNumBins - 1) * ncol;
+    hipLaunchKernelGGL(k_heavy_slab<VT>, dim3(heavy), dim3(kHeavyThreads), 0, st, src.a, sa, sel, c0, list, c_colptr,
+                       c_rowidx, (VT *)c_values, &hdr->status);
+    LAUNCHCHK();
+  }
+  return SPGEMM_OK;
 }
 
 template <class VT>

@@ -216,3 +216,16 @@ def test_colptr_scan_large():
         S.colptr(d, out, ws)
         ref = np.concatenate([[0], np.cumsum(x)])
         assert np.array_equal(out.cpu().numpy(), ref)
+
+
+def test_heavy_columns_tall_matrix_two_windows():
+    """m = 1.5M rows: heavy columns span two counting windows and 184 row
+    slabs; u_j ~ 12000 > the largest LDS bin."""
+    print("case: tall heavy", flush=True)
+    A = synth.erdos_renyi(1_500_000, 2000, 30, 31, torch.float32)
+    B = synth.erdos_renyi(2000, 64, 400, 32, torch.float32)
+    fl, nz = _symbolic(A, B)
+    assert np.array_equal(nz[0], oracle.count(A, B))
+    assert nz[0].min() > 5120
+    C, _ = _run(A, B)
+    assert_matches(C, oracle.spgemm(A, B), torch.float32, "tall")
