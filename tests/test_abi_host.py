@@ -164,7 +164,11 @@ def test_workspace_size_depends_on_shapes():
     small = out.value
     Abig = FakeCSC(1 << 20, 800, 5)
     S._lib.spgemm_workspace_size(S.OP_NUMERIC, ctypes.byref(Abig.d), ctypes.byref(B.d), 0, 700, 1, ctypes.byref(out))
-    assert out.value > small + (1 << 29)
+    # numeric: int32 slab offsets, (rows / 8192 + 1) per column of A, plus a slabbed copy of A
+    assert out.value >= small + 4 * 129 * 800
+    # merge keeps dense float64 accumulators for its heavy columns (about 1 GiB)
+    S._lib.spgemm_workspace_size(S.OP_MERGE, ctypes.byref(Abig.d), None, 0, 0, 4, ctypes.byref(out))
+    assert out.value > (1 << 29)
     assert S._lib.spgemm_workspace_size(99, ctypes.byref(A.d), ctypes.byref(B.d), 0, 700, 1, ctypes.byref(out)) == S.E_INVAL
     assert S._lib.spgemm_workspace_size(S.OP_NUMERIC, ctypes.byref(A.d), ctypes.byref(B.d), 0, 701, 1,
                                         ctypes.byref(out)) == S.E_INVAL
