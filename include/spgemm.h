@@ -162,6 +162,42 @@ int spgemm_numeric(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t
 int spgemm_merge(const spgemm_csc *parts, int32_t n_parts, const int64_t *c_colptr, int32_t *c_rowidx,
                  void *c_values, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- Gradient support.  For a loss defined on the pattern of C = A*B
+ * (not part of the paper), with dC = dLoss/dC on P(C):
+ *   dB = masked_xty(X = A,   Y = dC,   M = P(B))          aligned with B,
+ *   dA = scatter of masked_xty(X = B^T, Y = dC^T, M = P(A^T)) back to A's
+ *        storage through A^T's permutation.
+ * Every dC(i,j) these need lies in P(C). ---- */
+
+/* Sort-free transpose: X^T in CSC (X.ncols rows, X.nrows columns).
+ * t_colptr[X.nrows+1], t_rowidx[X.nnz] (column ids of X, in arbitrary order
+ * inside each column of X^T), t_values[X.nnz] of X's dtype (may be NULL:
+ * pattern only), perm[X.nnz] (may be NULL): perm[q] = the position in X of
+ * the entry stored at position q of X^T.  Requires X.ncols <= INT32_MAX.
+ * Workspace: spgemm_workspace_size(SPGEMM_OP_TRANSPOSE, X, ...).  Rows of X
+ * out of range set the workspace status and are dropped.  Asynchronous. */
+int spgemm_transpose(const spgemm_csc *X, int64_t *t_colptr, int32_t *t_rowidx, void *t_values, int64_t *perm,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* Masked product out(k,j) = sum over i of X(i,k) * Y(i,j) for every stored
+ * entry (k,j) of the pattern M, written at M's storage position
+ * (out_values[M.nnz], X's dtype; X and Y share a dtype; M's values are not
+ * read).  Shapes: X is m x K, Y is m x n, M is K x n.  Rows of Y(:,j) absent
+ * from a term count as zero.  Per output column j, Y(:,j) is held in an LDS
+ * hash table (or, above the largest table, a dense column of the workspace)
+ * and each entry of M(:,j) is a dot product against X(:,k), accumulated in
+ * float64 and rounded once.  Workspace: SPGEMM_OP_MASKED_XTY with A = X,
+ * B = Y.  Asynchronous. */
+int spgemm_masked_xty(const spgemm_csc *X, const spgemm_csc *Y, const spgemm_csc *M, void *out_values, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/* Value permutation of n elements of `dtype`: scatter == 0 gathers
+ * dst[i] = src[perm[i]]; scatter != 0 scatters dst[perm[i]] = src[i].  perm
+ * entries outside [0, n) are skipped.  src and dst must not overlap.
+ * Asynchronous; no workspace. */
+int spgemm_permute(const void *src, const int64_t *perm, int64_t n, int32_t dtype, int32_t scatter, void *dst,
+                   void *stream);
+
 /* Synchronizes `stream` and reports the device-side status word of a
  * workspace used by the calls above: SPGEMM_OK, or SPGEMM_E_DEVICE if a
  * kernel found counts that disagree with the product or an index out of

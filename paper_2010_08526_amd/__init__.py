@@ -334,3 +334,115 @@ def spgemm(A, B, *, layers: int = 1, budget_bytes: int | None = None, consume=No
     eng = Engine(A, B, layers, budget_bytes)
     res = eng.run(consume, stream)
     return res if consume is not None else res[0]
+
+
+# ------------------------------------------------------------ gradient support
+_lib.spgemm_transpose.argtypes = [_P, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.spgemm_masked_xty.argtypes = [_P, _P, _P, _vp, _vp, _sz, _vp]
+_lib.spgemm_permute.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _vp]
+
+
+def transpose(X, ws: torch.Tensor | None = None, values: bool = True, perm: bool = True, stream=None):
+    """X^T as a CSC (values optional) and the permutation perm with
+    X^T.values[q] = X.values[perm[q]]."""
+    dev = X.rowidx.device
+    if ws is None:
+        ws = alloc_workspace(workspace_size(OP_TRANSPOSE, X), dev)
+    tcp = torch.empty(X.nrows + 1, dtype=torch.int64, device=dev)
+    tri = torch.empty(max(1, X.nnz), dtype=torch.int32, device=dev)
+    tv = torch.empty(max(1, X.nnz), dtype=X.values.dtype, device=dev) if (values and X.values is not None) else None
+    pm = torch.empty(max(1, X.nnz), dtype=torch.int64, device=dev) if perm else None
+    _check(_lib.spgemm_transpose(ctypes.byref(desc(X)), _ptr(tcp), _ptr(tri), _ptr(tv), _ptr(pm), _ptr(ws),
+                                 ws.numel(), _stream(stream)), "spgemm_transpose")
+    n = X.nnz
+    T = CSC(X.ncols, X.nrows, tcp, tri[:n], None if tv is None else tv[:n])
+    return T, (None if pm is None else pm[:n])
+
+
+def masked_xty(X, Y, M, out: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None):
+    """out(k,j) = sum_i X(i,k) Y(i,j) for each stored (k,j) of M, in M's order."""
+    dev = Y.rowidx.device
+    if ws is None:
+        ws = alloc_workspace(workspace_size(OP_MASKED_XTY, X, Y, 0, Y.ncols), dev)
+    if out is None:
+        out = torch.empty(max(1, M.nnz), dtype=Y.values.dtype, device=dev)
+    Md = desc(M, F32)
+    Md.values = None
+    _check(_lib.spgemm_masked_xty(ctypes.byref(desc(X)), ctypes.byref(desc(Y)), ctypes.byref(Md), _ptr(out), _ptr(ws),
+                                  ws.numel(), _stream(stream)), "spgemm_masked_xty")
+    return out[:M.nnz]
+
+
+def permute(src: torch.Tensor, perm: torch.Tensor, scatter: bool = False, out: torch.Tensor | None = None,
+            stream=None) -> torch.Tensor:
+    """Gather out[i] = src[perm[i]] or scatter out[perm[i]] = src[i]."""
+    n = perm.numel()
+    if out is None:
+        out = torch.empty(n, dtype=src.dtype, device=src.device)
+    _check(_lib.spgemm_permute(_ptr(src), _ptr(perm), n, _DTYPE[src.dtype], int(scatter), _ptr(out), _stream(stream)),
+           "spgemm_permute")
+    return out
+
+
+class Backward:
+    """Gradients of a loss on P(C), C = A B, with respect to the stored values
+    of A and B.  The transposes of A's and B's patterns and of C's pattern are
+    formed once (per structure) and reused."""
+
+    def __init__(self, A, B, C, stream=None):
+        self.A, self.B, self.C = A, B, C
+        dev = C.rowidx.device
+        self.ws_tr = alloc_workspace(max(workspace_size(OP_TRANSPOSE, M) for M in (A, B, C)), dev)
+        self.AT, self.permA = transpose(A, self.ws_tr, values=False, perm=True, stream=stream)
+        self.CT, self.permC = transpose(C, self.ws_tr, values=False, perm=True, stream=stream)
+        self.BT, self.permB = transpose(B, self.ws_tr, values=True, perm=True, stream=stream)
+        self.ws_b = alloc_workspace(workspace_size(OP_MASKED_XTY, A, C, 0, C.ncols), dev)
+        self.ws_a = alloc_workspace(workspace_size(OP_MASKED_XTY, self.BT, self.CT, 0, self.CT.ncols), dev)
+
+    def refresh_values(self, B, stream=None):
+        """New values of B (same pattern): B^T's values are re-gathered."""
+        self.B = B
+        permute(B.values, self.permB, False, self.BT.values, stream)
+
+    def __call__(self, dC_values: torch.Tensor, stream=None):
+        A, B, C = self.A, self.B, self.C
+        Y = CSC(C.nrows, C.ncols, C.colptr, C.rowidx, dC_values)
+        dB = masked_xty(A, Y, B, ws=self.ws_b, stream=stream)
+        dCT = permute(dC_values, self.permC, False, stream=stream)
+        YT = CSC(self.CT.nrows, self.CT.ncols, self.CT.colptr, self.CT.rowidx, dCT)
+        dAT = masked_xty(self.BT, YT, self.AT, ws=self.ws_a, stream=stream)
+        dA = permute(dAT, self.permA, True, stream=stream)
+        return dA, dB
+
+    def check(self, stream=None):
+        for w in (self.ws_tr, self.ws_b, self.ws_a):
+            check_ws(w, "device-side check (backward)", stream)
+
+
+class SpGEMMFn(torch.autograd.Function):
+    """C.values = (A B).values as a function of A's and B's stored values;
+    C's pattern (colptr, rowidx) is returned as non-differentiable outputs.
+
+        c_vals, c_colptr, c_rowidx = SpGEMMFn.apply(a_vals, b_vals, A, B)
+
+    A and B give the patterns (their own values are ignored)."""
+
+    @staticmethod
+    def forward(ctx, a_vals, b_vals, A, B, layers=1, budget_bytes=None):
+        Av = CSC(A.nrows, A.ncols, A.colptr, A.rowidx, a_vals)
+        Bv = CSC(B.nrows, B.ncols, B.colptr, B.rowidx, b_vals)
+        C, _ = Engine(Av, Bv, layers, budget_bytes).run()
+        ctx.save_for_backward(a_vals, b_vals)
+        ctx.A, ctx.B, ctx.C = A, B, CSC(C.nrows, C.ncols, C.colptr, C.rowidx, None)
+        ctx.mark_non_differentiable(C.colptr, C.rowidx)
+        return C.values, C.colptr, C.rowidx
+
+    @staticmethod
+    def backward(ctx, d_vals, _d_cp, _d_ri):
+        a_vals, b_vals = ctx.saved_tensors
+        A = CSC(ctx.A.nrows, ctx.A.ncols, ctx.A.colptr, ctx.A.rowidx, a_vals)
+        B = CSC(ctx.B.nrows, ctx.B.ncols, ctx.B.colptr, ctx.B.rowidx, b_vals)
+        bw = Backward(A, B, ctx.C)
+        dA, dB = bw(d_vals.contiguous())
+        bw.check()
+        return dA, dB, None, None, None, None

@@ -40,7 +40,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     hipcc = _hipcc()
     objs = []
-    for src in ("host.cpp", "kernels.hip"):
+    for src in ("host.cpp", "kernels.hip", "backward.hip"):
         obj = os.path.join(LIBDIR, src.replace(".", "_") + ".o")
         cmd = [hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):

@@ -1,0 +1,32 @@
+// Host-side helpers shared by the HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace spg {
+
+int hip_fail(hipError_t e);
+int read_header(WsHeader *dev, hipStream_t st, WsHeader *out);  // synchronizes st
+int device_cus();
+int launch_init_header(WsHeader *h, int keep_clean, hipStream_t st);
+int launch_set_tag(WsHeader *h, uint64_t tag, hipStream_t st);
+int g_min_bin_value();  // the spgemm_debug_min_bin setting
+// colptr_out[0] = 0, colptr_out[i+1] = counts[0] + ... + counts[i]; bsum holds n / 8192 + 2 int64
+int launch_colptr_scan(const int64_t *counts, int64_t n, int64_t *colptr_out, int64_t *bsum, hipStream_t st);
+
+inline unsigned grid_of(int64_t n, int64_t per) { return (unsigned)((n + per - 1) / per); }
+
+#define HIPCHK(x)                              \
+  do {                                         \
+    hipError_t e_ = (x);                       \
+    if (e_ != hipSuccess) return hip_fail(e_); \
+  } while (0)
+#define LAUNCHCHK()                            \
+  do {                                         \
+    hipError_t e_ = hipGetLastError();         \
+    if (e_ != hipSuccess) return hip_fail(e_); \
+  } while (0)
+
+}  // namespace spg

@@ -89,6 +89,30 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
       }
       break;
     }
+    case SPGEMM_OP_TRANSPOSE: {
+      if (!A) return SPGEMM_E_INVAL;
+      if (A->nrows < 0 || A->nrows > INT32_MAX) return SPGEMM_E_OVERFLOW;
+      L->m = A->nrows;
+      L->bins = off;  // int64 row counts, then cursors
+      off = align_up(off + sizeof(int64_t) * (size_t)A->nrows);
+      L->scan = off;
+      off = align_up(off + sizeof(int64_t) * (size_t)(A->nrows / 8192 + 2));
+      break;
+    }
+    case SPGEMM_OP_MASKED_XTY: {
+      if (!A || !B) return SPGEMM_E_INVAL;
+      if (B->nrows < 0 || B->nrows > INT32_MAX) return SPGEMM_E_OVERFLOW;
+      L->ncol = B->ncols;
+      L->m = B->nrows;
+      L->bins = off;
+      off = align_up(off + sizeof(int32_t) * kNumBins * (size_t)B->ncols);
+      if (B->nrows > kNumCap[kNumBins - 2]) {
+        L->slots = heavy_slots(B->nrows);
+        L->heavy_vals = off;
+        off = align_up(off + sizeof(double) * (size_t)L->slots * (size_t)B->nrows);
+      }
+      break;
+    }
     case SPGEMM_OP_COLPTR: {
       if (c0 < 0 || c1 < c0) return SPGEMM_E_INVAL;
       int64_t n = c1 - c0;

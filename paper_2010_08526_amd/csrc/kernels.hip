@@ -18,6 +18,8 @@
 
 #include "device.hpp"
 #include "internal.hpp"
+#include "lds_hash.hpp"
+#include "hip_host.hpp"
 
 namespace spg {
 
@@ -129,15 +131,6 @@ __device__ __forceinline__ void flatten_rounds(int len, int excl, int total, int
 constexpr int kLongSeg = 256;
 constexpr int kVec = 8;
 constexpr int kBlk = kWave * kVec;
-
-__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-  return __longlong_as_double((long long)readlane64((int64_t)__double_as_longlong(v), l));
-}
 
 template <bool VALUES, class VT, class Ins>
 __device__ __forceinline__ void stream_segment(const int32_t *__restrict__ ri, const VT *__restrict__ v,
@@ -341,47 +334,6 @@ __device__ __forceinline__ void traverse_merge(const PartDesc *P, int nparts, in
       stream_segment<true, VT>(sri, sv, 1.0, sn, rounds_before, r_rank, r_stride, (uint32_t)m, status, ins);
       rounds_before += (sn + kBlk - 1) / kBlk;
     }
-  }
-}
-
-// ============================================================================
-// LDS hash tables (open addressing, linear probing, key kEmpty = free).
-// ============================================================================
-__device__ __forceinline__ int32_t lds_load(int32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
-
-// Inserts `key`; returns true if this call created it.
-__device__ __forceinline__ bool ht_insert_key(int32_t *keys, uint32_t T, int32_t key) {
-  uint32_t h = hash_slot(key, T);
-  for (uint32_t probe = 0; probe < T; probe++) {
-    const int32_t k = lds_load(&keys[h]);
-    if (k == key) return false;
-    if (k == kEmpty) {
-      const int32_t old = atomicCAS(&keys[h], kEmpty, key);
-      if (old == kEmpty) return true;
-      if (old == key) return false;
-    }
-    h = (h + 1 == T) ? 0 : h + 1;
-  }
-  return false;  // unreachable with tables at most half full
-}
-
-// Adds `v` to the slot of `key`, creating it if needed.
-__device__ __forceinline__ void ht_accumulate(int32_t *keys, double *vals, uint32_t T, int32_t key, double v) {
-  uint32_t h = hash_slot(key, T);
-  for (uint32_t probe = 0; probe < T; probe++) {
-    const int32_t k = lds_load(&keys[h]);
-    if (k == key) {
-      atomicAdd(&vals[h], v);
-      return;
-    }
-    if (k == kEmpty) {
-      const int32_t old = atomicCAS(&keys[h], kEmpty, key);
-      if (old == kEmpty || old == key) {
-        atomicAdd(&vals[h], v);
-        return;
-      }
-    }
-    h = (h + 1 == T) ? 0 : h + 1;
   }
 }
 
@@ -1065,30 +1017,20 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_final(const int64_t *x, i
 // ============================================================================
 // Host side.
 // ============================================================================
-static int hip_fail(hipError_t e) {
+int hip_fail(hipError_t e) {
   set_hip_error((int)e);
   return SPGEMM_E_HIP;
 }
-#define HIPCHK(x)                                \
-  do {                                           \
-    hipError_t e_ = (x);                         \
-    if (e_ != hipSuccess) return hip_fail(e_);   \
-  } while (0)
-#define LAUNCHCHK()                                         \
-  do {                                                      \
-    hipError_t e_ = hipGetLastError();                      \
-    if (e_ != hipSuccess) return hip_fail(e_);              \
-  } while (0)
-
-// Testing hook: every column goes to at least this bin (0 = natural bins).
-static int g_min_bin = 0;
 
 struct HostPinned {
   WsHeader *hdr = nullptr;
 };
 static thread_local HostPinned g_pin;
 
-static int read_header(WsHeader *dev, hipStream_t st, WsHeader *out) {
+// Testing hook: every column goes to at least this bin (0 = natural bins).
+static int g_min_bin = 0;
+
+int read_header(WsHeader *dev, hipStream_t st, WsHeader *out) {
   if (!g_pin.hdr) HIPCHK(hipHostMalloc((void **)&g_pin.hdr, sizeof(WsHeader), hipHostMallocDefault));
   HIPCHK(hipMemcpyAsync(g_pin.hdr, dev, sizeof(WsHeader), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1096,7 +1038,7 @@ static int read_header(WsHeader *dev, hipStream_t st, WsHeader *out) {
   return SPGEMM_OK;
 }
 
-static int device_cus() {
+int device_cus() {
   static int cus = 0;
   static std::once_flag once;
   std::call_once(once, [] {
@@ -1108,7 +1050,36 @@ static int device_cus() {
   return cus;
 }
 
-static inline unsigned grid_of(int64_t n, int64_t per) { return (unsigned)((n + per - 1) / per); }
+int g_min_bin_value() { return g_min_bin; }
+
+int launch_set_tag(WsHeader *h, uint64_t tag, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_tag, dim3(1), dim3(64), 0, st, h, tag);
+  LAUNCHCHK();
+  return SPGEMM_OK;
+}
+
+int launch_init_header(WsHeader *h, int keep_clean, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, h, keep_clean);
+  LAUNCHCHK();
+  return SPGEMM_OK;
+}
+
+int launch_colptr_scan(const int64_t *counts, int64_t n, int64_t *out, int64_t *bsum, hipStream_t s) {
+  if (n == 0) {
+    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, s, out, (int64_t)1);
+    LAUNCHCHK();
+    return SPGEMM_OK;
+  }
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n, bsum);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kScanThreads), 0, s, bsum, nb);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n, bsum, out);
+  LAUNCHCHK();
+  return SPGEMM_OK;
+}
+
 
 template <class VT>
 static ProductArgs<VT> product_args(const spgemm_csc *A, const spgemm_csc *B, int64_t klo, int64_t khi) {
@@ -1398,22 +1369,9 @@ int spgemm_colptr(const int64_t *counts, int64_t n, int64_t *colptr_out, void *w
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
   char *w = (char *)ws;
-  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)w, 0);
-  LAUNCHCHK();
-  if (n == 0) {
-    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, s, colptr_out, (int64_t)1);
-    LAUNCHCHK();
-    return SPGEMM_OK;
-  }
-  int64_t *bsum = (int64_t *)(w + L.scan);
-  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
-  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n, bsum);
-  LAUNCHCHK();
-  hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kScanThreads), 0, s, bsum, nb);
-  LAUNCHCHK();
-  hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n, bsum, colptr_out);
-  LAUNCHCHK();
-  return SPGEMM_OK;
+  st = launch_init_header((WsHeader *)w, 0, s);
+  if (st) return st;
+  return launch_colptr_scan(counts, n, colptr_out, (int64_t *)(w + L.scan), s);
 }
 
 int spgemm_debug_min_bin(int32_t bin) {

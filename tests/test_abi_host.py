@@ -173,3 +173,25 @@ def test_workspace_size_depends_on_shapes():
     assert S._lib.spgemm_workspace_size(S.OP_NUMERIC, ctypes.byref(A.d), ctypes.byref(B.d), 0, 701, 1,
                                         ctypes.byref(out)) == S.E_INVAL
     assert S._lib.spgemm_workspace_size(S.OP_COLPTR, None, None, 0, 1 << 20, 1, ctypes.byref(out)) == 0
+
+
+def test_backward_validation_before_launch():
+    lib = S._lib
+    X, Y, M = FakeCSC(10, 8, 5), FakeCSC(10, 7, 5), FakeCSC(8, 7, 5, values=False)
+    r = lib.spgemm_masked_xty(ctypes.byref(X.d), ctypes.byref(FakeCSC(11, 7, 5).d), ctypes.byref(M.d), 0x1, 0x10000,
+                              1 << 30, None)
+    assert r == S.E_SHAPE
+    r = lib.spgemm_masked_xty(ctypes.byref(X.d), ctypes.byref(FakeCSC(10, 7, 5, dtype=S.F64).d), ctypes.byref(M.d),
+                              0x1, 0x10000, 1 << 30, None)
+    assert r == S.E_DTYPE
+    r = lib.spgemm_masked_xty(ctypes.byref(X.d), ctypes.byref(Y.d), ctypes.byref(M.d), None, 0x10000, 1 << 30, None)
+    assert r == S.E_INVAL
+    r = lib.spgemm_masked_xty(ctypes.byref(X.d), ctypes.byref(Y.d), ctypes.byref(M.d), 0x1, None, 1 << 30, None)
+    assert r == S.E_WORKSPACE
+    assert lib.spgemm_transpose(None, 0x1, 0x1, None, None, 0x10000, 1 << 30, None) == S.E_INVAL
+    assert lib.spgemm_transpose(ctypes.byref(X.d), None, 0x1, None, None, 0x10000, 1 << 30, None) == S.E_INVAL
+    assert lib.spgemm_transpose(ctypes.byref(X.d), 0x1, 0x1, None, None, 0x10000, 8, None) == S.E_WORKSPACE
+    assert lib.spgemm_permute(0x1, 0x1, 10, 9, 0, 0x1, None) == S.E_DTYPE
+    assert lib.spgemm_permute(None, 0x1, 10, S.F32, 0, 0x1, None) == S.E_INVAL
+    assert lib.spgemm_permute(0x1, 0x1, -1, S.F32, 0, 0x1, None) == S.E_INVAL
+    assert lib.spgemm_permute(None, None, 0, S.F32, 0, None, None) == S.OK
