@@ -81,7 +81,9 @@ typedef enum {
   SPGEMM_OP_MERGE = 2,
   SPGEMM_OP_COLPTR = 3,
   SPGEMM_OP_MASKED_XTY = 4,
-  SPGEMM_OP_TRANSPOSE = 5
+  SPGEMM_OP_TRANSPOSE = 5,
+  SPGEMM_OP_BATCHED_FORWARD = 6,
+  SPGEMM_OP_BATCHED_BACKWARD = 7
 } spgemm_op;
 
 /* Workspace bytes needed by one call of `op`.  Host only; never syncs.
@@ -92,6 +94,8 @@ typedef enum {
  *   COLPTR:            c1 - c0 = number of counts; A, B unused (may be NULL).
  *   MASKED_XTY:        A = X, B = Y (M has Y's column count).
  *   TRANSPOSE:         A = the matrix to transpose.
+ *   BATCHED_FORWARD:   A, B = the packed operands; c0 = 0, c1 = B.ncols.
+ *   BATCHED_BACKWARD:  A, B = the operands of the product.
  * The result depends only on shapes, never on device data. */
 int spgemm_workspace_size(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t c1,
                           int32_t n_layers, size_t *bytes_host);
@@ -197,6 +201,71 @@ int spgemm_masked_xty(const spgemm_csc *X, const spgemm_csc *Y, const spgemm_csc
  * Asynchronous; no workspace. */
 int spgemm_permute(const void *src, const int64_t *perm, int64_t n, int32_t dtype, int32_t scatter, void *dst,
                    void *stream);
+
+/* ---- Batched form (not part of the paper).  A batch of independent
+ * products C_i = A_i * B_i is one product of block-diagonal operands: A_i
+ * occupies rows [r_i, r_i + m_i) and columns [k_i, k_i + K_i) of A, B_i rows
+ * [k_i, ...) and columns [c_i, c_i + n_i) of B, and C_i is then columns
+ * [c_i, c_i + n_i) of C with rows shifted by r_i.  Every phase runs once
+ * over all instances; binning by column balances uneven instances. ---- */
+
+/* Packs `count` instances (host array of descriptors, device arrays inside)
+ * into one block-diagonal CSC: colptr_out[sum ncols + 1], rowidx_out[sum nnz]
+ * (rows shifted by the instance's row offset), values_out[sum nnz] (may be
+ * NULL).  offsets_host[3*(count+1)] receives (row, column, entry) offsets of
+ * every instance followed by the totals.  ws: at least 64*count bytes.
+ * Packed rows must fit int32.  Blocks the host until done (the descriptor
+ * table is staged from host memory). */
+int spgemm_batch_pack(const spgemm_csc *instances, int32_t count, int64_t *colptr_out, int32_t *rowidx_out,
+                      void *values_out, int64_t *offsets_host, void *ws, size_t ws_bytes, void *stream);
+
+/* Whole product C = A*B with no host synchronization and launch grids that
+ * do not depend on device data, so the call can be captured in a HIP graph
+ * and replayed: symbolic pass (flops_out[B.ncols] may be NULL,
+ * nnz_out[B.ncols] per-column counts), column pointers c_colptr[B.ncols+1],
+ * numeric pass into c_rowidx/c_values of capacity nnz_cap entries.  The bin
+ * kernels are persistent: a fixed grid pulls columns from device-side bins.
+ * If nnz(C) exceeds nnz_cap the output is cut at the capacity and the
+ * workspace status reports SPGEMM_E_DEVICE.  Columns above the largest LDS
+ * table are supported when A has at most 8,388,608 rows (row-slab path);
+ * otherwise they are reported through the status word.  No batch planner:
+ * the caller sizes outputs (a previous symbolic pass gives nnz(C) exactly).
+ * Workspace: SPGEMM_OP_BATCHED_FORWARD. */
+int spgemm_batched_forward(const spgemm_csc *A, const spgemm_csc *B, int64_t nnz_cap, int64_t *flops_out,
+                           int64_t *nnz_out, int64_t *c_colptr, int32_t *c_rowidx, void *c_values, void *ws,
+                           size_t ws_bytes, void *stream);
+
+/* spgemm_masked_xty with no host synchronization (graph-capturable, same
+ * workspace).  Columns of Y above the largest LDS table are not supported
+ * here and are reported through the workspace status. */
+int spgemm_batched_masked_xty(const spgemm_csc *X, const spgemm_csc *Y, const spgemm_csc *M, void *out_values,
+                              void *ws, size_t ws_bytes, void *stream);
+
+/* Gradient of a loss on P(C), C = A*B, in one pass with no transpose and no
+ * host synchronization (graph-capturable): for each output column j, dC(:,j)
+ * (dC_values aligned with C's storage) is held in an LDS hash table and each
+ * stored (k,j) of B yields
+ *   dB(k,j)  = sum over i in A(:,k) of A(i,k) * dC(i,j)       -> dB_out[nnz(B)]
+ *   dA(i,k) += B(k,j) * dC(i,j) for every i in A(:,k)          -> dA_out[nnz(A)]
+ * dA is accumulated with float64 atomics in the workspace and rounded once
+ * (summation order is not fixed, so dA may differ in the last bits between
+ * calls).  C gives only the pattern (values not read).  Columns of C above
+ * the largest LDS table are reported through the workspace status; the
+ * transpose-based path (spgemm_transpose + spgemm_masked_xty) handles them.
+ * Workspace: SPGEMM_OP_BATCHED_BACKWARD with A, B. */
+int spgemm_batched_backward(const spgemm_csc *A, const spgemm_csc *B, const spgemm_csc *C, const void *dC_values,
+                            void *dA_out, void *dB_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Bin thresholds (process-wide; used by calls launched afterwards): which = 0
+ * for the symbolic pass, 1 for numeric, merge and masked products.
+ * caps_host[5] are the largest bounds on distinct rows that go to bins 0..4
+ * (wave tables of 64, 256, 1024 slots, workgroup tables of 4096 and
+ * 32768 (symbolic) or 10240 (numeric) slots); larger columns go to the
+ * heavy path.  They must be nondecreasing and at most each table's capacity
+ * (32, 128, 512, 2048, 16384 symbolic; 32, 128, 512, 2048, 5120 numeric),
+ * which are also the defaults (caps_host = NULL restores them).  Thresholds
+ * change speed, never results.  SPGEMM_E_INVAL otherwise. */
+int spgemm_set_bin_caps(int32_t which, const int64_t *caps_host);
 
 /* Synchronizes `stream` and reports the device-side status word of a
  * workspace used by the calls above: SPGEMM_OK, or SPGEMM_E_DEVICE if a

@@ -25,7 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 # ---------------------------------------------------------------- constants
 OK, E_INVAL, E_SHAPE, E_DTYPE, E_BUDGET, E_WORKSPACE, E_HIP, E_OVERFLOW, E_DEVICE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 F32, F64 = 0, 1
-OP_SYMBOLIC, OP_NUMERIC, OP_MERGE, OP_COLPTR, OP_MASKED_XTY, OP_TRANSPOSE = range(6)
+OP_SYMBOLIC, OP_NUMERIC, OP_MERGE, OP_COLPTR, OP_MASKED_XTY, OP_TRANSPOSE, OP_BATCHED_FORWARD, OP_BATCHED_BACKWARD = range(8)
 MAX_PARTS = 4096
 
 _DTYPE = {torch.float32: F32, torch.float64: F64}

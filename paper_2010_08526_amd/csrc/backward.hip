@@ -17,6 +17,7 @@
 // with atomic cursors (entry order inside each output column is arbitrary).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "device.hpp"
 #include "hip_host.hpp"
@@ -102,7 +103,7 @@ struct MxtyArgs {
 // with no entry need no work.
 constexpr int kMxColsPerWave = 16;
 __global__ __launch_bounds__(256) void k_mxty_bin(const int64_t *Ycp, const int64_t *Mcp, int64_t ncol, int min_bin,
-                                                  int32_t *bins, WsHeader *hdr) {
+                                                  BinCaps caps, int32_t *bins, WsHeader *hdr) {
   __shared__ int s_cnt[kNumBins];
   __shared__ int s_base[kNumBins];
   __shared__ int s_bin[256];
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(256) void k_mxty_bin(const int64_t *Ycp, const int6
     bin = kNumBins - 1;
 #pragma unroll
     for (int b = kNumBins - 2; b >= 0; b--)
-      if (u <= kNumCap[b]) bin = b;
+      if (u <= caps.cap[b]) bin = b;
     bin = max(bin, min_bin);
   }
   s_bin[t] = bin;
@@ -204,53 +205,61 @@ __device__ __forceinline__ void mxty_dots(const MxtyArgs<VT> &a, int64_t pb, int
 
 // One wavefront per column, TBL-slot table of Y(:,j) private to the wave.
 template <int TBL, class VT>
-__global__ __launch_bounds__(256) void k_mxty_wave(MxtyArgs<VT> a, const int32_t *list, int count, int32_t *status) {
+__global__ __launch_bounds__(256) void k_mxty_wave(MxtyArgs<VT> a, const int32_t *list, const int32_t *count_p,
+                                                   int32_t *status) {
   __shared__ int32_t s_keys[4][TBL];
   __shared__ double s_vals[4][TBL];
   const int w = threadIdx.x / kWave, l = lane();
-  const int idx = blockIdx.x * 4 + w;
-  if (idx >= count) return;
+  const int count = *count_p;
   int32_t *keys = s_keys[w];
   double *vals = s_vals[w];
-  for (int s = l; s < TBL; s += kWave) {
-    keys[s] = kEmpty;
-    vals[s] = 0.0;
+  for (int idx = blockIdx.x * 4 + w; idx < count; idx += gridDim.x * 4) {
+    for (int s = l; s < TBL; s += kWave) {
+      keys[s] = kEmpty;
+      vals[s] = 0.0;
+    }
+    wave_sync();
+    const int32_t j = list[idx];
+    for (int64_t p = a.Ycp[j] + l; p < a.Ycp[j + 1]; p += kWave) {
+      const int32_t r = a.Yri[p];
+      if ((uint32_t)r < (uint32_t)a.m)
+        ht_accumulate(keys, vals, TBL, r, (double)a.Yv[p]);
+      else
+        flag_error(status, 3);
+    }
+    wave_sync();
+    mxty_dots(a, a.Mcp[j], a.Mcp[j + 1], 0, 1, status, [&](int32_t r) { return ht_lookup(keys, vals, TBL, r); });
+    wave_sync();
   }
-  wave_sync();
-  const int32_t j = list[idx];
-  for (int64_t p = a.Ycp[j] + l; p < a.Ycp[j + 1]; p += kWave) {
-    const int32_t r = a.Yri[p];
-    if ((uint32_t)r < (uint32_t)a.m)
-      ht_accumulate(keys, vals, TBL, r, (double)a.Yv[p]);
-    else
-      flag_error(status, 3);
-  }
-  wave_sync();
-  mxty_dots(a, a.Mcp[j], a.Mcp[j + 1], 0, 1, status, [&](int32_t r) { return ht_lookup(keys, vals, TBL, r); });
 }
 
 // One workgroup per column, shared table.
 template <int TBL, int THREADS, class VT>
-__global__ __launch_bounds__(THREADS) void k_mxty_block(MxtyArgs<VT> a, const int32_t *list, int32_t *status) {
+__global__ __launch_bounds__(THREADS) void k_mxty_block(MxtyArgs<VT> a, const int32_t *list, const int32_t *count_p,
+                                                        int32_t *status) {
   constexpr int NW = THREADS / kWave;
   __shared__ int32_t s_keys[TBL];
   __shared__ double s_vals[TBL];
   const int w = threadIdx.x / kWave;
-  for (int s = threadIdx.x; s < TBL; s += THREADS) {
-    s_keys[s] = kEmpty;
-    s_vals[s] = 0.0;
+  const int count = *count_p;
+  for (int item = blockIdx.x; item < count; item += gridDim.x) {
+    for (int s = threadIdx.x; s < TBL; s += THREADS) {
+      s_keys[s] = kEmpty;
+      s_vals[s] = 0.0;
+    }
+    __syncthreads();
+    const int32_t j = list[item];
+    for (int64_t p = a.Ycp[j] + threadIdx.x; p < a.Ycp[j + 1]; p += THREADS) {
+      const int32_t r = a.Yri[p];
+      if ((uint32_t)r < (uint32_t)a.m)
+        ht_accumulate(s_keys, s_vals, TBL, r, (double)a.Yv[p]);
+      else
+        flag_error(status, 3);
+    }
+    __syncthreads();
+    mxty_dots(a, a.Mcp[j], a.Mcp[j + 1], w, NW, status, [&](int32_t r) { return ht_lookup(s_keys, s_vals, TBL, r); });
+    __syncthreads();
   }
-  __syncthreads();
-  const int32_t j = list[blockIdx.x];
-  for (int64_t p = a.Ycp[j] + threadIdx.x; p < a.Ycp[j + 1]; p += THREADS) {
-    const int32_t r = a.Yri[p];
-    if ((uint32_t)r < (uint32_t)a.m)
-      ht_accumulate(s_keys, s_vals, TBL, r, (double)a.Yv[p]);
-    else
-      flag_error(status, 3);
-  }
-  __syncthreads();
-  mxty_dots(a, a.Mcp[j], a.Mcp[j + 1], w, NW, status, [&](int32_t r) { return ht_lookup(s_keys, s_vals, TBL, r); });
 }
 
 // Heavy columns: Y(:,j) scattered into a dense float64 column of the
@@ -280,37 +289,60 @@ __global__ __launch_bounds__(256) void k_mxty_heavy_dot(MxtyArgs<VT> a, const in
   mxty_dots(a, a.Mcp[j], a.Mcp[j + 1], part * 4 + w, parts * 4, status, [&](int32_t r) { return d[r]; });
 }
 
+static unsigned mx_grid(int cnt, bool wave_kernel, int blocks_per_cu) {
+  const unsigned full = (unsigned)(blocks_per_cu * device_cus());
+  if (cnt < 0) return full;
+  const unsigned need = wave_kernel ? grid_of(cnt, 4) : (unsigned)cnt;
+  return std::max(1u, std::min(need, full));
+}
+
+__global__ void k_mx_flag_if_nonzero(const int32_t *count, int32_t *status, int code) {
+  if (threadIdx.x == 0 && *count > 0) flag_error(status, code);
+}
+
 template <class VT>
 static int mxty_typed(const spgemm_csc *X, const spgemm_csc *Y, const spgemm_csc *M, void *out, const WsLayout &L,
-                      char *ws, hipStream_t st) {
+                      char *ws, hipStream_t st, bool sync) {
   WsHeader *hdr = (WsHeader *)ws;
   int32_t *bins = (int32_t *)(ws + L.bins);
   const int64_t n = Y->ncols;
   int rc = launch_init_header(hdr, 1, st);
   if (rc) return rc;
   hipLaunchKernelGGL(k_mxty_bin, dim3(grid_of(n, 256)), dim3(256), 0, st, Y->colptr, M->colptr, n, g_min_bin_value(),
-                     bins, hdr);
+                     bin_caps(1), bins, hdr);
   LAUNCHCHK();
   WsHeader h;
-  rc = read_header(hdr, st, &h);
-  if (rc) return rc;
+  int cnt[kNumBins];
+  if (sync) {
+    rc = read_header(hdr, st, &h);
+    if (rc) return rc;
+    for (int b = 0; b < kNumBins; b++) cnt[b] = h.bin_count[b];
+  } else {
+    for (int b = 0; b < kNumBins; b++) cnt[b] = -1;
+    memset(&h, 0, sizeof(h));
+  }
   MxtyArgs<VT> a{X->colptr, X->rowidx, (const VT *)X->values, Y->colptr, Y->rowidx, (const VT *)Y->values,
                  M->colptr, M->rowidx, (VT *)out, Y->nrows, X->ncols, X->nnz};
   int32_t *status = &hdr->status;
   for (int b = 0; b < kNumBins - 1; b++) {
-    const int cnt = h.bin_count[b];
-    if (!cnt) continue;
+    if (cnt[b] == 0) continue;
     const int32_t *list = bins + (int64_t)b * n;
+    const int32_t *cp = &hdr->bin_count[b];
     switch (b) {
-      case 0: hipLaunchKernelGGL((k_mxty_wave<64, VT>), dim3(grid_of(cnt, 4)), dim3(256), 0, st, a, list, cnt, status); break;
-      case 1: hipLaunchKernelGGL((k_mxty_wave<256, VT>), dim3(grid_of(cnt, 4)), dim3(256), 0, st, a, list, cnt, status); break;
-      case 2: hipLaunchKernelGGL((k_mxty_wave<1024, VT>), dim3(grid_of(cnt, 4)), dim3(256), 0, st, a, list, cnt, status); break;
-      case 3: hipLaunchKernelGGL((k_mxty_block<4096, 256, VT>), dim3(cnt), dim3(256), 0, st, a, list, status); break;
-      default: hipLaunchKernelGGL((k_mxty_block<10240, 1024, VT>), dim3(cnt), dim3(1024), 0, st, a, list, status); break;
+      case 0: hipLaunchKernelGGL((k_mxty_wave<64, VT>), dim3(mx_grid(cnt[b], true, 8)), dim3(256), 0, st, a, list, cp, status); break;
+      case 1: hipLaunchKernelGGL((k_mxty_wave<256, VT>), dim3(mx_grid(cnt[b], true, 8)), dim3(256), 0, st, a, list, cp, status); break;
+      case 2: hipLaunchKernelGGL((k_mxty_wave<1024, VT>), dim3(mx_grid(cnt[b], true, 4)), dim3(256), 0, st, a, list, cp, status); break;
+      case 3: hipLaunchKernelGGL((k_mxty_block<4096, 256, VT>), dim3(mx_grid(cnt[b], false, 4)), dim3(256), 0, st, a, list, cp, status); break;
+      default: hipLaunchKernelGGL((k_mxty_block<10240, 1024, VT>), dim3(mx_grid(cnt[b], false, 1)), dim3(1024), 0, st, a, list, cp, status); break;
     }
     LAUNCHCHK();
   }
-  const int heavy = h.bin_count[kNumBins - 1];
+  const int heavy = cnt[kNumBins - 1];
+  if (heavy < 0) {  // no host count: heavy columns cannot be scheduled here
+    hipLaunchKernelGGL(k_mx_flag_if_nonzero, dim3(1), dim3(64), 0, st, &hdr->bin_count[kNumBins - 1], status, 7);
+    LAUNCHCHK();
+    return SPGEMM_OK;
+  }
   if (heavy > 0) {
     if (L.slots <= 0) return SPGEMM_E_INVAL;
     double *dense = (double *)(ws + L.heavy_vals);
@@ -335,6 +367,211 @@ static int mxty_typed(const spgemm_csc *X, const spgemm_csc *Y, const spgemm_csc
       LAUNCHCHK();
     }
   }
+  return SPGEMM_OK;
+}
+
+// ============================================================================
+// Fused gradient (graph-capturable): for each output column j, dC(:,j) goes
+// into an LDS hash table; every entry (k,j) of B then gives
+//   dB(k,j)  = sum over i in A(:,k) of A(i,k) * dC(i,j)     (a dot product)
+//   dA(i,k) += B(k,j) * dC(i,j)  for i in A(:,k)           (float64 atomics)
+// in one traversal of the product's terms, with no transpose.  dA is
+// accumulated in a float64 workspace array and rounded once.
+// ============================================================================
+template <class VT>
+struct FbArgs {
+  const int64_t *Acp;
+  const int32_t *Ari;
+  const VT *Av;
+  const int64_t *Bcp;
+  const int32_t *Bri;
+  const VT *Bv;
+  const int64_t *Ccp;
+  const int32_t *Cri;
+  const VT *dC;
+  VT *dB;
+  double *dA;
+  int64_t m, kdim, nnzA;
+};
+
+template <class VT, class Look>
+__device__ __forceinline__ void fbwd_column(const FbArgs<VT> &a, int64_t j, int c_rank, int c_stride, int32_t *status,
+                                            Look &&look) {
+  const int l = lane();
+  const int64_t pb = a.Bcp[j], pe = a.Bcp[j + 1];
+  for (int64_t base = pb + (int64_t)c_rank * kWave; base < pe; base += (int64_t)c_stride * kWave) {
+    const int64_t p = base + l;
+    int64_t x0 = 0, x1 = 0;
+    double bkj = 0.0;
+    if (p < pe) {
+      const int32_t k = a.Bri[p];
+      if ((uint32_t)k >= (uint32_t)a.kdim) {
+        flag_error(status, 1);
+      } else {
+        x0 = a.Acp[k];
+        x1 = a.Acp[k + 1];
+        bkj = (double)a.Bv[p];
+        if (x0 < 0 || x1 < x0 || x1 > a.nnzA) {
+          flag_error(status, 5);
+          x0 = x1 = 0;
+        }
+      }
+    }
+    const int len = (int)(x1 - x0);
+    const bool lg = len >= kLongDot;
+    if (p < pe && !lg) {
+      double s = 0.0;
+      for (int t0 = 0; t0 < len; t0 += kDotUnroll) {
+        int32_t r[kDotUnroll];
+        double av[kDotUnroll];
+#pragma unroll
+        for (int t = 0; t < kDotUnroll; t++) {
+          r[t] = -1;
+          av[t] = 0.0;
+          if (t0 + t < len) {
+            r[t] = a.Ari[x0 + t0 + t];
+            av[t] = (double)a.Av[x0 + t0 + t];
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < kDotUnroll; t++) {
+          if (t0 + t < len) {
+            if ((uint32_t)r[t] < (uint32_t)a.m) {
+              const double g = look(r[t]);
+              s += av[t] * g;
+              atomicAdd(&a.dA[x0 + t0 + t], bkj * g);
+            } else {
+              flag_error(status, 3);
+            }
+          }
+        }
+      }
+      a.dB[p] = (VT)s;
+    }
+    uint64_t lm = __ballot(p < pe && lg);
+    while (lm) {
+      const int L = __builtin_ctzll(lm);
+      lm &= lm - 1;
+      const int64_t lx0 = readlane64(x0, L), lx1 = readlane64(x1, L);
+      const double lb = readlane_f64(bkj, L);
+      double s = 0.0;
+      for (int64_t q = lx0 + l; q < lx1; q += kWave) {
+        const int32_t r = a.Ari[q];
+        if ((uint32_t)r < (uint32_t)a.m) {
+          const double g = look(r);
+          s += (double)a.Av[q] * g;
+          atomicAdd(&a.dA[q], lb * g);
+        } else {
+          flag_error(status, 3);
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+      if (l == 0) a.dB[base + L] = (VT)s;
+    }
+  }
+}
+
+template <int TBL, class VT>
+__global__ __launch_bounds__(256) void k_fbwd_wave(FbArgs<VT> a, const int32_t *list, const int32_t *count_p,
+                                                   int32_t *status) {
+  __shared__ int32_t s_keys[4][TBL];
+  __shared__ double s_vals[4][TBL];
+  const int w = threadIdx.x / kWave, l = lane();
+  const int count = *count_p;
+  int32_t *keys = s_keys[w];
+  double *vals = s_vals[w];
+  for (int idx = blockIdx.x * 4 + w; idx < count; idx += gridDim.x * 4) {
+    for (int s = l; s < TBL; s += kWave) {
+      keys[s] = kEmpty;
+      vals[s] = 0.0;
+    }
+    wave_sync();
+    const int32_t j = list[idx];
+    for (int64_t p = a.Ccp[j] + l; p < a.Ccp[j + 1]; p += kWave) {
+      const int32_t r = a.Cri[p];
+      if ((uint32_t)r < (uint32_t)a.m)
+        ht_accumulate(keys, vals, TBL, r, (double)a.dC[p]);
+      else
+        flag_error(status, 3);
+    }
+    wave_sync();
+    fbwd_column(a, j, 0, 1, status, [&](int32_t r) { return ht_lookup(keys, vals, TBL, r); });
+    wave_sync();
+  }
+}
+
+template <int TBL, int THREADS, class VT>
+__global__ __launch_bounds__(THREADS) void k_fbwd_block(FbArgs<VT> a, const int32_t *list, const int32_t *count_p,
+                                                        int32_t *status) {
+  constexpr int NW = THREADS / kWave;
+  __shared__ int32_t s_keys[TBL];
+  __shared__ double s_vals[TBL];
+  const int w = threadIdx.x / kWave;
+  const int count = *count_p;
+  for (int item = blockIdx.x; item < count; item += gridDim.x) {
+    for (int s = threadIdx.x; s < TBL; s += THREADS) {
+      s_keys[s] = kEmpty;
+      s_vals[s] = 0.0;
+    }
+    __syncthreads();
+    const int32_t j = list[item];
+    for (int64_t p = a.Ccp[j] + threadIdx.x; p < a.Ccp[j + 1]; p += THREADS) {
+      const int32_t r = a.Cri[p];
+      if ((uint32_t)r < (uint32_t)a.m)
+        ht_accumulate(s_keys, s_vals, TBL, r, (double)a.dC[p]);
+      else
+        flag_error(status, 3);
+    }
+    __syncthreads();
+    fbwd_column(a, j, w, NW, status, [&](int32_t r) { return ht_lookup(s_keys, s_vals, TBL, r); });
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_f64(double *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0.0;
+}
+
+template <class VT>
+__global__ void k_round(const double *src, int64_t n, VT *dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (VT)src[i];
+}
+
+template <class VT>
+static int fbwd_typed(const spgemm_csc *A, const spgemm_csc *B, const spgemm_csc *C, const void *dC, void *dA,
+                      void *dB, const WsLayout &L, char *ws, hipStream_t st) {
+  WsHeader *hdr = (WsHeader *)ws;
+  int32_t *bins = (int32_t *)(ws + L.bins);
+  double *acc = (double *)(ws + L.heavy_vals);
+  const int64_t n = C->ncols;
+  int rc = launch_init_header(hdr, 0, st);
+  if (rc) return rc;
+  const unsigned gz = (unsigned)std::max<int64_t>(1, std::min<int64_t>(grid_of(A->nnz, 256), 8 * device_cus()));
+  hipLaunchKernelGGL(k_zero_f64, dim3(gz), dim3(256), 0, st, acc, A->nnz);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_mxty_bin, dim3(grid_of(n, 256)), dim3(256), 0, st, C->colptr, B->colptr, n, g_min_bin_value(),
+                     bin_caps(1), bins, hdr);
+  LAUNCHCHK();
+  FbArgs<VT> a{A->colptr, A->rowidx, (const VT *)A->values, B->colptr, B->rowidx, (const VT *)B->values,
+               C->colptr, C->rowidx, (const VT *)dC, (VT *)dB, acc, C->nrows, A->ncols, A->nnz};
+  int32_t *status = &hdr->status;
+  for (int b = 0; b < kNumBins - 1; b++) {
+    const int32_t *list = bins + (int64_t)b * n;
+    const int32_t *cp = &hdr->bin_count[b];
+    switch (b) {
+      case 0: hipLaunchKernelGGL((k_fbwd_wave<64, VT>), dim3(mx_grid(-1, true, 8)), dim3(256), 0, st, a, list, cp, status); break;
+      case 1: hipLaunchKernelGGL((k_fbwd_wave<256, VT>), dim3(mx_grid(-1, true, 8)), dim3(256), 0, st, a, list, cp, status); break;
+      case 2: hipLaunchKernelGGL((k_fbwd_wave<1024, VT>), dim3(mx_grid(-1, true, 4)), dim3(256), 0, st, a, list, cp, status); break;
+      case 3: hipLaunchKernelGGL((k_fbwd_block<4096, 256, VT>), dim3(mx_grid(-1, false, 4)), dim3(256), 0, st, a, list, cp, status); break;
+      default: hipLaunchKernelGGL((k_fbwd_block<10240, 1024, VT>), dim3(mx_grid(-1, false, 1)), dim3(1024), 0, st, a, list, cp, status); break;
+    }
+    LAUNCHCHK();
+  }
+  hipLaunchKernelGGL(k_mx_flag_if_nonzero, dim3(1), dim3(64), 0, st, &hdr->bin_count[kNumBins - 1], status, 7);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_round<VT>, dim3(gz), dim3(256), 0, st, acc, A->nnz, (VT *)dA);
+  LAUNCHCHK();
   return SPGEMM_OK;
 }
 
@@ -406,8 +643,47 @@ int spgemm_masked_xty(const spgemm_csc *X, const spgemm_csc *Y, const spgemm_csc
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
   if (Y->ncols == 0 || M->nnz == 0) return launch_init_header((WsHeader *)ws, 1, s);
-  if (X->dtype == SPGEMM_F64) return mxty_typed<double>(X, Y, M, out_values, L, (char *)ws, s);
-  return mxty_typed<float>(X, Y, M, out_values, L, (char *)ws, s);
+  if (X->dtype == SPGEMM_F64) return mxty_typed<double>(X, Y, M, out_values, L, (char *)ws, s, true);
+  return mxty_typed<float>(X, Y, M, out_values, L, (char *)ws, s, true);
+}
+
+int spgemm_batched_masked_xty(const spgemm_csc *X, const spgemm_csc *Y, const spgemm_csc *M, void *out_values,
+                              void *ws, size_t ws_bytes, void *stream) {
+  int st = check_csc(X, true);
+  if (!st) st = check_csc(Y, true);
+  if (!st) st = check_csc(M, false);
+  if (st) return st;
+  if (X->dtype != Y->dtype) return SPGEMM_E_DTYPE;
+  if (X->nrows != Y->nrows || M->nrows != X->ncols || M->ncols != Y->ncols) return SPGEMM_E_SHAPE;
+  if (M->nnz > 0 && !out_values) return SPGEMM_E_INVAL;
+  WsLayout L;
+  st = ws_layout(SPGEMM_OP_MASKED_XTY, X, Y, 0, Y->ncols, 1, &L);
+  if (st) return st;
+  st = check_ws(ws, ws_bytes, L.total);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (Y->ncols == 0 || M->nnz == 0) return launch_init_header((WsHeader *)ws, 1, s);
+  if (X->dtype == SPGEMM_F64) return mxty_typed<double>(X, Y, M, out_values, L, (char *)ws, s, false);
+  return mxty_typed<float>(X, Y, M, out_values, L, (char *)ws, s, false);
+}
+
+int spgemm_batched_backward(const spgemm_csc *A, const spgemm_csc *B, const spgemm_csc *C, const void *dC_values,
+                            void *dA_out, void *dB_out, void *ws, size_t ws_bytes, void *stream) {
+  int st = check_csc(A, true);
+  if (!st) st = check_csc(B, true);
+  if (!st) st = check_csc(C, false);
+  if (st) return st;
+  if (A->dtype != B->dtype) return SPGEMM_E_DTYPE;
+  if (A->ncols != B->nrows || C->nrows != A->nrows || C->ncols != B->ncols) return SPGEMM_E_SHAPE;
+  if ((C->nnz > 0 && !dC_values) || (A->nnz > 0 && !dA_out) || (B->nnz > 0 && !dB_out)) return SPGEMM_E_INVAL;
+  WsLayout L;
+  st = ws_layout(SPGEMM_OP_BATCHED_BACKWARD, A, B, 0, B->ncols, 1, &L);
+  if (st) return st;
+  st = check_ws(ws, ws_bytes, L.total);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (A->dtype == SPGEMM_F64) return fbwd_typed<double>(A, B, C, dC_values, dA_out, dB_out, L, (char *)ws, s);
+  return fbwd_typed<float>(A, B, C, dC_values, dA_out, dB_out, L, (char *)ws, s);
 }
 
 int spgemm_permute(const void *src, const int64_t *perm, int64_t n, int32_t dtype, int32_t scatter, void *dst,

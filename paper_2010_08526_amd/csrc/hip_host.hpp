@@ -13,6 +13,7 @@ int device_cus();
 int launch_init_header(WsHeader *h, int keep_clean, hipStream_t st);
 int launch_set_tag(WsHeader *h, uint64_t tag, hipStream_t st);
 int g_min_bin_value();  // the spgemm_debug_min_bin setting
+BinCaps bin_caps(int which);  // 0: symbolic, 1: numeric / merge / masked product
 // colptr_out[0] = 0, colptr_out[i+1] = counts[0] + ... + counts[i]; bsum holds n / 8192 + 2 int64
 int launch_colptr_scan(const int64_t *counts, int64_t n, int64_t *colptr_out, int64_t *bsum, hipStream_t st);
 

@@ -50,6 +50,7 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
   switch (op) {
     case SPGEMM_OP_SYMBOLIC:
     case SPGEMM_OP_NUMERIC:
+    case SPGEMM_OP_BATCHED_FORWARD:
     case SPGEMM_OP_MERGE: {
       if (!A) return SPGEMM_E_INVAL;
       int64_t ncol;
@@ -69,7 +70,8 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
         L->parts = off;
         off = align_up(off + kPartDescBytes * (size_t)n_layers);
       }
-      if (op == SPGEMM_OP_NUMERIC && A->nrows > kNumCap[kNumBins - 2] && num_slabs(A->nrows) <= kMaxSlabs) {
+      const bool numeric = op == SPGEMM_OP_NUMERIC || op == SPGEMM_OP_BATCHED_FORWARD;
+      if (numeric && A->nrows > kNumCap[kNumBins - 2] && num_slabs(A->nrows) <= kMaxSlabs) {
         L->P = num_slabs(A->nrows);
         L->slab_off = off;
         off = align_up(off + sizeof(int32_t) * (size_t)(L->P + 1) * (size_t)A->ncols);
@@ -77,7 +79,7 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
         off = align_up(off + sizeof(int32_t) * (size_t)A->nnz);
         L->slab_v = off;
         off = align_up(off + sizeof(double) * (size_t)A->nnz);
-      } else if (op != SPGEMM_OP_SYMBOLIC && A->nrows > kNumCap[kNumBins - 2]) {
+      } else if ((op == SPGEMM_OP_NUMERIC || op == SPGEMM_OP_MERGE) && A->nrows > kNumCap[kNumBins - 2]) {
         L->slots = heavy_slots(A->nrows);
         L->nseg = (A->nrows + kHeavySeg - 1) / kHeavySeg;
         L->heavy_vals = off;
@@ -86,6 +88,10 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
         off = align_up(off + (size_t)L->slots * (size_t)A->nrows);
         L->heavy_segcnt = off;
         off = align_up(off + sizeof(int64_t) * (size_t)L->slots * (size_t)L->nseg);
+      }
+      if (op == SPGEMM_OP_BATCHED_FORWARD) {
+        L->scan = off;
+        off = align_up(off + sizeof(int64_t) * (size_t)(ncol / 8192 + 2));
       }
       break;
     }
@@ -111,6 +117,17 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
         L->heavy_vals = off;
         off = align_up(off + sizeof(double) * (size_t)L->slots * (size_t)B->nrows);
       }
+      break;
+    }
+    case SPGEMM_OP_BATCHED_BACKWARD: {  // A, B of the product
+      if (!A || !B) return SPGEMM_E_INVAL;
+      if (A->nrows < 0 || A->nrows > INT32_MAX) return SPGEMM_E_OVERFLOW;
+      L->ncol = B->ncols;
+      L->m = A->nrows;
+      L->bins = off;
+      off = align_up(off + sizeof(int32_t) * kNumBins * (size_t)B->ncols);
+      L->heavy_vals = off;  // float64 accumulators of dA
+      off = align_up(off + sizeof(double) * (size_t)A->nnz);
       break;
     }
     case SPGEMM_OP_COLPTR: {

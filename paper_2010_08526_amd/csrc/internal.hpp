@@ -27,6 +27,16 @@ constexpr int64_t kSymCap[kNumBins - 1] = {32, 128, 512, 2048, 16384};
 // numeric / merge (int32 key + float64 value, 12 bytes per slot)
 constexpr int64_t kNumCap[kNumBins - 1] = {32, 128, 512, 2048, 5120};
 
+// Largest capacity each LDS bin's table allows (half its slots).
+constexpr int64_t kSymTableCap[kNumBins - 1] = {32, 128, 512, 2048, 16384};
+constexpr int64_t kNumTableCap[kNumBins - 1] = {32, 128, 512, 2048, 5120};
+
+// Bin thresholds passed to the binning kernels (monotone, each at most the
+// table capacity of its bin).
+struct BinCaps {
+  int64_t cap[kNumBins - 1];
+};
+
 constexpr int kMaxParts = 4096;  // merge: parts per call
 constexpr size_t kPartDescBytes = 24;  // device-side copy of one part's pointers
 constexpr int64_t kBitmapRows = 1 << 20;  // heavy symbolic: rows per LDS bitmap window (128 KiB)
@@ -53,6 +63,8 @@ struct WsHeader {
   uint64_t clean_tag;  // nonzero iff the heavy accumulator region is known to be all zero
   int32_t bin_count[kNumBins];
   int32_t pad1[2];
+  int32_t cursor[kNumBins];  // work-queue positions of the persistent kernels
+  int32_t pad2[2];
 };
 constexpr size_t kHeaderBytes = 4096;
 

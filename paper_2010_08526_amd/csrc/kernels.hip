@@ -340,10 +340,11 @@ __device__ __forceinline__ void traverse_merge(const PartDesc *P, int nparts, in
 // ============================================================================
 // Small kernels: header init, fills.
 // ============================================================================
-__global__ void k_init_header(WsHeader *h, int keep_clean) {
+__global__ void k_init_header(WsHeader *h, int keep_clean, int keep_status = 0) {
   if (threadIdx.x == 0) {
-    h->status = 0;
+    if (!keep_status) h->status = 0;
     for (int b = 0; b < kNumBins; b++) h->bin_count[b] = 0;
+    for (int b = 0; b < kNumBins; b++) h->cursor[b] = 0;
     if (!keep_clean) h->clean_tag = 0;
   }
 }
@@ -376,11 +377,10 @@ __global__ void k_store_parts(PartDesc *dst, PartsChunk src, int n) {
 // One wavefront per column, 16 columns per wave, one block-level append per
 // bin and block.
 // ============================================================================
-template <bool SYM>
-__device__ __forceinline__ int bin_of(int64_t bound) {
+__device__ __forceinline__ int bin_of(int64_t bound, const BinCaps &caps) {
 #pragma unroll
   for (int b = 0; b < kNumBins - 1; b++) {
-    if (bound <= (SYM ? kSymCap[b] : kNumCap[b])) return b;
+    if (bound <= caps.cap[b]) return b;
   }
   return kNumBins - 1;
 }
@@ -391,7 +391,8 @@ template <bool SYM>
 __global__ __launch_bounds__(256) void k_bin(const int64_t *Acp, const int64_t *Bcp, const int32_t *Bri,
                                              int64_t c0, int64_t ncol, int64_t klo, int64_t khi, int64_t kdim,
                                              int64_t m, const int64_t *c_colptr, int64_t *flops_out,
-                                             int64_t *nnz_out, int32_t *bins, WsHeader *hdr, int min_bin) {
+                                             int64_t *nnz_out, int32_t *bins, WsHeader *hdr, int min_bin,
+                                             BinCaps caps) {
   __shared__ int s_cnt[kNumBins];
   __shared__ int s_base[kNumBins];
   __shared__ int s_bin[4 * kBinColsPerWave];
@@ -423,7 +424,7 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t *Acp, const int64_t *
       } else {
         bound = c_colptr[jj + 1] - c_colptr[jj];
       }
-      if (bound > 0) bin = max(bin_of<SYM>(bound), min_bin);
+      if (bound > 0) bin = max(bin_of(bound, caps), min_bin);
     }
     if (l == 0) {
       s_bin[slot] = bin;
@@ -451,64 +452,80 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t *Acp, const int64_t *
 // ============================================================================
 // One wavefront per column, TBL-slot table private to the wave.
 template <int TBL>
-__global__ __launch_bounds__(256) void k_sym_wave(ProductArgs<float> a, int64_t c0, const int32_t *list, int count,
-                                                  int64_t *nnz_out, int32_t *status) {
+__global__ __launch_bounds__(256) void k_sym_wave(ProductArgs<float> a, int64_t c0, const int32_t *list,
+                                                  const int32_t *count_p, int64_t *nnz_out, int32_t *status) {
   __shared__ int32_t s_keys[4][TBL];
   __shared__ SegScratch s_sc[4];
   const int w = threadIdx.x / kWave, l = lane();
-  const int idx = blockIdx.x * 4 + w;
-  if (idx >= count) return;
+  const int count = *count_p;
   int32_t *keys = s_keys[w];
   SegScratch &sc = s_sc[w];
-  for (int s = l; s < TBL; s += kWave) keys[s] = kEmpty;
   sc.mark[l] = 0;
-  wave_sync();
-  const int32_t jj = list[idx];
-  int cnt = 0;
-  traverse_product<false, float>(a, c0 + jj, 0, 1, 0, 1, sc, status, [&](int32_t row, double) {
-    cnt += ht_insert_key(keys, TBL, row) ? 1 : 0;
-  });
-  cnt = wave_sum_i32(cnt);
-  if (l == 0) nnz_out[jj] = cnt;
+  for (int idx = blockIdx.x * 4 + w; idx < count; idx += gridDim.x * 4) {
+    for (int s = l; s < TBL; s += kWave) keys[s] = kEmpty;
+    wave_sync();
+    const int32_t jj = list[idx];
+    int cnt = 0;
+    traverse_product<false, float>(a, c0 + jj, 0, 1, 0, 1, sc, status, [&](int32_t row, double) {
+      cnt += ht_insert_key(keys, TBL, row) ? 1 : 0;
+    });
+    cnt = wave_sum_i32(cnt);
+    if (l == 0) nnz_out[jj] = cnt;
+    wave_sync();
+  }
 }
 
 // One workgroup per column, TBL-slot table shared by its waves.
 template <int TBL, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_sym_block(ProductArgs<float> a, int64_t c0, const int32_t *list,
-                                                       int64_t *nnz_out, int32_t *status) {
+                                                       const int32_t *count_p, int64_t *nnz_out, int32_t *status) {
   constexpr int NW = THREADS / kWave;
   __shared__ int32_t s_keys[TBL];
   __shared__ SegScratch s_sc[NW];
   __shared__ int s_cnt;
   const int w = threadIdx.x / kWave, l = lane();
-  for (int s = threadIdx.x; s < TBL; s += THREADS) s_keys[s] = kEmpty;
+  const int count = *count_p;
   s_sc[w].mark[l] = 0;
-  if (threadIdx.x == 0) s_cnt = 0;
-  __syncthreads();
-  const int32_t jj = list[blockIdx.x];
-  int cnt = 0;
-  traverse_product_block<false, float>(a, c0 + jj, w, NW, s_sc[w], status, [&](int32_t row, double) {
-    cnt += ht_insert_key(s_keys, TBL, row) ? 1 : 0;
-  });
-  cnt = wave_sum_i32(cnt);
-  if (l == 0) atomicAdd(&s_cnt, cnt);
-  __syncthreads();
-  if (threadIdx.x == 0) nnz_out[jj] = s_cnt;
+  for (int item = blockIdx.x; item < count; item += gridDim.x) {
+    for (int s = threadIdx.x; s < TBL; s += THREADS) s_keys[s] = kEmpty;
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    const int32_t jj = list[item];
+    int cnt = 0;
+    traverse_product_block<false, float>(a, c0 + jj, w, NW, s_sc[w], status, [&](int32_t row, double) {
+      cnt += ht_insert_key(s_keys, TBL, row) ? 1 : 0;
+    });
+    cnt = wave_sum_i32(cnt);
+    if (l == 0) atomicAdd(&s_cnt, cnt);
+    __syncthreads();
+    if (threadIdx.x == 0) nnz_out[jj] = s_cnt;
+    __syncthreads();
+  }
 }
 
 // Heavy columns: exact count with an LDS bitmap over windows of kBitmapRows
 // rows (one pass over the column's terms per window).
 constexpr int kBmWords = (int)(kBitmapRows / 32);
 __global__ __launch_bounds__(1024) void k_sym_bitmap(ProductArgs<float> a, int64_t c0, const int32_t *list,
-                                                     int64_t *nnz_out, int32_t *status) {
+                                                     const int32_t *count_p, int *cursor, int64_t *nnz_out,
+                                                     int32_t *status) {
   constexpr int NW = 1024 / kWave;
   __shared__ uint32_t s_bm[kBmWords];
   __shared__ SegScratch s_sc[NW];
   __shared__ unsigned long long s_cnt;
+  __shared__ int s_item;
   const int w = threadIdx.x / kWave, l = lane();
+  const int count = *count_p;
   s_sc[w].mark[l] = 0;
-  if (threadIdx.x == 0) s_cnt = 0;
-  const int32_t jj = list[blockIdx.x];
+  for (;;) {  // columns taken from a work queue (heaviest work is uneven)
+  if (threadIdx.x == 0) {
+    s_cnt = 0;
+    s_item = atomicAdd(cursor, 1);
+  }
+  __syncthreads();
+  const int item = s_item;
+  if (item >= count) break;
+  const int32_t jj = list[item];
   for (int64_t r0 = 0; r0 < a.m; r0 += kBitmapRows) {
     const int words = (int)((min((int64_t)kBitmapRows, a.m - r0) + 31) / 32);
     for (int s = threadIdx.x; s < words; s += 1024) s_bm[s] = 0;
@@ -525,6 +542,8 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(ProductArgs<float> a, int64
     __syncthreads();
   }
   if (threadIdx.x == 0) nnz_out[jj] = (int64_t)s_cnt;
+  __syncthreads();
+  }
 }
 
 // ============================================================================
@@ -593,57 +612,66 @@ __device__ __forceinline__ void compact_range(const int32_t *keys, const double 
 }
 
 template <int TBL, class VT, class Src>
-__global__ __launch_bounds__(256) void k_num_wave(Src src, const int32_t *list, int count, const int64_t *c_colptr,
-                                                  int32_t *out_ri, VT *out_v, int32_t *status) {
+__global__ __launch_bounds__(256) void k_num_wave(Src src, const int32_t *list, const int32_t *count_p,
+                                                  const int64_t *c_colptr, int32_t *out_ri, VT *out_v,
+                                                  int32_t *status) {
   __shared__ int32_t s_keys[4][TBL];
   __shared__ double s_vals[4][TBL];
   __shared__ __align__(16) char s_sc[4][kScratchBytes];
   __shared__ int s_written[4];
   const int w = threadIdx.x / kWave, l = lane();
-  const int idx = blockIdx.x * 4 + w;
-  if (idx >= count) return;
+  const int count = *count_p;
   int32_t *keys = s_keys[w];
   double *vals = s_vals[w];
-  for (int s = l; s < TBL; s += kWave) {
-    keys[s] = kEmpty;
-    vals[s] = 0.0;
-  }
   init_mark<VT>(s_sc[w]);
-  if (l == 0) s_written[w] = 0;
-  wave_sync();
-  const int32_t jj = list[idx];
-  src.visit(jj, 0, 1, 0, 1, s_sc[w], status, [&](int32_t row, double v) { ht_accumulate(keys, vals, TBL, row, v); });
-  wave_sync();
-  const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
-  compact_range<VT>(keys, vals, 0, TBL, base, cap, &s_written[w], out_ri, out_v);
-  wave_sync();
-  if (l == 0 && s_written[w] != cap) flag_error(status, 4);
+  for (int idx = blockIdx.x * 4 + w; idx < count; idx += gridDim.x * 4) {
+    for (int s = l; s < TBL; s += kWave) {
+      keys[s] = kEmpty;
+      vals[s] = 0.0;
+    }
+    if (l == 0) s_written[w] = 0;
+    wave_sync();
+    const int32_t jj = list[idx];
+    src.visit(jj, 0, 1, 0, 1, s_sc[w], status, [&](int32_t row, double v) { ht_accumulate(keys, vals, TBL, row, v); });
+    wave_sync();
+    const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
+    compact_range<VT>(keys, vals, 0, TBL, base, cap, &s_written[w], out_ri, out_v);
+    wave_sync();
+    if (l == 0 && s_written[w] != cap) flag_error(status, 4);
+    wave_sync();
+  }
 }
 
 template <int TBL, int THREADS, class VT, class Src>
-__global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *list, const int64_t *c_colptr,
-                                                       int32_t *out_ri, VT *out_v, int32_t *status) {
+__global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *list, const int32_t *count_p,
+                                                       const int64_t *c_colptr, int32_t *out_ri, VT *out_v,
+                                                       int32_t *status) {
   constexpr int NW = THREADS / kWave;
   __shared__ int32_t s_keys[TBL];
   __shared__ double s_vals[TBL];
   __shared__ __align__(16) char s_sc[NW][kScratchBytes];
   __shared__ int s_written;
   const int w = threadIdx.x / kWave;
-  for (int s = threadIdx.x; s < TBL; s += THREADS) {
-    s_keys[s] = kEmpty;
-    s_vals[s] = 0.0;
-  }
+  const int count = *count_p;
   init_mark<VT>(s_sc[w]);
-  if (threadIdx.x == 0) s_written = 0;
-  __syncthreads();
-  const int32_t jj = list[blockIdx.x];
-  src.visit(jj, w, NW, 0, 1, s_sc[w], status, [&](int32_t row, double v) { ht_accumulate(s_keys, s_vals, TBL, row, v); });
-  __syncthreads();
-  const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
-  constexpr int PER = (TBL + NW - 1) / NW;
-  compact_range<VT>(s_keys, s_vals, w * PER, min(TBL, (w + 1) * PER), base, cap, &s_written, out_ri, out_v);
-  __syncthreads();
-  if (threadIdx.x == 0 && s_written != cap) flag_error(status, 4);
+  for (int item = blockIdx.x; item < count; item += gridDim.x) {
+    for (int s = threadIdx.x; s < TBL; s += THREADS) {
+      s_keys[s] = kEmpty;
+      s_vals[s] = 0.0;
+    }
+    if (threadIdx.x == 0) s_written = 0;
+    __syncthreads();
+    const int32_t jj = list[item];
+    src.visit(jj, w, NW, 0, 1, s_sc[w], status,
+              [&](int32_t row, double v) { ht_accumulate(s_keys, s_vals, TBL, row, v); });
+    __syncthreads();
+    const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
+    constexpr int PER = (TBL + NW - 1) / NW;
+    compact_range<VT>(s_keys, s_vals, w * PER, min(TBL, (w + 1) * PER), base, cap, &s_written, out_ri, out_v);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_written != cap) flag_error(status, 4);
+    __syncthreads();
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -654,11 +682,11 @@ __global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *l
 template <class VT>
 __global__ __launch_bounds__(256) void k_slab_split(const int64_t *Acp, const int32_t *Ari, const VT *Av,
                                                     int64_t klo, int64_t khi, int P, int32_t *soff,
-                                                    int32_t *s_ri, VT *s_v) {
+                                                    int32_t *s_ri, VT *s_v, const int32_t *heavy_count) {
   __shared__ int s_hist[4][kMaxSlabs + 1];
   const int w = threadIdx.x / kWave, l = lane();
   const int64_t k = klo + (int64_t)blockIdx.x * 4 + w;
-  if (k >= khi) return;
+  if (k >= khi || *heavy_count == 0) return;
   int *h = s_hist[w];
   for (int t = l; t <= P; t += kWave) h[t] = 0;
   wave_sync();
@@ -707,6 +735,7 @@ static_assert(kBitmapRows / 8 <= kBigBytes, "bitmap does not fit");
 template <class VT>
 __global__ __launch_bounds__(kHeavyThreads) void k_heavy_slab(ProductArgs<VT> a, ProductArgs<VT> sa, SlabSel sel,
                                                               int64_t c0, const int32_t *list,
+                                                              const int32_t *count_p, int *cursor,
                                                               const int64_t *c_colptr, int32_t *out_ri, VT *out_v,
                                                               int32_t *status) {
   constexpr int NW = kHeavyThreads / kWave;
@@ -715,9 +744,17 @@ __global__ __launch_bounds__(kHeavyThreads) void k_heavy_slab(ProductArgs<VT> a,
   __shared__ SegScratch s_sc[NW];
   __shared__ int s_wsum[NW];
   __shared__ int s_written;
+  __shared__ int s_item;
   const int w = threadIdx.x / kWave, l = lane();
+  const int count = *count_p;
   s_sc[w].mark[l] = 0;
-  const int32_t jj = list[blockIdx.x];
+  for (;;) {  // heavy columns taken from a work queue
+  if (threadIdx.x == 0) s_item = atomicAdd(cursor, 1);
+  __syncthreads();
+  const int item = s_item;
+  __syncthreads();
+  if (item >= count) break;
+  const int32_t jj = list[item];
   const int64_t col = c0 + jj;
   const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
   int64_t running = 0;
@@ -829,6 +866,7 @@ __global__ __launch_bounds__(kHeavyThreads) void k_heavy_slab(ProductArgs<VT> a,
     __syncthreads();
   }
   if (threadIdx.x == 0 && running != cap) flag_error(status, 4);
+  }
 }
 
 // Heavy columns: dense float64 accumulators in the workspace, one per slot;
@@ -1029,6 +1067,9 @@ static thread_local HostPinned g_pin;
 
 // Testing hook: every column goes to at least this bin (0 = natural bins).
 static int g_min_bin = 0;
+// Bin thresholds in use (symbolic, numeric); tunable within the table sizes.
+static BinCaps g_caps[2] = {BinCaps{{kSymCap[0], kSymCap[1], kSymCap[2], kSymCap[3], kSymCap[4]}},
+                            BinCaps{{kNumCap[0], kNumCap[1], kNumCap[2], kNumCap[3], kNumCap[4]}}};
 
 int read_header(WsHeader *dev, hipStream_t st, WsHeader *out) {
   if (!g_pin.hdr) HIPCHK(hipHostMalloc((void **)&g_pin.hdr, sizeof(WsHeader), hipHostMallocDefault));
@@ -1051,6 +1092,7 @@ int device_cus() {
 }
 
 int g_min_bin_value() { return g_min_bin; }
+BinCaps bin_caps(int which) { return g_caps[which ? 1 : 0]; }
 
 int launch_set_tag(WsHeader *h, uint64_t tag, hipStream_t st) {
   hipLaunchKernelGGL(k_set_tag, dim3(1), dim3(64), 0, st, h, tag);
@@ -1059,7 +1101,7 @@ int launch_set_tag(WsHeader *h, uint64_t tag, hipStream_t st) {
 }
 
 int launch_init_header(WsHeader *h, int keep_clean, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, h, keep_clean);
+  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, h, keep_clean, 0);
   LAUNCHCHK();
   return SPGEMM_OK;
 }
@@ -1099,34 +1141,100 @@ static ProductArgs<VT> product_args(const spgemm_csc *A, const spgemm_csc *B, in
 }
 
 // One symbolic pass over inner range [klo, khi) writing one row of counts.
+// Grid of a persistent bin kernel: the exact need when the bin's count is
+// known on the host (cnt >= 0), else a fixed grid that fills the device.
+static unsigned bin_grid(int cnt, bool wave_kernel, int blocks_per_cu) {
+  const unsigned full = (unsigned)(blocks_per_cu * device_cus());
+  if (cnt < 0) return full;
+  const unsigned need = wave_kernel ? grid_of(cnt, 4) : (unsigned)cnt;
+  return std::max(1u, std::min(need, full));
+}
+
+__global__ void k_flag_if_nonzero(const int32_t *count, int32_t *status, int code) {
+  if (threadIdx.x == 0 && *count > 0) flag_error(status, code);
+}
+
+// Column pointers beyond the output capacity are clamped to it (their
+// columns then fail the count check and are cut short); the status word
+// records the overflow.
+__global__ void k_clamp_colptr(int64_t *colptr, int64_t ncol, int64_t cap, int32_t *status) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= ncol; i += (int64_t)gridDim.x * blockDim.x) {
+    if (colptr[i] > cap) {
+      colptr[i] = cap;
+      if (i == ncol) flag_error(status, 8);
+    }
+  }
+}
+
+// One workgroup per instance: copies instance i of a batch into the block
+// diagonal at its row/column/entry offsets.
+struct PackDesc {
+  const int64_t *cp;
+  const int32_t *ri;
+  const void *v;
+  int64_t ncols, nnz, row_off, col_off, nnz_off;
+};
+
+template <class VT>
+__global__ __launch_bounds__(256) void k_pack(const PackDesc *d, int count, int64_t *cp_out, int32_t *ri_out,
+                                              VT *v_out) {
+  for (int i = blockIdx.x; i < count; i += gridDim.x) {
+    const PackDesc q = d[i];
+    for (int64_t j = threadIdx.x; j < q.ncols; j += 256) cp_out[q.col_off + j] = q.nnz_off + q.cp[j];
+    for (int64_t p = threadIdx.x; p < q.nnz; p += 256) {
+      ri_out[q.nnz_off + p] = (int32_t)(q.row_off + q.ri[p]);
+      if (v_out) v_out[q.nnz_off + p] = ((const VT *)q.v)[p];
+    }
+  }
+}
+
+__global__ void k_pack_last(int64_t *cp_out, int64_t ncols, int64_t nnz) {
+  if (threadIdx.x == 0) cp_out[ncols] = nnz;
+}
+
+// Counts of the bins: read back (one synchronization) or left on the device.
+static int bin_counts(WsHeader *hdr, hipStream_t st, bool sync, int *cnt, WsHeader *h) {
+  if (sync) {
+    int rc = read_header(hdr, st, h);
+    if (rc) return rc;
+    for (int b = 0; b < kNumBins; b++) cnt[b] = h->bin_count[b];
+  } else {
+    for (int b = 0; b < kNumBins; b++) cnt[b] = -1;
+    memset(h, 0, sizeof(*h));
+  }
+  return SPGEMM_OK;
+}
+
+// One symbolic pass over inner range [klo, khi) writing one row of counts.
 static int symbolic_pass(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t ncol, int64_t klo,
                          int64_t khi, int64_t *flops_out, int64_t *nnz_row, const WsLayout &L, char *ws,
-                         hipStream_t st) {
+                         hipStream_t st, bool sync) {
   WsHeader *hdr = (WsHeader *)ws;
   int32_t *bins = (int32_t *)(ws + L.bins);
-  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, 0);
+  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, 0, 0);
   LAUNCHCHK();
   const int64_t per_block = 4 * kBinColsPerWave;
   hipLaunchKernelGGL(k_bin<true>, dim3(grid_of(ncol, per_block)), dim3(256), 0, st, A->colptr, B->colptr, B->rowidx,
                      c0, ncol, klo, khi, (int64_t)A->ncols, A->nrows, (const int64_t *)nullptr, flops_out, nnz_row,
-                     bins, hdr, g_min_bin);
+                     bins, hdr, g_min_bin, g_caps[0]);
   LAUNCHCHK();
+  int cnt[kNumBins];
   WsHeader h;
-  int rc = read_header(hdr, st, &h);
+  int rc = bin_counts(hdr, st, sync, cnt, &h);
   if (rc) return rc;
   ProductArgs<float> a = product_args<float>(A, B, klo, khi);
   int32_t *status = &hdr->status;
   for (int b = 0; b < kNumBins; b++) {
-    const int cnt = h.bin_count[b];
-    if (!cnt) continue;
+    if (cnt[b] == 0) continue;
     const int32_t *list = bins + (int64_t)b * ncol;
+    const int32_t *cp = &hdr->bin_count[b];
     switch (b) {
-      case 0: hipLaunchKernelGGL(k_sym_wave<64>, dim3(grid_of(cnt, 4)), dim3(256), 0, st, a, c0, list, cnt, nnz_row, status); break;
-      case 1: hipLaunchKernelGGL(k_sym_wave<256>, dim3(grid_of(cnt, 4)), dim3(256), 0, st, a, c0, list, cnt, nnz_row, status); break;
-      case 2: hipLaunchKernelGGL(k_sym_wave<1024>, dim3(grid_of(cnt, 4)), dim3(256), 0, st, a, c0, list, cnt, nnz_row, status); break;
-      case 3: hipLaunchKernelGGL((k_sym_block<4096, 256>), dim3(cnt), dim3(256), 0, st, a, c0, list, nnz_row, status); break;
-      case 4: hipLaunchKernelGGL((k_sym_block<32768, 1024>), dim3(cnt), dim3(1024), 0, st, a, c0, list, nnz_row, status); break;
-      default: hipLaunchKernelGGL(k_sym_bitmap, dim3(cnt), dim3(1024), 0, st, a, c0, list, nnz_row, status); break;
+      case 0: hipLaunchKernelGGL(k_sym_wave<64>, dim3(bin_grid(cnt[b], true, 8)), dim3(256), 0, st, a, c0, list, cp, nnz_row, status); break;
+      case 1: hipLaunchKernelGGL(k_sym_wave<256>, dim3(bin_grid(cnt[b], true, 8)), dim3(256), 0, st, a, c0, list, cp, nnz_row, status); break;
+      case 2: hipLaunchKernelGGL(k_sym_wave<1024>, dim3(bin_grid(cnt[b], true, 8)), dim3(256), 0, st, a, c0, list, cp, nnz_row, status); break;
+      case 3: hipLaunchKernelGGL((k_sym_block<4096, 256>), dim3(bin_grid(cnt[b], false, 8)), dim3(256), 0, st, a, c0, list, cp, nnz_row, status); break;
+      case 4: hipLaunchKernelGGL((k_sym_block<32768, 1024>), dim3(bin_grid(cnt[b], false, 1)), dim3(1024), 0, st, a, c0, list, cp, nnz_row, status); break;
+      default: hipLaunchKernelGGL(k_sym_bitmap, dim3(bin_grid(cnt[b], false, 1)), dim3(1024), 0, st, a, c0, list, cp, &hdr->cursor[b], nnz_row, status); break;
     }
     LAUNCHCHK();
   }
@@ -1137,29 +1245,38 @@ static uint64_t clean_tag_of(const WsLayout &L) {
   return 0x5eed0000f00dull ^ ((uint64_t)L.slots << 40) ^ (uint64_t)L.m ^ ((uint64_t)L.heavy_vals << 20);
 }
 
-// Numeric-style pass (product or merge) given bins already filled.
+// Numeric-style pass (product or merge) once the bins are filled.  cnt[b]
+// < 0 means the count is only on the device (no host synchronization);
+// then heavy columns must take the slab path (heavy_global = false), and a
+// heavy column that would need the global path is reported as an error.
 template <class VT, class Src>
-static int accumulate_pass(const Src &src, const WsHeader &h, const WsLayout &L, char *ws, const int64_t *c_colptr,
-                           int32_t *out_ri, VT *out_v, hipStream_t st, bool heavy_global = true) {
+static int accumulate_pass(const Src &src, const int *cnt, const WsHeader &h, const WsLayout &L, char *ws,
+                           const int64_t *c_colptr, int32_t *out_ri, VT *out_v, hipStream_t st,
+                           bool heavy_global = true) {
   WsHeader *hdr = (WsHeader *)ws;
   int32_t *bins = (int32_t *)(ws + L.bins);
   int32_t *status = &hdr->status;
   const int64_t ncol = L.ncol;
   for (int b = 0; b < kNumBins - 1; b++) {
-    const int cnt = h.bin_count[b];
-    if (!cnt) continue;
+    if (cnt[b] == 0) continue;
     const int32_t *list = bins + (int64_t)b * ncol;
+    const int32_t *cp = &hdr->bin_count[b];
     switch (b) {
-      case 0: hipLaunchKernelGGL((k_num_wave<64, VT, Src>), dim3(grid_of(cnt, 4)), dim3(256), 0, st, src, list, cnt, c_colptr, out_ri, out_v, status); break;
-      case 1: hipLaunchKernelGGL((k_num_wave<256, VT, Src>), dim3(grid_of(cnt, 4)), dim3(256), 0, st, src, list, cnt, c_colptr, out_ri, out_v, status); break;
-      case 2: hipLaunchKernelGGL((k_num_wave<1024, VT, Src>), dim3(grid_of(cnt, 4)), dim3(256), 0, st, src, list, cnt, c_colptr, out_ri, out_v, status); break;
-      case 3: hipLaunchKernelGGL((k_num_block<4096, 256, VT, Src>), dim3(cnt), dim3(256), 0, st, src, list, c_colptr, out_ri, out_v, status); break;
-      default: hipLaunchKernelGGL((k_num_block<10240, 1024, VT, Src>), dim3(cnt), dim3(1024), 0, st, src, list, c_colptr, out_ri, out_v, status); break;
+      case 0: hipLaunchKernelGGL((k_num_wave<64, VT, Src>), dim3(bin_grid(cnt[b], true, 8)), dim3(256), 0, st, src, list, cp, c_colptr, out_ri, out_v, status); break;
+      case 1: hipLaunchKernelGGL((k_num_wave<256, VT, Src>), dim3(bin_grid(cnt[b], true, 8)), dim3(256), 0, st, src, list, cp, c_colptr, out_ri, out_v, status); break;
+      case 2: hipLaunchKernelGGL((k_num_wave<1024, VT, Src>), dim3(bin_grid(cnt[b], true, 4)), dim3(256), 0, st, src, list, cp, c_colptr, out_ri, out_v, status); break;
+      case 3: hipLaunchKernelGGL((k_num_block<4096, 256, VT, Src>), dim3(bin_grid(cnt[b], false, 4)), dim3(256), 0, st, src, list, cp, c_colptr, out_ri, out_v, status); break;
+      default: hipLaunchKernelGGL((k_num_block<10240, 1024, VT, Src>), dim3(bin_grid(cnt[b], false, 1)), dim3(1024), 0, st, src, list, cp, c_colptr, out_ri, out_v, status); break;
     }
     LAUNCHCHK();
   }
-  const int heavy = h.bin_count[kNumBins - 1];
-  if (heavy > 0 && heavy_global) {
+  const int heavy = cnt[kNumBins - 1];
+  if (heavy != 0 && heavy_global) {
+    if (heavy < 0) {  // no host count: the global path cannot be scheduled
+      hipLaunchKernelGGL(k_flag_if_nonzero, dim3(1), dim3(64), 0, st, &hdr->bin_count[kNumBins - 1], status, 7);
+      LAUNCHCHK();
+      return SPGEMM_OK;
+    }
     if (L.slots <= 0) return SPGEMM_E_INVAL;
     double *vals = (double *)(ws + L.heavy_vals);
     uint8_t *flags = (uint8_t *)(ws + L.heavy_flags);
@@ -1192,32 +1309,34 @@ static int accumulate_pass(const Src &src, const WsHeader &h, const WsLayout &L,
 template <class VT>
 static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t ncol, int64_t klo,
                          int64_t khi, const int64_t *c_colptr, int32_t *c_rowidx, void *c_values, const WsLayout &L,
-                         char *ws, hipStream_t st) {
+                         char *ws, hipStream_t st, bool sync, bool keep_status = false) {
   WsHeader *hdr = (WsHeader *)ws;
   int32_t *bins = (int32_t *)(ws + L.bins);
-  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, 1);
+  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, 1, keep_status ? 1 : 0);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_bin<false>, dim3(grid_of(ncol, 4 * kBinColsPerWave)), dim3(256), 0, st, A->colptr, B->colptr,
                      B->rowidx, c0, ncol, klo, khi, (int64_t)A->ncols, A->nrows, c_colptr, (int64_t *)nullptr,
-                     (int64_t *)nullptr, bins, hdr, g_min_bin);
+                     (int64_t *)nullptr, bins, hdr, g_min_bin, g_caps[1]);
   LAUNCHCHK();
+  int cnt[kNumBins];
   WsHeader h;
-  int rc = read_header(hdr, st, &h);
+  int rc = bin_counts(hdr, st, sync, cnt, &h);
   if (rc) return rc;
   ProductSrc<VT> src;
   src.a = product_args<VT>(A, B, klo, khi);
   src.c0 = c0;
   const bool slabs = L.P > 0;
-  rc = accumulate_pass<VT>(src, h, L, ws, c_colptr, c_rowidx, (VT *)c_values, st, !slabs);
+  rc = accumulate_pass<VT>(src, cnt, h, L, ws, c_colptr, c_rowidx, (VT *)c_values, st, !slabs);
   if (rc) return rc;
-  const int heavy = h.bin_count[kNumBins - 1];
-  if (slabs && heavy > 0) {
+  const int heavy = cnt[kNumBins - 1];
+  if (slabs && heavy != 0) {
     int32_t *soff = (int32_t *)(ws + L.slab_off);
     int32_t *s_ri = (int32_t *)(ws + L.slab_ri);
     VT *s_v = (VT *)(ws + L.slab_v);
+    const int32_t *hc = &hdr->bin_count[kNumBins - 1];
     if (khi > klo) {
       hipLaunchKernelGGL(k_slab_split<VT>, dim3(grid_of(khi - klo, 4)), dim3(256), 0, st, A->colptr, A->rowidx,
-                         (const VT *)A->values, klo, khi, (int)L.P, soff, s_ri, s_v);
+                         (const VT *)A->values, klo, khi, (int)L.P, soff, s_ri, s_v, hc);
       LAUNCHCHK();
     }
     ProductArgs<VT> sa = src.a;
@@ -1225,8 +1344,8 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
     sa.Av = s_v;
     SlabSel sel{soff, (int)L.P, 0, 0};
     const int32_t *list = bins + (int64_t)(kNumBins - 1) * ncol;
-    hipLaunchKernelGGL(k_heavy_slab<VT>, dim3(heavy), dim3(kHeavyThreads), 0, st, src.a, sa, sel, c0, list, c_colptr,
-                       c_rowidx, (VT *)c_values, &hdr->status);
+    hipLaunchKernelGGL(k_heavy_slab<VT>, dim3(bin_grid(heavy, false, 1)), dim3(kHeavyThreads), 0, st, src.a, sa, sel,
+                       c0, list, hc, &hdr->cursor[kNumBins - 1], c_colptr, c_rowidx, (VT *)c_values, &hdr->status);
     LAUNCHCHK();
   }
   return SPGEMM_OK;
@@ -1238,7 +1357,7 @@ static int merge_typed(const spgemm_csc *parts, int32_t n_parts, const int64_t *
   WsHeader *hdr = (WsHeader *)ws;
   int32_t *bins = (int32_t *)(ws + L.bins);
   PartDesc *pd = (PartDesc *)(ws + L.parts);
-  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, 1);
+  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, 1, 0);
   LAUNCHCHK();
   for (int c = 0; c < n_parts; c += kWave) {
     PartsChunk hc;
@@ -1251,16 +1370,17 @@ static int merge_typed(const spgemm_csc *parts, int32_t n_parts, const int64_t *
   hipLaunchKernelGGL(k_bin<false>, dim3(grid_of(L.ncol, 4 * kBinColsPerWave)), dim3(256), 0, st,
                      (const int64_t *)nullptr, (const int64_t *)nullptr, (const int32_t *)nullptr, (int64_t)0, L.ncol,
                      (int64_t)0, (int64_t)0, (int64_t)0, L.m, c_colptr, (int64_t *)nullptr, (int64_t *)nullptr, bins,
-                     hdr, g_min_bin);
+                     hdr, g_min_bin, g_caps[1]);
   LAUNCHCHK();
+  int cnt[kNumBins];
   WsHeader h;
-  int rc = read_header(hdr, st, &h);
+  int rc = bin_counts(hdr, st, true, cnt, &h);
   if (rc) return rc;
   MergeSrc<VT> src;
   src.P = pd;
   src.nparts = n_parts;
   src.m = L.m;
-  return accumulate_pass<VT>(src, h, L, ws, c_colptr, c_rowidx, (VT *)c_values, st);
+  return accumulate_pass<VT>(src, cnt, h, L, ws, c_colptr, c_rowidx, (VT *)c_values, st);
 }
 
 static_assert(sizeof(PartDesc) == kPartDescBytes, "part descriptor size");
@@ -1289,19 +1409,19 @@ int spgemm_symbolic(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_
   hipStream_t s = (hipStream_t)stream;
   char *w = (char *)ws;
   if (ncol == 0) {
-    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)w, 0);
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)w, 0, 0);
     LAUNCHCHK();
     return SPGEMM_OK;
   }
   const int64_t kdim = A->ncols;
-  if (n_layers == 1) return symbolic_pass(A, B, c0, ncol, 0, kdim, flops_out, nnz_out, L, w, s);
+  if (n_layers == 1) return symbolic_pass(A, B, c0, ncol, 0, kdim, flops_out, nnz_out, L, w, s, true);
   const int64_t width = (kdim + n_layers - 1) / n_layers;
   for (int32_t l = 0; l < n_layers; l++) {
     const int64_t klo = std::min<int64_t>(kdim, (int64_t)l * width), khi = std::min<int64_t>(kdim, klo + width);
-    int rc = symbolic_pass(A, B, c0, ncol, klo, khi, nullptr, nnz_out + (int64_t)l * ncol, L, w, s);
+    int rc = symbolic_pass(A, B, c0, ncol, klo, khi, nullptr, nnz_out + (int64_t)l * ncol, L, w, s, true);
     if (rc) return rc;
   }
-  return symbolic_pass(A, B, c0, ncol, 0, kdim, flops_out, nnz_out + (int64_t)n_layers * ncol, L, w, s);
+  return symbolic_pass(A, B, c0, ncol, 0, kdim, flops_out, nnz_out + (int64_t)n_layers * ncol, L, w, s, true);
 }
 
 int spgemm_numeric(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t c1, int32_t layer,
@@ -1322,7 +1442,7 @@ int spgemm_numeric(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t
   const int64_t ncol = c1 - c0;
   if (ncol > 0 && !c_colptr) return SPGEMM_E_INVAL;
   if (ncol == 0) {
-    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, (hipStream_t)stream, (WsHeader *)ws, 1);
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, (hipStream_t)stream, (WsHeader *)ws, 1, 0);
     LAUNCHCHK();
     return SPGEMM_OK;
   }
@@ -1331,8 +1451,8 @@ int spgemm_numeric(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t
   const int64_t klo = std::min<int64_t>(kdim, (int64_t)layer * width), khi = std::min<int64_t>(kdim, klo + width);
   hipStream_t s = (hipStream_t)stream;
   if (A->dtype == SPGEMM_F32)
-    return numeric_typed<float>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, (char *)ws, s);
-  return numeric_typed<double>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, (char *)ws, s);
+    return numeric_typed<float>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, (char *)ws, s, true);
+  return numeric_typed<double>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, (char *)ws, s, true);
 }
 
 int spgemm_merge(const spgemm_csc *parts, int32_t n_parts, const int64_t *c_colptr, int32_t *c_rowidx,
@@ -1351,7 +1471,7 @@ int spgemm_merge(const spgemm_csc *parts, int32_t n_parts, const int64_t *c_colp
   if (st) return st;
   if (L.ncol > 0 && !c_colptr) return SPGEMM_E_INVAL;
   if (L.ncol == 0) {
-    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, (hipStream_t)stream, (WsHeader *)ws, 1);
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, (hipStream_t)stream, (WsHeader *)ws, 1, 0);
     LAUNCHCHK();
     return SPGEMM_OK;
   }
@@ -1374,6 +1494,99 @@ int spgemm_colptr(const int64_t *counts, int64_t n, int64_t *colptr_out, void *w
   return launch_colptr_scan(counts, n, colptr_out, (int64_t *)(w + L.scan), s);
 }
 
+int spgemm_batched_forward(const spgemm_csc *A, const spgemm_csc *B, int64_t nnz_cap, int64_t *flops_out,
+                           int64_t *nnz_out, int64_t *c_colptr, int32_t *c_rowidx, void *c_values, void *ws,
+                           size_t ws_bytes, void *stream) {
+  int st = check_csc(A, true);
+  if (!st) st = check_csc(B, true);
+  if (st) return st;
+  if (A->dtype != B->dtype) return SPGEMM_E_DTYPE;
+  if (A->ncols != B->nrows) return SPGEMM_E_SHAPE;
+  if (nnz_cap < 0 || !nnz_out || !c_colptr || (nnz_cap > 0 && (!c_rowidx || !c_values))) return SPGEMM_E_INVAL;
+  WsLayout L;
+  st = ws_layout(SPGEMM_OP_BATCHED_FORWARD, A, B, 0, B->ncols, 1, &L);
+  if (st) return st;
+  st = check_ws(ws, ws_bytes, L.total);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  char *w = (char *)ws;
+  const int64_t n = B->ncols;
+  if (n == 0) {
+    st = launch_init_header((WsHeader *)w, 0, s);
+    if (st) return st;
+    return launch_colptr_scan(nnz_out, 0, c_colptr, (int64_t *)(w + L.scan), s);
+  }
+  st = symbolic_pass(A, B, 0, n, 0, A->ncols, flops_out, nnz_out, L, w, s, false);
+  if (st) return st;
+  st = launch_colptr_scan(nnz_out, n, c_colptr, (int64_t *)(w + L.scan), s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_clamp_colptr, dim3(std::max(1u, std::min(grid_of(n + 1, 256), 1024u))), dim3(256), 0, s,
+                     c_colptr, n, nnz_cap, &((WsHeader *)w)->status);
+  LAUNCHCHK();
+  // the numeric pass keeps the status word, so an overflow found above is reported
+  if (A->dtype == SPGEMM_F32)
+    return numeric_typed<float>(A, B, 0, n, 0, A->ncols, c_colptr, c_rowidx, c_values, L, w, s, false, true);
+  return numeric_typed<double>(A, B, 0, n, 0, A->ncols, c_colptr, c_rowidx, c_values, L, w, s, false, true);
+}
+
+int spgemm_set_bin_caps(int32_t which, const int64_t *caps_host) {
+  if (which != 0 && which != 1) return SPGEMM_E_INVAL;
+  const int64_t *table = which == 0 ? kSymTableCap : kNumTableCap;
+  BinCaps c;
+  for (int b = 0; b < kNumBins - 1; b++) c.cap[b] = caps_host ? caps_host[b] : table[b];
+  for (int b = 0; b < kNumBins - 1; b++) {
+    if (c.cap[b] < 1 || c.cap[b] > table[b]) return SPGEMM_E_INVAL;
+    if (b > 0 && c.cap[b] < c.cap[b - 1]) return SPGEMM_E_INVAL;
+  }
+  g_caps[which] = c;
+  return SPGEMM_OK;
+}
+
+int spgemm_batch_pack(const spgemm_csc *instances, int32_t count, int64_t *colptr_out, int32_t *rowidx_out,
+                      void *values_out, int64_t *offsets_host, void *ws, size_t ws_bytes, void *stream) {
+  if (!instances || count < 0 || !colptr_out || !offsets_host) return SPGEMM_E_INVAL;
+  const int32_t dt = instances[0].dtype;
+  int64_t rows = 0, cols = 0, nnz = 0;
+  std::vector<PackDesc> d((size_t)std::max(count, 1));
+  for (int i = 0; i < count; i++) {
+    const spgemm_csc &q = instances[i];
+    int st = check_csc(&q, values_out != nullptr);
+    if (st) return st;
+    if (values_out && q.dtype != dt) return SPGEMM_E_DTYPE;
+    d[i] = PackDesc{q.colptr, q.rowidx, q.values, q.ncols, q.nnz, rows, cols, nnz};
+    offsets_host[3 * i + 0] = rows;
+    offsets_host[3 * i + 1] = cols;
+    offsets_host[3 * i + 2] = nnz;
+    rows += q.nrows;
+    cols += q.ncols;
+    nnz += q.nnz;
+  }
+  offsets_host[3 * count + 0] = rows;
+  offsets_host[3 * count + 1] = cols;
+  offsets_host[3 * count + 2] = nnz;
+  if (rows > INT32_MAX) return SPGEMM_E_OVERFLOW;
+  if (nnz > 0 && !rowidx_out) return SPGEMM_E_INVAL;
+  const size_t need = sizeof(PackDesc) * (size_t)std::max(count, 1);
+  int st = check_ws(ws, ws_bytes, need);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (count > 0) {
+    HIPCHK(hipMemcpyAsync(ws, d.data(), sizeof(PackDesc) * (size_t)count, hipMemcpyHostToDevice, s));
+    const unsigned g = (unsigned)std::min(count, 8 * device_cus());
+    if (values_out && dt == SPGEMM_F64)
+      hipLaunchKernelGGL(k_pack<double>, dim3(g), dim3(256), 0, s, (const PackDesc *)ws, count, colptr_out, rowidx_out,
+                         (double *)values_out);
+    else
+      hipLaunchKernelGGL(k_pack<float>, dim3(g), dim3(256), 0, s, (const PackDesc *)ws, count, colptr_out, rowidx_out,
+                         (float *)values_out);
+    LAUNCHCHK();
+  }
+  hipLaunchKernelGGL(k_pack_last, dim3(1), dim3(64), 0, s, colptr_out, cols, nnz);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(s));  // the descriptor staging buffer is pageable host memory
+  return SPGEMM_OK;
+}
+
 int spgemm_debug_min_bin(int32_t bin) {
   if (bin < 0 || bin >= kNumBins) return SPGEMM_E_INVAL;
   g_min_bin = bin;
@@ -1387,7 +1600,7 @@ int spgemm_ws_status(void *ws, void *stream) {
   int rc = read_header((WsHeader *)ws, s, &h);
   if (rc) return rc;
   if (h.status != 0) {
-    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)ws, 1);
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)ws, 1, 0);
     return SPGEMM_E_DEVICE;
   }
   return SPGEMM_OK;

@@ -259,3 +259,48 @@ def batch_instance(spec: BatchSpec, i: int, seed: int, dtype=torch.float32, devi
     sb = seed * 1_000_003 + 2 * i + 2
     return (erdos_renyi(n, n, int(spec.dA[i]), sa, dtype, device),
             erdos_renyi(n, n, int(spec.dB[i]), sb, dtype, device))
+
+
+def batch_packed(spec: BatchSpec, seed: int, dtype=torch.float32, device="cpu", first: int = 0,
+                 count: int | None = None, chunk_cols: int = 1 << 22):
+    """Instances [first, first+count) of a batch as two block-diagonal CSC
+    matrices: instance i's A_i (n_i x n_i, dA_i distinct uniform rows per
+    column) occupies rows and columns [o_i, o_i + n_i) of A, and likewise B_i
+    in B, with o_i = n_first + ... + n_{i-1}.  Values 1-U[0,1).  Every draw is
+    keyed by the instance's global column id, so an instance's bytes do not
+    depend on which other instances are packed with it.
+
+    Returns (A, B, offsets) with offsets int64 [count+1] (o_i and the total)."""
+    dev = torch.device(device)
+    count = spec.n.numel() - first if count is None else count
+    n = spec.n[first:first + count].to(dev)
+    off = torch.zeros(count + 1, dtype=torch.int64, device=dev)
+    off[1:] = torch.cumsum(n, 0)
+    total = int(off[-1])
+    # global column id of each packed column: instance columns are numbered
+    # across the whole batch (not just this slice)
+    allcol = torch.zeros(spec.n.numel() + 1, dtype=torch.int64)
+    allcol[1:] = torch.cumsum(spec.n, 0)
+    gbase = int(allcol[first])
+    inst = torch.repeat_interleave(torch.arange(count, device=dev), n)
+    mats = []
+    for which, degs, tag in ((0, spec.dA, 11), (1, spec.dB, 12)):
+        d = degs[first:first + count].to(dev)[inst]  # per packed column
+        m = n[inst]
+        rows = torch.empty(0, dtype=torch.int32, device=dev)
+        parts = []
+        for c0 in range(0, total, chunk_cols):
+            c1 = min(total, c0 + chunk_cols)
+            gcol = torch.arange(c0, c1, device=dev, dtype=torch.int64) + gbase
+            r = _floyd_rows(seed * 2 + which, m[c0:c1], d[c0:c1], 32, gcol * 32, tag=TAG_ROWS + 16 * tag)
+            r = r + off[inst[c0:c1]][:, None]
+            parts.append(r[r >= off[inst[c0:c1]][:, None]].to(torch.int32))  # drop the -1 padding
+        rows = torch.cat(parts) if parts else rows
+        cp = torch.zeros(total + 1, dtype=torch.int64, device=dev)
+        cp[1:] = torch.cumsum(d, 0)
+        # value of entry t of global column g: counter g * 32 + t
+        gcol_e = torch.repeat_interleave(torch.arange(total, device=dev, dtype=torch.int64) + gbase, d)
+        t = torch.arange(rows.numel(), device=dev, dtype=torch.int64) - cp[:-1].repeat_interleave(d)
+        vals = (1.0 - Stream(seed * 2 + which, TAG_VALS + 16 * tag).uniform(gcol_e * 32 + t)).to(dtype)
+        mats.append(CSC(total, total, cp, rows, vals))
+    return mats[0], mats[1], off

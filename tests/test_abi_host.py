@@ -195,3 +195,19 @@ def test_backward_validation_before_launch():
     assert lib.spgemm_permute(None, 0x1, 10, S.F32, 0, 0x1, None) == S.E_INVAL
     assert lib.spgemm_permute(0x1, 0x1, -1, S.F32, 0, 0x1, None) == S.E_INVAL
     assert lib.spgemm_permute(None, None, 0, S.F32, 0, None, None) == S.OK
+
+
+def test_bin_caps_validation():
+    lib = S._lib
+    import numpy as _np
+    good = _np.array([16, 64, 256, 1024, 4096], _np.int64)
+    assert lib.spgemm_set_bin_caps(1, good.ctypes.data) == S.OK
+    assert lib.spgemm_set_bin_caps(1, None) == S.OK
+    too_big = _np.array([33, 128, 512, 2048, 5120], _np.int64)
+    assert lib.spgemm_set_bin_caps(1, too_big.ctypes.data) == S.E_INVAL
+    not_monotone = _np.array([32, 16, 512, 2048, 5120], _np.int64)
+    assert lib.spgemm_set_bin_caps(1, not_monotone.ctypes.data) == S.E_INVAL
+    assert lib.spgemm_set_bin_caps(2, good.ctypes.data) == S.E_INVAL
+    sym = _np.array([32, 128, 512, 2048, 16384], _np.int64)
+    assert lib.spgemm_set_bin_caps(0, sym.ctypes.data) == S.OK
+    assert lib.spgemm_set_bin_caps(0, None) == S.OK
