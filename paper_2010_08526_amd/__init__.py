@@ -48,6 +48,12 @@ _lib.spgemm_colptr.argtypes = [_vp, _i64, _vp, _vp, _sz, _vp]
 _lib.spgemm_numeric.argtypes = [_P, _P, _i64, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.spgemm_merge.argtypes = [_P, _i32, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.spgemm_ws_status.argtypes = [_vp, _vp]
+_lib.spgemm_batched_forward.argtypes = [_P, _P, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.spgemm_batched_masked_xty.argtypes = [_P, _P, _P, _vp, _vp, _sz, _vp]
+_lib.spgemm_batched_backward.argtypes = [_P, _P, _P, _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.spgemm_set_bin_caps.argtypes = [_i32, _vp]
+_lib.spgemm_batch_pack.argtypes = [_P, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.spgemm_debug_min_bin.argtypes = [_i32]
 _lib.spgemm_status_string.restype = ctypes.c_char_p
 _lib.spgemm_status_string.argtypes = [ctypes.c_int]
 _lib.spgemm_last_hip_error.restype = ctypes.c_int

@@ -24,13 +24,6 @@ import torch
 from . import (CSC, F32, OP_BATCHED_BACKWARD, OP_BATCHED_FORWARD, OP_SYMBOLIC, _check, _lib, _ptr, _stream,
                alloc_workspace, check_ws, desc, spgemm_csc, symbolic, workspace_size)
 
-_vp, _i64, _i32, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
-_P = ctypes.POINTER(spgemm_csc)
-_lib.spgemm_batched_forward.argtypes = [_P, _P, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
-_lib.spgemm_batched_masked_xty.argtypes = [_P, _P, _P, _vp, _vp, _sz, _vp]
-_lib.spgemm_batched_backward.argtypes = [_P, _P, _P, _vp, _vp, _vp, _vp, _sz, _vp]
-_lib.spgemm_set_bin_caps.argtypes = [_i32, _vp]
-_lib.spgemm_batch_pack.argtypes = [_P, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
 
 SYM_TABLE_CAP = (32, 128, 512, 2048, 16384)
 NUM_TABLE_CAP = (32, 128, 512, 2048, 5120)
