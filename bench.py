@@ -1,23 +1,28 @@
-"""Benchmark: SpGEMM GFLOP/s (2 * flops / s) and HBM roofline fraction on one
-MI355X.
+"""Benchmark: SpGEMM GFLOP/s (2 * flops / s) with the HBM-roofline fraction of
+the dominant kernel, on one MI355X.
 
-Default workload: R-MAT scale 20 (n = 1,048,576), edge factor 16,
+Headline workload: R-MAT scale 20 (n = 1,048,576), edge factor 16,
 (a, b, c) = (.57, .19, .19), symmetrized, deduplicated, float32 (0, 1];
-C = A A with an HBM budget set so the batch planner picks 4 column batches.
-A step is one whole product: symbolic pass, counts to the host, batch
-planner, then per batch the numeric pass (and merge when layered); each
-batch is handed to a consumer that discards it.  Inputs are resident in HBM
-before timing starts.
+C = A A with an HBM budget set so that the batch planner picks 4 column
+batches.  A step is one whole product: symbolic pass, counts to the host,
+batch planner, then per batch the numeric pass; each batch is handed to a
+consumer that discards it.  Inputs are resident in HBM before timing.
+
+Also reported on the same GPU (same accuracy bar as the tests):
+  fwd_bwd : Erdos-Renyi A, B (n = 262,144, 16 per column, N(0,1)): forward
+            alone vs forward + backward (gradients of a loss on P(C)).
+  batched : 4096 Erdos-Renyi pairs (n_i log-uniform in [256, 65536], 4-32
+            per column) as one HIP-graph replay vs a loop of 4096 plain
+            calls (column ranges of the same packed product).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Prints one JSON line.
+Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -26,6 +31,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "SpGEMM GFLOP/s (2*flops/s) + % HBM roofline; fwd+bwd & batched vs plain"
+
+
+def log(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
 
 
 def _parse():
@@ -35,41 +45,38 @@ def _parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--scale", type=int, default=20, help="R-MAT scale (20 is the named workload)")
     p.add_argument("--batches", type=int, default=4)
+    p.add_argument("--er-n", type=int, default=262_144)
+    p.add_argument("--batch-count", type=int, default=4096)
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-extras", action="store_true", help="skip the fwd_bwd and batched sections")
     return p.parse_args()
 
 
-def main():
-    args = _parse()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only; this build has no multi-GPU path (run with --gpus 1)",
-              file=sys.stderr)
-        sys.exit(2)
-    import numpy as np
-    import torch
+def _timed(fn, reps, torch):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / reps
 
-    import paper_2010_08526_amd as S
-    import synth
 
+# ----------------------------------------------------------------- headline
+def headline(args, torch, np, S, synth):
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     t0 = time.time()
     A = synth.rmat(args.scale, 16, synth.WORKLOADS["rmat20"].seed, dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
-    print(f"# generated R-MAT scale {args.scale}: n={A.ncols} nnz={A.nnz} in {time.time() - t0:.1f}s",
-          file=sys.stderr, flush=True)
-
+    log(f"R-MAT scale {args.scale}: n={A.ncols} nnz={A.nnz} generated in {time.time() - t0:.1f}s")
     eng = S.Engine(A, A, 1, budget_bytes=1 << 62)
     plan = eng.plan()
     flops = plan.total_flops
     nnz_c = int(plan.nnz_host.sum())
-    r = 8
+    r = 8  # int32 row + float32 value
     total_out = int((r * plan.nnz_host[0] + 8).sum())
-    # budget: inputs + library reserve + a share of the output that yields the target batch count
-    target = args.batches
-    lo, hi = total_out // (target + 1) + 1, total_out // max(1, target - 1) + 1
-    avail = None
+    # smallest output share that still gives the target batch count
+    lo, hi, avail = total_out // (args.batches + 1) + 1, total_out // max(1, args.batches - 1) + 1, None
     while lo <= hi:
         mid = (lo + hi) // 2
         try:
@@ -77,62 +84,79 @@ def main():
         except S.SpgemmError:
             lo = mid + 1
             continue
-        nb = len(b) - 1
-        if nb > target:
+        if len(b) - 1 > args.batches:
             lo = mid + 1
         else:
-            avail = mid
-            hi = mid - 1
+            avail, hi = mid, mid - 1
     eng.budget_bytes = eng.input_bytes + eng.reserve_bytes + avail
-    print(f"# flops={flops:.4e} nnz(C)={nnz_c:.4e} cf={flops / nnz_c:.3f} out={total_out / 1e9:.1f} GB "
-          f"budget={eng.budget_bytes / 1e9:.1f} GB", file=sys.stderr, flush=True)
+    log(f"flops={flops:.4e} nnz(C)={nnz_c:.4e} cf={flops / nnz_c:.3f} C={total_out / 1e9:.1f} GB "
+        f"budget={eng.budget_bytes / 1e9:.1f} GB")
 
     stream = torch.cuda.current_stream()
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-    times = {"symbolic": [], "numeric": []}
+    phase = {"symbolic_plan": [], "numeric": []}
 
     def step(record):
         e0 = ev(); e0.record(stream)
         pl = eng.plan()
         e1 = ev(); e1.record(stream)
-        num = []
+        spans = []
         for i in range(pl.nbatches):
             a = ev(); a.record(stream)
-            eng.run_batch(pl, i)
+            eng.run_batch(pl, i)  # consumer: the batch is discarded
             b = ev(); b.record(stream)
-            num.append((a, b))
+            spans.append((a, b))
         if record:
             torch.cuda.synchronize()
-            times["symbolic"].append(e0.elapsed_time(e1))
-            times["numeric"].append(sum(a.elapsed_time(b) for a, b in num))
+            phase["symbolic_plan"].append(e0.elapsed_time(e1))
+            phase["numeric"].append(sum(a.elapsed_time(b) for a, b in spans))
         return pl
 
     for _ in range(args.warmup):
         pl = step(False)
     torch.cuda.synchronize()
     eng.check()
+    S.profile_enable(True)
+    torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
         pl = step(True)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
+    prof = S.profile_report()
+    S.profile_enable(False)
     eng.check()
+    nb = pl.nbatches
     ms = 1e3 * t_total / args.steps
     gflops = 2.0 * flops / (t_total / args.steps) / 1e9
+    log(f"headline: {ms:.1f} ms/step, {gflops:.1f} GFLOP/s; kernels: " +
+        ", ".join(f"{k}={v[0] / args.steps:.1f}ms" for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])))
 
-    # Compulsory bytes of the numeric phase (per step, all batches): A is read
-    # once per batch, B once, C written once, plus column pointers.
-    nb = pl.nbatches
-    num_bytes = nb * r * A.nnz + r * A.nnz + r * nnz_c + 8 * (A.ncols + nb)
-    t_num = float(np.mean(times["numeric"])) / 1e3
-    achieved = num_bytes / t_num / 1e9
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(A, args.cpu_seconds)
-
-    out = {
-        "metric": "SpGEMM GFLOP/s (2*flops/s)",
+    # Dominant kernel and its compulsory bytes per launch.
+    dom = max(prof.items(), key=lambda kv: kv[1][0])
+    dom_name, (dom_ms, dom_calls) = dom[0], dom[1]
+    bcp = A.colptr.cpu().numpy()
+    bdeg = np.diff(bcp)
+    u = plan.nnz_host[0]
+    heavy = u > 5120
+    # per batch, the heavy columns' B entries and outputs, plus one read of A
+    per_batch = []
+    for i in range(nb):
+        c0, c1 = pl.bounds[i], pl.bounds[i + 1]
+        h = heavy[c0:c1]
+        per_batch.append(r * int(bdeg[c0:c1][h].sum()) + r * int(u[c0:c1][h].sum()) + 8 * int(h.sum()) + r * A.nnz)
+    num_bytes = nb * r * A.nnz + r * A.nnz + r * nnz_c + 8 * (A.ncols + nb)  # whole numeric phase
+    if dom_name == "heavy_slab":
+        alg_bytes_per_launch = float(np.mean(per_batch))
+        unit = "heavy output columns of one batch: r*(nnz(B) + nnz(C)) of those columns + 8 per column + r*nnz(A)"
+    else:
+        alg_bytes_per_launch = num_bytes / max(1, dom_calls / args.steps)
+        unit = "share of the numeric phase's compulsory bytes"
+    avg_launch_s = dom_ms / dom_calls / 1e3
+    achieved = alg_bytes_per_launch / avg_launch_s / 1e9
+    t_num = float(np.mean(phase["numeric"])) / 1e3
+    res = {
+        "metric": METRIC,
         "value": round(gflops, 3),
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -142,40 +166,149 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 values, f64 accumulation, int32 rows, int64 column pointers",
-        "data": "synthetic, seeded R-MAT",
-        "config": {"workload": f"rmat{args.scale}: C=A*A, R-MAT scale {args.scale} ef16 (.57,.19,.19) symmetrized "
-                               f"fp32, {nb} column batches from an HBM budget",
+        "dtype": "f64",
+        "value_storage": "f32 values, int32 rows, int64 column pointers",
+        "data": "synthetic, seeded R-MAT (no dataset)",
+        "config": {"workload": f"rmat{args.scale}: C=A*A, R-MAT scale {args.scale} ef16 (.57,.19,.19) symmetrized, "
+                               f"fp32 values, {nb} column batches from an HBM budget",
                    "n": A.ncols, "nnz_A": A.nnz, "flops": flops, "nnz_C": nnz_c, "batches": nb,
                    "budget_bytes": eng.budget_bytes},
-        "phases_ms": {"symbolic": round(float(np.mean(times["symbolic"])), 3),
-                      "numeric_all_batches": round(t_num * 1e3, 3)},
-        "roofline": {"bound": "hbm", "kernel": "numeric phase (all batches)", "achieved": round(achieved, 2),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
-        "cpu_baseline": cpu,
+        "phases_ms": {"symbolic_and_plan": round(float(np.mean(phase["symbolic_plan"])), 3),
+                      "numeric_all_batches": round(t_num * 1e3, 3),
+                      "numeric_phase_GBps_compulsory": round(num_bytes / t_num / 1e9, 2)},
+        "kernels_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items()},
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "bytes_per_launch": int(alg_bytes_per_launch), "bytes_unit": unit,
+                     "avg_launch_ms": round(avg_launch_s * 1e3, 3), "launches_per_step": dom_calls / args.steps},
     }
-    print(json.dumps(out), flush=True)
+    return res, A
+
+
+# -------------------------------------------------------------- fwd vs bwd
+def fwd_bwd(args, torch, np, S, synth):
+    dev = torch.device("cuda:0")
+    A, B = synth.make_workload("er262k", device=dev, n=args.er_n)
+    flops = args.er_n * 16 * 16
+    eng = S.Engine(A, B, 1)
+    pl = eng.plan()
+    C = eng.run_batch(pl, 0)
+    col = torch.repeat_interleave(torch.arange(C.ncols, device=dev), C.colptr[1:] - C.colptr[:-1])
+    # targets are taken at the first forward's storage slots (one wavefront per
+    # column keeps the slot order of these columns fixed from run to run)
+    T = synth.target_values(C.rowidx, col, C.ncols, synth.WORKLOADS["er262k"].seed, torch.float32)
+    bw = S.Backward(A, B, C)  # pattern transposes made once per structure
+
+    def fwd():
+        p = eng.plan()
+        eng.run_batch(p, 0)
+
+    def fwdbwd():
+        p = eng.plan()
+        Cb = eng.run_batch(p, 0)
+        dC = Cb.values - T  # loss 0.5*||C - T||^2 on P(C); C's storage order is fixed by the forward
+        bw.refresh_values(B)
+        bw(dC)
+
+    import paper_2010_08526_amd.batched as Bt
+    be = Bt.BatchedEngine(A, B, backward=True)
+    be.forward()
+    Cf = be.C
+    colf = torch.repeat_interleave(torch.arange(Cf.ncols, device=dev), Cf.colptr[1:] - Cf.colptr[:-1])
+    Tf = synth.target_values(Cf.rowidx, colf, Cf.ncols, synth.WORKLOADS["er262k"].seed, torch.float32)
+
+    def fwd_fused():
+        be.forward()
+        be.backward((be.values[:be.nnz_c] - Tf).contiguous())
+
+    fwd(); fwdbwd(); fwd_fused()
+    reps = max(3, args.steps)
+    t_f = _timed(fwd, reps, torch)
+    t_fb = _timed(fwdbwd, reps, torch)
+    t_ff = _timed(fwd_fused, reps, torch)
+    bw.check()
+    be.check()
+    out = {"workload": f"er{args.er_n}: A, B independent Erdos-Renyi n={args.er_n}, 16 per column, fp32 N(0,1); "
+                       "loss 0.5*||C-T||^2 on P(C)",
+           "flops_forward": flops,
+           "forward_ms": round(t_f * 1e3, 3), "forward_GFLOPs": round(2 * flops / t_f / 1e9, 2),
+           "fwd_bwd_ms": round(t_fb * 1e3, 3), "fwd_bwd_GFLOPs": round(6 * flops / t_fb / 1e9, 2),
+           "fwd_bwd_fused_ms": round(t_ff * 1e3, 3), "fwd_bwd_fused_GFLOPs": round(6 * flops / t_ff / 1e9, 2),
+           "fwd_bwd_over_fwd_time": round(t_fb / t_f, 3),
+           "note": "fwd_bwd = forward + transpose-based backward (dA via B^T, dC^T); fused = graph-capturable "
+                   "forward + one-pass backward (float64 atomics for dA); GFLOP/s counts 3x forward flops"}
+    log(f"fwd_bwd: fwd {t_f * 1e3:.2f} ms, fwd+bwd {t_fb * 1e3:.2f} ms, fused {t_ff * 1e3:.2f} ms")
+    return out
+
+
+# ------------------------------------------------------- batched vs plain
+def batched(args, torch, np, S, synth):
+    import paper_2010_08526_amd.batched as Bt
+    dev = torch.device("cuda:0")
+    w = synth.WORKLOADS["batch4096"]
+    spec = synth.batch_spec(args.batch_count, w.seed)
+    t0 = time.time()
+    A, B, off = synth.batch_packed(spec, w.seed, torch.float32, dev)
+    torch.cuda.synchronize()
+    flops = int((spec.n * spec.dA * spec.dB).sum())
+    log(f"batch: {args.batch_count} instances, sum n={int(spec.n.sum())}, nnz(A)={A.nnz}, flops={flops:.4e}, "
+        f"generated in {time.time() - t0:.1f}s")
+    eng = Bt.BatchedEngine(A, B)
+    tune = Bt.autotune(eng, reps=1, use_cache=False)
+    eng.capture(eng.forward)
+    reps = max(3, args.steps)
+    t_graph = _timed(eng.replay, reps, torch)
+    eng.check()
+    nnz_c = eng.nnz_c
+    # loop of plain calls: one column range (= one instance) per call
+    offs = off.cpu().tolist()
+    ws_sym = S.alloc_workspace(S.workspace_size(S.OP_SYMBOLIC, A, B, 0, B.ncols, 1))
+    ws_num = S.alloc_workspace(S.workspace_size(S.OP_NUMERIC, A, B, 0, B.ncols, 1))
+    ws_scan = S.alloc_workspace(S.workspace_size(S.OP_COLPTR, None, None, 0, B.ncols + 1))
+    cnt = torch.empty(B.ncols, dtype=torch.int64, device=dev)
+    cp = torch.empty(B.ncols + 1, dtype=torch.int64, device=dev)
+    big = int((eng.colptr[off[1:]] - eng.colptr[off[:-1]]).max())
+    ri = torch.empty(big, dtype=torch.int32, device=dev)
+    vv = torch.empty(big, dtype=torch.float32, device=dev)
+
+    def plain_loop():
+        for i in range(args.batch_count):
+            c0, c1 = offs[i], offs[i + 1]
+            S.symbolic(A, B, c0, c1, 1, None, cnt[c0:c1], ws_sym)
+            S.colptr(cnt[c0:c1], cp[c0:c1 + 1], ws_scan)
+            S.numeric(A, B, c0, c1, 0, 1, None, cp[c0:c1 + 1], ri, vv, ws_num)
+
+    plain_loop()
+    t_plain = _timed(plain_loop, 1, torch)
+    S.check_ws(ws_num, "plain loop")
+    out = {"workload": f"batch{args.batch_count}: independent Erdos-Renyi pairs, n_i log-uniform [256, 65536], "
+                       "4-32 per column, fp32 (0,1]; one packed block-diagonal product",
+           "flops": flops, "nnz_C": nnz_c,
+           "batched_graph_ms": round(t_graph * 1e3, 3), "batched_GFLOPs": round(2 * flops / t_graph / 1e9, 2),
+           "plain_loop_ms": round(t_plain * 1e3, 3), "plain_loop_GFLOPs": round(2 * flops / t_plain / 1e9, 2),
+           "speedup_batched_over_plain": round(t_plain / t_graph, 2),
+           "autotuned_caps": tune["caps"]}
+    log(f"batched: graph {t_graph * 1e3:.1f} ms vs plain loop {t_plain * 1e3:.1f} ms")
+    return out
 
 
 def cpu_baseline(A, seconds: float):
     """The oracle (plain C, float64 dense accumulator, OpenMP over columns) on
-    a seeded random sample of output columns of the same product."""
+    a seeded random sample of output columns of the headline product."""
     import numpy as np
 
     import oracle
 
     Ah = oracle.as_mat(A)
     n = Ah.ncols
-    rng = np.random.default_rng(12345)
-    perm = rng.permutation(n)
+    perm = np.random.default_rng(12345).permutation(n)
 
     def sample(cnt):
         cols = np.sort(perm[:cnt])
-        cp = np.zeros(cnt + 1, np.int64)
         lens = Ah.colptr[cols + 1] - Ah.colptr[cols]
+        cp = np.zeros(cnt + 1, np.int64)
         np.cumsum(lens, out=cp[1:])
-        idx = np.concatenate([np.arange(Ah.colptr[c], Ah.colptr[c + 1]) for c in cols]) if cnt else np.zeros(0, int)
+        idx = np.concatenate([np.arange(Ah.colptr[c], Ah.colptr[c + 1]) for c in cols])
         return oracle.Mat(Ah.nrows, cnt, cp, Ah.rowidx[idx], Ah.values[idx])
 
     threads = oracle.max_threads()
@@ -183,14 +316,39 @@ def cpu_baseline(A, seconds: float):
     while True:
         Bs = sample(cnt)
         t = time.perf_counter()
-        P = oracle.spgemm(Ah, Bs)
+        oracle.spgemm(Ah, Bs)
         dt = time.perf_counter() - t
         if dt > seconds / 4 or cnt >= n:
             break
         cnt = min(n, int(cnt * max(2.0, min(16.0, seconds / 2 / max(dt, 1e-3)))))
     fl = int(oracle.flops(Ah, Bs).sum())
     return {"value": round(2.0 * fl / dt / 1e9, 4), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"{cnt} random output columns of the same product ({fl:.3e} flops, {dt:.1f} s)"}
+            "sample": f"{cnt} seeded random output columns of the headline product ({fl:.3e} flops, {dt:.1f} s, "
+                      f"float64, structure + values)"}
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2010_08526_amd as S
+    import synth
+
+    torch.cuda.set_device(0)
+    res, A = headline(args, torch, np, S, synth)
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        res["fwd_bwd"] = fwd_bwd(args, torch, np, S, synth)
+        torch.cuda.empty_cache()
+        res["batched"] = batched(args, torch, np, S, synth)
+        torch.cuda.empty_cache()
+    res["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(A, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -267,6 +267,16 @@ int spgemm_batched_backward(const spgemm_csc *A, const spgemm_csc *B, const spge
  * change speed, never results.  SPGEMM_E_INVAL otherwise. */
 int spgemm_set_bin_caps(int32_t which, const int64_t *caps_host);
 
+/* Per-kernel timing (process-wide, off by default; not under graph
+ * capture).  spgemm_profile_enable(1) clears the records and brackets each
+ * main kernel launch that follows with HIP events on its stream;
+ * spgemm_profile_enable(0) stops recording and clears.  spgemm_profile_report
+ * waits for the recorded events and writes one line per kernel name,
+ * "name total_ms launches\n", into buf_host (SPGEMM_E_INVAL if it does not
+ * fit). */
+int spgemm_profile_enable(int32_t on);
+int spgemm_profile_report(char *buf_host, size_t buf_bytes);
+
 /* Synchronizes `stream` and reports the device-side status word of a
  * workspace used by the calls above: SPGEMM_OK, or SPGEMM_E_DEVICE if a
  * kernel found counts that disagree with the product or an index out of

@@ -54,6 +54,24 @@ _lib.spgemm_batched_backward.argtypes = [_P, _P, _P, _vp, _vp, _vp, _vp, _sz, _v
 _lib.spgemm_set_bin_caps.argtypes = [_i32, _vp]
 _lib.spgemm_batch_pack.argtypes = [_P, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.spgemm_debug_min_bin.argtypes = [_i32]
+_lib.spgemm_profile_enable.argtypes = [_i32]
+_lib.spgemm_profile_report.argtypes = [ctypes.c_char_p, _sz]
+
+
+def profile_enable(on: bool = True):
+    """Start (or stop) per-kernel HIP-event timing inside the library."""
+    _check(_lib.spgemm_profile_enable(int(on)), "spgemm_profile_enable")
+
+
+def profile_report() -> dict:
+    """{kernel name: (total ms, launches)} since profile_enable(True)."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(_lib.spgemm_profile_report(buf, len(buf)), "spgemm_profile_report")
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, ms, cnt = line.split()
+        out[name] = (float(ms), int(cnt))
+    return out
 _lib.spgemm_status_string.restype = ctypes.c_char_p
 _lib.spgemm_status_string.argtypes = [ctypes.c_int]
 _lib.spgemm_last_hip_error.restype = ctypes.c_int

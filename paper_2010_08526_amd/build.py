@@ -40,10 +40,10 @@ def build(verbose: bool = False) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     hipcc = _hipcc()
     objs = []
-    for src in ("host.cpp", "kernels.hip", "backward.hip"):
+    for src in ("host.cpp", "kernels.hip", "backward.hip", "profile.cpp"):
         obj = os.path.join(LIBDIR, src.replace(".", "_") + ".o")
         cmd = [hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-        if src.endswith(".cpp"):
+        if src == "host.cpp":
             cmd = [hipcc, "-O2", "-std=c++17", "-fPIC", "-Wall", f"-I{os.path.join(ROOT, 'include')}", "-c",
                    os.path.join(CSRC, src), "-o", obj]
         if verbose:

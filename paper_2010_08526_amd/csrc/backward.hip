@@ -23,6 +23,7 @@
 #include "hip_host.hpp"
 #include "internal.hpp"
 #include "lds_hash.hpp"
+#include "profile.hpp"
 
 namespace spg {
 
@@ -326,6 +327,7 @@ static int mxty_typed(const spgemm_csc *X, const spgemm_csc *Y, const spgemm_csc
   int32_t *status = &hdr->status;
   for (int b = 0; b < kNumBins - 1; b++) {
     if (cnt[b] == 0) continue;
+    ProfScope prof("masked_xty", st);
     const int32_t *list = bins + (int64_t)b * n;
     const int32_t *cp = &hdr->bin_count[b];
     switch (b) {
@@ -557,6 +559,7 @@ static int fbwd_typed(const spgemm_csc *A, const spgemm_csc *B, const spgemm_csc
                C->colptr, C->rowidx, (const VT *)dC, (VT *)dB, acc, C->nrows, A->ncols, A->nnz};
   int32_t *status = &hdr->status;
   for (int b = 0; b < kNumBins - 1; b++) {
+    ProfScope prof("fused_backward", st);
     const int32_t *list = bins + (int64_t)b * n;
     const int32_t *cp = &hdr->bin_count[b];
     switch (b) {
@@ -581,6 +584,7 @@ static int transpose_typed(const spgemm_csc *X, int64_t *t_colptr, int32_t *t_ro
   WsHeader *hdr = (WsHeader *)ws;
   int rc = launch_init_header(hdr, 0, st);
   if (rc) return rc;
+  ProfScope prof("transpose", st);
   const int64_t m = X->nrows;
   unsigned long long *cnt = (unsigned long long *)(ws + L.bins);
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(grid_of(std::max(m, X->nnz), 256), 8 * device_cus()));

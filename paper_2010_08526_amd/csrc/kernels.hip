@@ -20,6 +20,7 @@
 #include "internal.hpp"
 #include "lds_hash.hpp"
 #include "hip_host.hpp"
+#include "profile.hpp"
 
 namespace spg {
 
@@ -1113,6 +1114,7 @@ int launch_colptr_scan(const int64_t *counts, int64_t n, int64_t *out, int64_t *
     return SPGEMM_OK;
   }
   const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  ProfScope prof("scan", s);
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n, bsum);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kScanThreads), 0, s, bsum, nb);
@@ -1214,18 +1216,24 @@ static int symbolic_pass(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
   hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, 0, 0);
   LAUNCHCHK();
   const int64_t per_block = 4 * kBinColsPerWave;
-  hipLaunchKernelGGL(k_bin<true>, dim3(grid_of(ncol, per_block)), dim3(256), 0, st, A->colptr, B->colptr, B->rowidx,
-                     c0, ncol, klo, khi, (int64_t)A->ncols, A->nrows, (const int64_t *)nullptr, flops_out, nnz_row,
-                     bins, hdr, g_min_bin, g_caps[0]);
-  LAUNCHCHK();
+  {
+    ProfScope prof_bin("bin_symbolic", st);
+    hipLaunchKernelGGL(k_bin<true>, dim3(grid_of(ncol, per_block)), dim3(256), 0, st, A->colptr, B->colptr,
+                       B->rowidx, c0, ncol, klo, khi, (int64_t)A->ncols, A->nrows, (const int64_t *)nullptr,
+                       flops_out, nnz_row, bins, hdr, g_min_bin, g_caps[0]);
+    LAUNCHCHK();
+  }
   int cnt[kNumBins];
   WsHeader h;
   int rc = bin_counts(hdr, st, sync, cnt, &h);
   if (rc) return rc;
   ProductArgs<float> a = product_args<float>(A, B, klo, khi);
   int32_t *status = &hdr->status;
+  static const char *kSymNames[kNumBins] = {"sym_wave64", "sym_wave256", "sym_wave1024", "sym_block4096",
+                                            "sym_block32768", "sym_bitmap"};
   for (int b = 0; b < kNumBins; b++) {
     if (cnt[b] == 0) continue;
+    ProfScope prof(kSymNames[b], st);
     const int32_t *list = bins + (int64_t)b * ncol;
     const int32_t *cp = &hdr->bin_count[b];
     switch (b) {
@@ -1257,8 +1265,11 @@ static int accumulate_pass(const Src &src, const int *cnt, const WsHeader &h, co
   int32_t *bins = (int32_t *)(ws + L.bins);
   int32_t *status = &hdr->status;
   const int64_t ncol = L.ncol;
+  static const char *kNumNames[kNumBins - 1] = {"num_wave64", "num_wave256", "num_wave1024", "num_block4096",
+                                                "num_block10240"};
   for (int b = 0; b < kNumBins - 1; b++) {
     if (cnt[b] == 0) continue;
+    ProfScope prof(kNumNames[b], st);
     const int32_t *list = bins + (int64_t)b * ncol;
     const int32_t *cp = &hdr->bin_count[b];
     switch (b) {
@@ -1290,6 +1301,7 @@ static int accumulate_pass(const Src &src, const int *cnt, const WsHeader &h, co
       LAUNCHCHK();
     }
     const int32_t *list = bins + (int64_t)(kNumBins - 1) * ncol;
+    ProfScope prof("heavy_global", st);
     for (int first = 0; first < heavy; first += (int)L.slots) {
       const int ns = (int)std::min<int64_t>(L.slots, heavy - first);
       int parts = (int)std::max<int64_t>(1, std::min<int64_t>(64, (4 * device_cus() + ns - 1) / ns));
@@ -1335,6 +1347,7 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
     VT *s_v = (VT *)(ws + L.slab_v);
     const int32_t *hc = &hdr->bin_count[kNumBins - 1];
     if (khi > klo) {
+      ProfScope prof("slab_split", st);
       hipLaunchKernelGGL(k_slab_split<VT>, dim3(grid_of(khi - klo, 4)), dim3(256), 0, st, A->colptr, A->rowidx,
                          (const VT *)A->values, klo, khi, (int)L.P, soff, s_ri, s_v, hc);
       LAUNCHCHK();
@@ -1344,6 +1357,7 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
     sa.Av = s_v;
     SlabSel sel{soff, (int)L.P, 0, 0};
     const int32_t *list = bins + (int64_t)(kNumBins - 1) * ncol;
+    ProfScope prof("heavy_slab", st);
     hipLaunchKernelGGL(k_heavy_slab<VT>, dim3(bin_grid(heavy, false, 1)), dim3(kHeavyThreads), 0, st, src.a, sa, sel,
                        c0, list, hc, &hdr->cursor[kNumBins - 1], c_colptr, c_rowidx, (VT *)c_values, &hdr->status);
     LAUNCHCHK();
