@@ -20,8 +20,10 @@ numpy arrays.  Every function cites the passage it implements:
 
 Parity status: every function here is pinned by tests in
 ``tests/test_oracle.py`` against numpy/scipy, closed forms, invariants or
-hand-derived fixtures, except ``plan_batches``' choice of split points,
-which the paper leaves open (it is pinned only by its invariants).
+hand-derived fixtures. ``plan_batches`` is pinned by a brute-force search over
+all contiguous splits (fewest batches, then smallest largest batch); which of
+several equally balanced splits it returns is a convention the paper leaves
+open.
 """
 from __future__ import annotations
 
