@@ -50,6 +50,8 @@ def _parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extras", action="store_true", help="skip the fwd_bwd and batched sections")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain device copy of known size (to scale HBM byte counters) and exit")
     return p.parse_args()
 
 
@@ -146,11 +148,14 @@ def headline(args, torch, np, S, synth):
         h = heavy[c0:c1]
         per_batch.append(r * int(bdeg[c0:c1][h].sum()) + r * int(u[c0:c1][h].sum()) + 8 * int(h.sum()) + r * A.nnz)
     num_bytes = nb * r * A.nnz + r * A.nnz + r * nnz_c + 8 * (A.ncols + nb)  # whole numeric phase
-    if dom_name == "heavy_slab":
-        alg_bytes_per_launch = float(np.mean(per_batch))
-        unit = "heavy output columns of one batch: r*(nnz(B) + nnz(C)) of those columns + 8 per column + r*nnz(A)"
+    launches = max(1.0, dom_calls / args.steps)
+    if dom_name == "heavy_items":
+        # the heavy columns of every batch, spread evenly over the item launches
+        alg_bytes_per_launch = float(sum(per_batch)) / launches
+        unit = ("heavy output columns: r*(nnz(B) + nnz(C)) of those columns + 8 per column + r*nnz(A) per batch, "
+                "summed over batches and divided by the item launches per step")
     else:
-        alg_bytes_per_launch = num_bytes / max(1, dom_calls / args.steps)
+        alg_bytes_per_launch = num_bytes / launches
         unit = "share of the numeric phase's compulsory bytes"
     avg_launch_s = dom_ms / dom_calls / 1e3
     achieved = alg_bytes_per_launch / avg_launch_s / 1e9
@@ -178,7 +183,8 @@ def headline(args, torch, np, S, synth):
                       "numeric_phase_GBps_compulsory": round(num_bytes / t_num / 1e9, 2)},
         "kernels_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items()},
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": measured_traffic(dom_name, f"rmat{args.scale}"),
                      "bytes_per_launch": int(alg_bytes_per_launch), "bytes_unit": unit,
                      "avg_launch_ms": round(avg_launch_s * 1e3, 3), "launches_per_step": dom_calls / args.steps},
     }
@@ -327,6 +333,49 @@ def cpu_baseline(A, seconds: float):
                       f"float64, structure + values)"}
 
 
+# ------------------------------------------------------------ HBM traffic
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+COPY_BYTES = 1 << 31
+
+
+def copy_calibration(torch):
+    """A plain device-to-device copy of COPY_BYTES, five times: the reference
+    for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    x = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda:0")
+    y = torch.empty_like(x)
+    x.fill_(1)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "launches": 5}), flush=True)
+
+
+def source_digest():
+    """Digest of the device sources; measured traffic is tied to it."""
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2010_08526_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter runs, or None when there are none for the current sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel") != kernel or t.get("workload") != workload or t.get("source_digest") != source_digest():
+        return None
+    return int(t["hbm_bytes_per_launch"])
+
+
 def main():
     args = _parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -340,6 +389,9 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     res, A = headline(args, torch, np, S, synth)
     torch.cuda.empty_cache()
     if not args.no_extras:

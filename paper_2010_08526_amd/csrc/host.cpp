@@ -71,14 +71,20 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
         off = align_up(off + kPartDescBytes * (size_t)n_layers);
       }
       const bool numeric = op == SPGEMM_OP_NUMERIC || op == SPGEMM_OP_BATCHED_FORWARD;
-      if (numeric && A->nrows > kNumCap[kNumBins - 2] && num_slabs(A->nrows) <= kMaxSlabs) {
-        L->P = num_slabs(A->nrows);
+      const int64_t P = num_slabs(A->nrows);
+      if (numeric && A->nrows > kNumCap[kNumBins - 2] && P <= kMaxSlabs &&
+          sizeof(int32_t) * (uint64_t)(P + 1) * (uint64_t)A->ncols <= kMaxSlabOffBytes) {
+        L->P = P;
         L->slab_off = off;
         off = align_up(off + sizeof(int32_t) * (size_t)(L->P + 1) * (size_t)A->ncols);
         L->slab_ri = off;
         off = align_up(off + sizeof(int32_t) * (size_t)A->nnz);
         L->slab_v = off;
         off = align_up(off + sizeof(double) * (size_t)A->nnz);
+        L->hv_cur = off;
+        off = align_up(off + sizeof(int32_t) * (size_t)ncol);
+        L->hv_items = off;
+        off = align_up(off + 8 * (size_t)hv_item_cap(ncol, P));
       } else if ((op == SPGEMM_OP_NUMERIC || op == SPGEMM_OP_MERGE) && A->nrows > kNumCap[kNumBins - 2]) {
         L->slots = heavy_slots(A->nrows);
         L->nseg = (A->nrows + kHeavySeg - 1) / kHeavySeg;

@@ -44,17 +44,31 @@ constexpr int64_t kHeavySeg = 16384;  // global heavy path: rows per compaction 
 constexpr int kMaxAdeg = 1 << 25;  // per-column degree of the left operand handled per chunk
 
 // Heavy numeric columns: the left operand's entries are bucketed by row slab
-// of 2^kSlabShift rows; a heavy column is formed one group of consecutive
-// slabs at a time in LDS: a hash table when the group holds at most
-// kGroupCap distinct rows, else a single slab in a dense array.
-constexpr int kSlabShift = 13;
+// of 2^kSlabShift rows.  A heavy column is cut into independent items: runs of
+// consecutive slabs whose flop bounds add up to at most kHvCap (an LDS hash
+// table of kHvSlots slots), or one slab whose bound exceeds kHvCap (a dense
+// LDS accumulator of kSlabRows rows).  Columns with more than kHvWideT
+// entries in B(:,j) skip the bounds: every slab is a dense item.
+constexpr int kSlabShift = 12;
 constexpr int64_t kSlabRows = int64_t(1) << kSlabShift;
-constexpr int kMaxSlabs = 1024;  // rows up to kMaxSlabs * kSlabRows use slabs
-constexpr int kGroupSlots = 10240;
-constexpr int kGroupCap = 5120;
-constexpr int kWinSlabs = (int)(kBitmapRows / kSlabRows);  // slabs per counting window
+constexpr int kMaxSlabs = 2048;  // rows up to kMaxSlabs * kSlabRows use slabs
+constexpr uint64_t kMaxSlabOffBytes = uint64_t(8) << 30;  // cap on the slab offset table
+constexpr int kHvSlots = 2560;
+constexpr int kHvCap = kHvSlots / 2;
+constexpr int64_t kHvWideT = 1024;
+constexpr uint64_t kHvItemBytes = uint64_t(64) << 20;  // item list of one chunk of heavy columns
 
 inline int64_t num_slabs(int64_t m) { return (m + kSlabRows - 1) / kSlabRows; }
+
+// Item list capacity (items of 8 bytes) for ncol columns and P slabs: a
+// chunk of heavy columns at most this many items over P covers them.
+inline int64_t hv_item_cap(int64_t ncol, int64_t P) {
+  const int64_t lim = (int64_t)(kHvItemBytes / 8);
+  int64_t c = ncol * P;
+  if (c > lim) c = lim;
+  if (c < P) c = P;
+  return c;
+}
 
 // Workspace header: one 4 KiB block at offset 0.
 struct WsHeader {
@@ -62,7 +76,8 @@ struct WsHeader {
   int32_t pad0;
   uint64_t clean_tag;  // nonzero iff the heavy accumulator region is known to be all zero
   int32_t bin_count[kNumBins];
-  int32_t pad1[2];
+  int32_t items;        // heavy items listed for the current chunk
+  int32_t item_cursor;  // work-queue position over those items
   int32_t cursor[kNumBins];  // work-queue positions of the persistent kernels
   int32_t pad2[2];
 };
@@ -90,6 +105,8 @@ struct WsLayout {
   size_t slab_off = 0;    // numeric: int32 [kcols][P+1] slab offsets of the left operand
   size_t slab_ri = 0;     // numeric: int32 [nnzA] slabbed rows
   size_t slab_v = 0;      // numeric: 8-byte [nnzA] slabbed values
+  size_t hv_cur = 0;      // numeric: int32 [ncol] output cursor per heavy column
+  size_t hv_items = 0;    // numeric: uint2 [hv_item_cap] heavy items of one chunk
   int64_t P = 0;          // numeric: slabs (0 = heavy columns use global accumulators)
   size_t total = 0;
   int64_t slots = 0, nseg = 0, ncol = 0, m = 0;

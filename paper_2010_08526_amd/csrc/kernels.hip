@@ -346,6 +346,8 @@ __global__ void k_init_header(WsHeader *h, int keep_clean, int keep_status = 0) 
     if (!keep_status) h->status = 0;
     for (int b = 0; b < kNumBins; b++) h->bin_count[b] = 0;
     for (int b = 0; b < kNumBins; b++) h->cursor[b] = 0;
+    h->items = 0;
+    h->item_cursor = 0;
     if (!keep_clean) h->clean_tag = 0;
   }
 }
@@ -720,153 +722,257 @@ __global__ __launch_bounds__(256) void k_slab_split(const int64_t *Acp, const in
   }
 }
 
-// One workgroup per heavy column.  For each window of kBitmapRows rows: an
-// LDS bitmap pass counts the distinct rows of every slab; consecutive slabs
-// are grouped while their counts sum to at most kGroupCap; each group is
-// accumulated over the slabbed operand in an LDS hash table (or, for a
-// single slab with more than kGroupCap rows, a dense LDS array) and written
-// out at the column's running offset.  Output groups follow row order; rows
-// inside a hash group are in table order.
-constexpr int kHeavyThreads = 1024;
-constexpr int kBigBytes = 131072;
-static_assert(kGroupSlots * 12 <= kBigBytes, "group table does not fit");
-static_assert(kSlabRows * 8 + kSlabRows / 8 <= kBigBytes, "dense slab does not fit");
-static_assert(kBitmapRows / 8 <= kBigBytes, "bitmap does not fit");
+// Heavy columns: independent slab items (the constants are in internal.hpp).
+// An item is uint2 {x: position in the heavy list, y: slab range}; hv_enc
+// packs the range [sa, sb) and the dense flag.
+__device__ __forceinline__ uint32_t hv_enc(int sa, int sb, bool dense) {
+  return (uint32_t)sa | ((uint32_t)sb << 12) | (dense ? (1u << 24) : 0u);
+}
+static_assert(kMaxSlabs < (1 << 12), "slab ids must fit 12 bits");
 
-template <class VT>
-__global__ __launch_bounds__(kHeavyThreads) void k_heavy_slab(ProductArgs<VT> a, ProductArgs<VT> sa, SlabSel sel,
-                                                              int64_t c0, const int32_t *list,
-                                                              const int32_t *count_p, int *cursor,
-                                                              const int64_t *c_colptr, int32_t *out_ri, VT *out_v,
-                                                              int32_t *status) {
-  constexpr int NW = kHeavyThreads / kWave;
-  __shared__ __align__(16) unsigned char s_big[kBigBytes];
-  __shared__ int s_cnt[kWinSlabs];
-  __shared__ SegScratch s_sc[NW];
-  __shared__ int s_wsum[NW];
-  __shared__ int s_written;
-  __shared__ int s_item;
+// Per-thread counts -> exclusive offset within the workgroup; `total` gets
+// the workgroup's sum.  Contains a barrier.
+template <int NW>
+__device__ __forceinline__ int block_excl(int c, int *s_w, int &total) {
   const int w = threadIdx.x / kWave, l = lane();
-  const int count = *count_p;
-  s_sc[w].mark[l] = 0;
-  for (;;) {  // heavy columns taken from a work queue
-  if (threadIdx.x == 0) s_item = atomicAdd(cursor, 1);
+  const int incl = wave_incl_add(c);
+  if (l == kWave - 1) s_w[w] = incl;
   __syncthreads();
-  const int item = s_item;
-  __syncthreads();
-  if (item >= count) break;
-  const int32_t jj = list[item];
-  const int64_t col = c0 + jj;
-  const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
-  int64_t running = 0;
-  for (int64_t r0 = 0; r0 < a.m; r0 += kBitmapRows) {
-    const int64_t wrows = min((int64_t)kBitmapRows, a.m - r0);
-    const int words = (int)((wrows + 31) / 32);
-    const int nsl = (int)((wrows + kSlabRows - 1) / kSlabRows);
-    const int slab0 = (int)(r0 >> kSlabShift);
-    // ---- count distinct rows per slab
-    uint32_t *bm = (uint32_t *)s_big;
-    for (int t = threadIdx.x; t < words; t += kHeavyThreads) bm[t] = 0;
-    __syncthreads();
-    traverse_product_block<false, VT>(a, col, w, NW, s_sc[w], status, [&](int32_t row, double) {
-      const int64_t r = (int64_t)row - r0;
-      if (r >= 0 && r < wrows) atomicOr(&bm[r >> 5], 1u << (r & 31));
-    });
-    __syncthreads();
-    constexpr int WPS = (int)(kSlabRows / 32);  // words per slab
-    for (int t = w; t < nsl; t += NW) {
-      int c = 0;
-      for (int q = l; q < WPS; q += kWave) {
-        const int wi = t * WPS + q;
-        c += wi < words ? __popc(bm[wi]) : 0;
+  int before = 0, tot = 0;
+#pragma unroll
+  for (int z = 0; z < NW; z++) {
+    const int v = s_w[z];
+    if (z < w) before += v;
+    tot += v;
+  }
+  total = tot;
+  return before + incl - c;
+}
+
+__global__ void k_hv_reset(WsHeader *h) {
+  if (threadIdx.x == 0) {
+    h->items = 0;
+    h->item_cursor = 0;
+  }
+}
+
+// Planning: one workgroup per heavy column of the chunk [h0, h1) of the heavy
+// list.  The flop bound of slab s is F_s = sum over k in B(:,col) of the
+// entries of A(:,k) in slab s (read from the slab offsets: lanes along slabs,
+// a loop over B(:,col)).  Slabs are then cut into items in order: a slab
+// with F_s > kHvCap is a dense item, other slabs are joined while their
+// bounds add up to at most kHvCap (one hash item).  Wide columns (more than
+// kHvWideT entries in B(:,col)) make every slab a dense item.
+constexpr int kHvPlanThreads = 256;
+
+__global__ __launch_bounds__(kHvPlanThreads) void k_hv_plan(const int64_t *Bcp, const int32_t *Bri, int64_t c0,
+                                                            int64_t klo, int64_t khi, const int32_t *off, int P,
+                                                            const int32_t *list, const int32_t *count_p, int64_t h0,
+                                                            int64_t h1, uint2 *items, int64_t item_cap,
+                                                            WsHeader *hdr) {
+  constexpr int NW = kHvPlanThreads / kWave;
+  __shared__ int s_F[kMaxSlabs];
+  __shared__ uint32_t s_grp[kMaxSlabs];
+  __shared__ int s_ng, s_base;
+  const int w = threadIdx.x / kWave, l = lane();
+  const int64_t count = min((int64_t)*count_p, h1);
+  int32_t *status = &hdr->status;
+  for (int64_t h = h0 + blockIdx.x; h < count; h += gridDim.x) {
+    const int64_t col = c0 + list[h];
+    const int64_t pb = Bcp[col], pe = Bcp[col + 1];
+    const bool wide = pe - pb > kHvWideT;
+    if (!wide) {
+      for (int sb = w * kWave; sb < P; sb += NW * kWave) {
+        const int s = sb + l;
+        int64_t acc = 0;
+        for (int64_t q0 = pb; q0 < pe; q0 += kWave) {
+          const int32_t kv = q0 + l < pe ? Bri[q0 + l] : -1;
+          const int nk = (int)min((int64_t)kWave, pe - q0);
+          for (int i = 0; i < nk; i += 4) {
+            int32_t lo_[4], hi_[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+              const int32_t k = readlane(kv, min(i + u, kWave - 1));
+              const bool ok = i + u < nk && k >= klo && k < khi && s < P;
+              const int32_t *o = off + (ok ? (int64_t)(k - klo) * (P + 1) : 0);
+              lo_[u] = ok ? o[s] : 0;
+              hi_[u] = ok ? o[s + 1] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) acc += hi_[u] - lo_[u];
+          }
+        }
+        if (s < P) s_F[s] = (int)min(acc, (int64_t)1 << 30);
       }
-      c = wave_sum_i32(c);
-      if (l == 0) s_cnt[t] = c;
     }
     __syncthreads();
-    // ---- groups of slabs (every thread derives the same grouping)
-    int t = 0;
-    while (t < nsl) {
-      if (s_cnt[t] == 0) {
-        t++;
-        continue;
-      }
-      int t2 = t + 1, gcnt = s_cnt[t];
-      const bool dense = gcnt > kGroupCap;
-      if (!dense) {
-        while (t2 < nsl && gcnt + s_cnt[t2] <= kGroupCap) gcnt += s_cnt[t2++];
-      }
-      SlabSel g = sel;
-      g.sa = slab0 + t;
-      g.sb = slab0 + t2;
-      const int64_t gbase = base + running;
-      if (dense) {
-        double *acc = (double *)s_big;
-        uint32_t *bits = (uint32_t *)(s_big + kSlabRows * 8);
-        const int64_t rb = r0 + (int64_t)t * kSlabRows;
-        for (int q = threadIdx.x; q < (int)kSlabRows; q += kHeavyThreads) acc[q] = 0.0;
-        for (int q = threadIdx.x; q < (int)(kSlabRows / 32); q += kHeavyThreads) bits[q] = 0;
-        __syncthreads();
-        traverse_product_block<true, VT, true>(sa, col, w, NW, s_sc[w], status, [&](int32_t row, double v) {
-          const int64_t r = (int64_t)row - rb;
-          if (r >= 0 && r < kSlabRows) {
-            atomicAdd(&acc[r], v);
-            atomicOr(&bits[r >> 5], 1u << (r & 31));
+    if (threadIdx.x == 0) {
+      int ng = 0;
+      if (wide) {
+        for (int t = 0; t < P; t++) s_grp[ng++] = hv_enc(t, t + 1, true);
+      } else {
+        int t = 0;
+        while (t < P) {
+          const int f = s_F[t];
+          if (f == 0) {
+            t++;
+          } else if (f > kHvCap) {
+            s_grp[ng++] = hv_enc(t, t + 1, true);
+            t++;
+          } else {
+            int sum = f, t2 = t + 1;
+            while (t2 < P && sum + s_F[t2] <= kHvCap) sum += s_F[t2++];
+            s_grp[ng++] = hv_enc(t, t2, false);
+            t = t2;
           }
-        }, g);
-        __syncthreads();
-        // ordered compaction: thread q < kSlabRows/32 owns word q
-        const int q = threadIdx.x;
-        const uint32_t word = q < (int)(kSlabRows / 32) ? bits[q] : 0u;
-        const int c = __popc(word);
-        const int incl = wave_incl_add(c);
-        if (l == kWave - 1) s_wsum[w] = incl;
-        __syncthreads();
-        int wb = 0, wt = 0;
-        for (int z = 0; z < NW; z++) {
-          if (z < w) wb += s_wsum[z];
-          wt += s_wsum[z];
         }
-        if (threadIdx.x == 0 && wt != gcnt) flag_error(status, 6);
-        int64_t o = wb + incl - c;
+      }
+      s_ng = ng;
+      s_base = ng ? atomicAdd(&hdr->items, ng) : 0;
+      if ((int64_t)s_base + ng > item_cap) flag_error(status, 9);
+    }
+    __syncthreads();
+    const int ng = s_ng, base = s_base;
+    if ((int64_t)base + ng <= item_cap)
+      for (int i = threadIdx.x; i < ng; i += kHvPlanThreads) items[base + i] = make_uint2((uint32_t)h, s_grp[i]);
+    __syncthreads();
+  }
+}
+
+// Items: persistent workgroups take items from a queue (the next index is
+// fetched while the current item runs).  A dense item accumulates slab sa in
+// a float64 array of kSlabRows rows plus an occupancy bitmap; a hash item
+// accumulates slabs [sa, sb) in a kHvSlots-slot table.  The item's rows are
+// appended to its column at a position reserved on the column's cursor
+// (dense items in row order, hash items in slot order).
+constexpr int kHvThreads = 256;
+
+template <class VT>
+__global__ __launch_bounds__(kHvThreads) void k_hv_items(ProductArgs<VT> sa, SlabSel sel, int64_t c0,
+                                                         const int32_t *list, const uint2 *items, WsHeader *hdr,
+                                                         int64_t item_cap, const int64_t *c_colptr, int32_t *hv_cur,
+                                                         int32_t *out_ri, VT *out_v) {
+  constexpr int NW = kHvThreads / kWave;
+  constexpr int kWords = (int)(kSlabRows / 32);
+  constexpr int kPer = kHvSlots / kHvThreads;
+  static_assert(kHvSlots % kHvThreads == 0, "hash slots split evenly over threads");
+  static_assert(kWords <= kHvThreads, "one bitmap word per thread");
+  static_assert(kHvSlots * 12 <= kSlabRows * 8, "hash table fits the dense array");
+  __shared__ __align__(16) unsigned char s_tab[kSlabRows * 8 + kSlabRows / 8];
+  __shared__ SegScratch s_sc[NW];
+  __shared__ int s_w[NW];
+  __shared__ int s_next, s_pos;
+  const int w = threadIdx.x / kWave, l = lane();
+  int32_t *status = &hdr->status;
+  const int nitems = (int)min((int64_t)hdr->items, item_cap);
+  const int nheavy = hdr->bin_count[kNumBins - 1];
+  s_sc[w].mark[l] = 0;
+  if (threadIdx.x == 0) s_next = atomicAdd(&hdr->item_cursor, 1);
+  __syncthreads();
+  int it = s_next;
+  while (it < nitems) {
+    __syncthreads();  // every thread has taken s_next
+    if (threadIdx.x == 0) s_next = atomicAdd(&hdr->item_cursor, 1);
+    const uint2 rec = items[it];
+    const int h = (int)rec.x;
+    const int sa0 = (int)(rec.y & 0xfffu), sb0 = (int)((rec.y >> 12) & 0xfffu);
+    const bool dense = ((rec.y >> 24) & 1u) != 0;
+    if (h < 0 || h >= nheavy || sa0 >= sb0 || sb0 > sel.P || (dense && sb0 != sa0 + 1)) {
+      if (threadIdx.x == 0) flag_error(status, 9);
+      __syncthreads();
+      it = s_next;
+      continue;
+    }
+    const int64_t jj = list[h];
+    const int64_t col = c0 + jj;
+    SlabSel g = sel;
+    g.sa = sa0;
+    g.sb = sb0;
+    if (dense) {
+      double *acc = (double *)s_tab;
+      uint32_t *bits = (uint32_t *)(s_tab + kSlabRows * 8);
+      for (int q = threadIdx.x; q < (int)kSlabRows; q += kHvThreads) acc[q] = 0.0;
+      if (threadIdx.x < kWords) bits[threadIdx.x] = 0u;
+      __syncthreads();
+      const int64_t rb = (int64_t)sa0 << kSlabShift;
+      traverse_product_block<true, VT, true>(sa, col, w, NW, s_sc[w], status, [&](int32_t row, double v) {
+        const uint64_t r = (uint64_t)((int64_t)row - rb);
+        if (r < (uint64_t)kSlabRows) {
+          atomicAdd(&acc[r], v);
+          atomicOr(&bits[r >> 5], 1u << (r & 31));
+        } else {
+          flag_error(status, 6);
+        }
+      }, g);
+      __syncthreads();
+      const uint32_t word = threadIdx.x < kWords ? bits[threadIdx.x] : 0u;
+      int total;
+      const int ex = block_excl<NW>(__popc(word), s_w, total);
+      if (threadIdx.x == 0) s_pos = total ? atomicAdd(&hv_cur[h], total) : 0;
+      __syncthreads();
+      const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
+      if ((int64_t)s_pos + total > cap) {
+        if (threadIdx.x == 0) flag_error(status, 4);
+      } else {
+        int64_t o = base + s_pos + ex;
         uint32_t bw = word;
         while (bw) {
           const int b = __ffs(bw) - 1;
           bw &= bw - 1;
-          const int r = q * 32 + b;
-          if (running + o < cap) {
-            out_ri[gbase + o] = (int32_t)(rb + r);
-            out_v[gbase + o] = (VT)acc[r];
-          }
+          const int r = (int)threadIdx.x * 32 + b;
+          out_ri[o] = (int32_t)(rb + r);
+          out_v[o] = (VT)acc[r];
           o++;
         }
-        __syncthreads();
-      } else {
-        int32_t *keys = (int32_t *)s_big;
-        double *vals = (double *)(s_big + kGroupSlots * 4);
-        for (int q = threadIdx.x; q < kGroupSlots; q += kHeavyThreads) {
-          keys[q] = kEmpty;
-          vals[q] = 0.0;
-        }
-        if (threadIdx.x == 0) s_written = 0;
-        __syncthreads();
-        traverse_product_block<true, VT, true>(sa, col, w, NW, s_sc[w], status, [&](int32_t row, double v) {
-          ht_accumulate(keys, vals, kGroupSlots, row, v);
-        }, g);
-        __syncthreads();
-        constexpr int PER = (kGroupSlots + NW - 1) / NW;
-        const int64_t room = cap - running;
-        compact_range<VT>(keys, vals, w * PER, min(kGroupSlots, (w + 1) * PER), gbase, min(room, (int64_t)gcnt),
-                          &s_written, out_ri, out_v);
-        __syncthreads();
-        if (threadIdx.x == 0 && s_written != gcnt) flag_error(status, 6);
       }
-      running += gcnt;
-      t = t2;
+    } else {
+      int32_t *keys = (int32_t *)s_tab;
+      double *vals = (double *)(s_tab + kHvSlots * 4);
+      for (int q = threadIdx.x; q < kHvSlots; q += kHvThreads) {
+        keys[q] = kEmpty;
+        vals[q] = 0.0;
+      }
+      __syncthreads();
+      traverse_product_block<true, VT, true>(sa, col, w, NW, s_sc[w], status, [&](int32_t row, double v) {
+        ht_accumulate(keys, vals, kHvSlots, row, v);
+      }, g);
+      __syncthreads();
+      const int q0 = (int)threadIdx.x * kPer;
+      int c = 0;
+#pragma unroll
+      for (int i = 0; i < kPer; i++) c += keys[q0 + i] != kEmpty ? 1 : 0;
+      int total;
+      const int ex = block_excl<NW>(c, s_w, total);
+      if (threadIdx.x == 0) s_pos = total ? atomicAdd(&hv_cur[h], total) : 0;
+      __syncthreads();
+      const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
+      if ((int64_t)s_pos + total > cap) {
+        if (threadIdx.x == 0) flag_error(status, 4);
+      } else {
+        int64_t o = base + s_pos + ex;
+#pragma unroll
+        for (int i = 0; i < kPer; i++) {
+          const int32_t key = keys[q0 + i];
+          if (key != kEmpty) {
+            out_ri[o] = key;
+            out_v[o] = (VT)vals[q0 + i];
+            o++;
+          }
+        }
+      }
     }
     __syncthreads();
+    it = s_next;
   }
-  if (threadIdx.x == 0 && running != cap) flag_error(status, 4);
+}
+
+// Every heavy column received exactly its symbolic count.
+__global__ void k_hv_check(const int32_t *list, const int32_t *count_p, const int64_t *c_colptr,
+                           const int32_t *hv_cur, int32_t *status) {
+  const int count = *count_p;
+  for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < count; h += gridDim.x * blockDim.x) {
+    const int64_t jj = list[h];
+    if ((int64_t)hv_cur[h] != c_colptr[jj + 1] - c_colptr[jj]) flag_error(status, 4);
   }
 }
 
@@ -1357,9 +1463,32 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
     sa.Av = s_v;
     SlabSel sel{soff, (int)L.P, 0, 0};
     const int32_t *list = bins + (int64_t)(kNumBins - 1) * ncol;
-    ProfScope prof("heavy_slab", st);
-    hipLaunchKernelGGL(k_heavy_slab<VT>, dim3(bin_grid(heavy, false, 1)), dim3(kHeavyThreads), 0, st, src.a, sa, sel,
-                       c0, list, hc, &hdr->cursor[kNumBins - 1], c_colptr, c_rowidx, (VT *)c_values, &hdr->status);
+    int32_t *hv_cur = (int32_t *)(ws + L.hv_cur);
+    uint2 *items = (uint2 *)(ws + L.hv_items);
+    const int64_t icap = hv_item_cap(ncol, L.P);
+    const int64_t H = std::max<int64_t>(1, icap / L.P);
+    const int64_t hmax = heavy > 0 ? heavy : ncol;  // heavy < 0: the count is only on the device
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid_of((ncol * 4 + 15) / 16, 256)), dim3(256), 0, st, (uint4 *)hv_cur,
+                       (ncol * 4 + 15) / 16);
+    LAUNCHCHK();
+    for (int64_t h0 = 0; h0 < hmax; h0 += H) {
+      const int64_t h1 = std::min(hmax, h0 + H);
+      hipLaunchKernelGGL(k_hv_reset, dim3(1), dim3(64), 0, st, hdr);
+      LAUNCHCHK();
+      {
+        ProfScope prof("heavy_plan", st);
+        const unsigned pg = (unsigned)std::min<int64_t>(h1 - h0, 16 * (int64_t)device_cus());
+        hipLaunchKernelGGL(k_hv_plan, dim3(pg), dim3(kHvPlanThreads), 0, st, B->colptr, B->rowidx, c0, klo, khi,
+                           (const int32_t *)soff, (int)L.P, list, hc, h0, h1, items, icap, hdr);
+        LAUNCHCHK();
+      }
+      ProfScope prof("heavy_items", st);
+      hipLaunchKernelGGL(k_hv_items<VT>, dim3(4 * device_cus()), dim3(kHvThreads), 0, st, sa, sel, c0, list,
+                         (const uint2 *)items, hdr, icap, c_colptr, hv_cur, c_rowidx, (VT *)c_values);
+      LAUNCHCHK();
+    }
+    hipLaunchKernelGGL(k_hv_check, dim3(grid_of(hmax, 256)), dim3(256), 0, st, list, hc, c_colptr,
+                       (const int32_t *)hv_cur, &hdr->status);
     LAUNCHCHK();
   }
   return SPGEMM_OK;
