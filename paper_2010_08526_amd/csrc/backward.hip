@@ -163,21 +163,22 @@ __device__ __forceinline__ void mxty_dots(const MxtyArgs<VT> &a, int64_t pb, int
       double s = 0.0;
       for (int t0 = 0; t0 < len; t0 += kDotUnroll) {
         int32_t r[kDotUnroll];
-        double xv[kDotUnroll];
+        VT xv[kDotUnroll];
 #pragma unroll
         for (int t = 0; t < kDotUnroll; t++) {
           r[t] = -1;
-          xv[t] = 0.0;
+          xv[t] = VT(0);
           if (t0 + t < len) {
             r[t] = a.Xri[x0 + t0 + t];
-            xv[t] = (double)a.Xv[x0 + t0 + t];
+            xv[t] = a.Xv[x0 + t0 + t];
           }
         }
 #pragma unroll
         for (int t = 0; t < kDotUnroll; t++) {
           if (t0 + t < len) {
-            if ((uint32_t)r[t] < (uint32_t)a.m)
-              s += xv[t] * look(r[t]);
+            const int32_t rt = opaque(r[t]);
+            if ((uint32_t)rt < (uint32_t)a.m)
+              s += (double)opaque(xv[t]) * look(rt);
             else
               flag_error(status, 3);
           }
@@ -191,12 +192,29 @@ __device__ __forceinline__ void mxty_dots(const MxtyArgs<VT> &a, int64_t pb, int
       lm &= lm - 1;
       const int64_t lx0 = readlane64(x0, L), lx1 = readlane64(x1, L);
       double s = 0.0;
-      for (int64_t q = lx0 + l; q < lx1; q += kWave) {
-        const int32_t r = a.Xri[q];
-        if ((uint32_t)r < (uint32_t)a.m)
-          s += (double)a.Xv[q] * look(r);
-        else
-          flag_error(status, 3);
+      for (int64_t q0 = lx0 + l; q0 < lx1; q0 += 4 * kWave) {
+        int32_t r[4];
+        VT xv[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          const int64_t q = q0 + t * kWave;
+          r[t] = 0;
+          xv[t] = VT(0);
+          if (q < lx1) {
+            r[t] = a.Xri[q];
+            xv[t] = a.Xv[q];
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          if (q0 + t * kWave < lx1) {
+            const int32_t rt = opaque(r[t]);
+            if ((uint32_t)rt < (uint32_t)a.m)
+              s += (double)opaque(xv[t]) * look(rt);
+            else
+              flag_error(status, 3);
+          }
+        }
       }
       for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
       if (l == 0) a.out[base + L] = (VT)s;
@@ -425,22 +443,23 @@ __device__ __forceinline__ void fbwd_column(const FbArgs<VT> &a, int64_t j, int 
       double s = 0.0;
       for (int t0 = 0; t0 < len; t0 += kDotUnroll) {
         int32_t r[kDotUnroll];
-        double av[kDotUnroll];
+        VT av[kDotUnroll];
 #pragma unroll
         for (int t = 0; t < kDotUnroll; t++) {
           r[t] = -1;
-          av[t] = 0.0;
+          av[t] = VT(0);
           if (t0 + t < len) {
             r[t] = a.Ari[x0 + t0 + t];
-            av[t] = (double)a.Av[x0 + t0 + t];
+            av[t] = a.Av[x0 + t0 + t];
           }
         }
 #pragma unroll
         for (int t = 0; t < kDotUnroll; t++) {
           if (t0 + t < len) {
-            if ((uint32_t)r[t] < (uint32_t)a.m) {
-              const double g = look(r[t]);
-              s += av[t] * g;
+            const int32_t rt = opaque(r[t]);
+            if ((uint32_t)rt < (uint32_t)a.m) {
+              const double g = look(rt);
+              s += (double)opaque(av[t]) * g;
               atomicAdd(&a.dA[x0 + t0 + t], bkj * g);
             } else {
               flag_error(status, 3);

@@ -111,6 +111,15 @@ __device__ __forceinline__ int wave_flatten(int len, int *mark, Body &&body) {
   return total;
 }
 
+// Returns v unchanged, but the compiler cannot move a use of the result above
+// this point: a gathered value used only after every gather of a batch has
+// been issued keeps those loads in flight together (no wait between them).
+template <class T>
+__device__ __forceinline__ T opaque(T v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // Device-side status word: first writer wins, value kept for the host.
 __device__ __forceinline__ void flag_error(int32_t *status, int code) { atomicCAS(status, 0, code); }
 

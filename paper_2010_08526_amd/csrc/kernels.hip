@@ -61,15 +61,16 @@ struct ProductArgs {
 // r_stride waves can share one column; r_stride = 1 processes every round.
 // The owner of round fb's first element comes from a ballot (the highest
 // lane whose segment starts at or before fb), so rounds are independent.
-// Rounds are taken kPipe at a time: owners first, then every gather
-// (load(o, e, row, val)), then every insert (ins(row, val)), so that a
-// wavefront keeps kPipe independent global loads in flight.
+// Rounds are taken kPipe at a time in three phases: owners, then every
+// gather (load(o, e, row, raw) issues the loads of element e of segment o and
+// must not use their results), then every insert (ins(row, value(o, raw))),
+// so that a wavefront keeps kPipe independent global loads in flight.
 constexpr int kPipe = 8;
 
-template <class Load, class Ins>
+template <class RawT, class Load, class Value, class Ins>
 __device__ __forceinline__ void flatten_rounds(int len, int excl, int total, int *mark, int64_t r_base,
                                                int64_t r_rank, int64_t r_stride, uint32_t m, int32_t *status,
-                                               Load &&load, Ins &&ins) {
+                                               Load &&load, Value &&value, Ins &&ins) {
   const int l = lane();
   int64_t r0 = (r_rank - r_base) % r_stride;
   if (r0 < 0) r0 += r_stride;
@@ -104,19 +105,19 @@ __device__ __forceinline__ void flatten_rounds(int len, int excl, int total, int
       }
     }
     int32_t row_[kPipe];
-    double v_[kPipe];
-    // gathers: nothing below depends on a loaded value until every load is issued
+    RawT raw_[kPipe];
 #pragma unroll
     for (int u = 0; u < kPipe; u++) {
       row_[u] = -1;
-      v_[u] = 0.0;
-      if (own_[u] >= 0) load(own_[u], e_[u], row_[u], v_[u]);
+      raw_[u] = RawT(0);
+      if (own_[u] >= 0) load(own_[u], e_[u], row_[u], raw_[u]);
     }
 #pragma unroll
     for (int u = 0; u < kPipe; u++) {
       if (own_[u] >= 0) {
-        if ((uint32_t)row_[u] < m)
-          ins(row_[u], v_[u]);
+        const int32_t row = opaque(row_[u]);
+        if ((uint32_t)row < m)
+          ins(row, value(own_[u], opaque(raw_[u])));
         else
           flag_error(status, 3);
       }
@@ -127,7 +128,8 @@ __device__ __forceinline__ void flatten_rounds(int len, int excl, int total, int
 // Long segments (at least kLongSeg elements) bypass the owner search: the
 // whole wavefront streams them in blocks of kBlk elements, element
 // blk*kBlk + t*64 + lane for t < kVec, so every load instruction reads 64
-// consecutive entries and each lane keeps kVec loads in flight.  Blocks are
+// consecutive entries and each lane keeps kVec loads in flight (values are
+// scaled only after every load of the block is issued).  Blocks are
 // numbered from unit_base and split among r_stride waves like rounds.
 constexpr int kLongSeg = 256;
 constexpr int kVec = 8;
@@ -144,22 +146,23 @@ __device__ __forceinline__ void stream_segment(const int32_t *__restrict__ ri, c
   for (int64_t blk = b0; blk < nblk; blk += r_stride) {
     const int e0 = (int)blk * kBlk + l;
     int32_t row[kVec];
-    double val[kVec];
+    VT raw[kVec];
 #pragma unroll
     for (int t = 0; t < kVec; t++) {
       const int e = e0 + t * kWave;
       row[t] = 0;
-      val[t] = 0.0;
+      raw[t] = VT(0);
       if (e < len) {
         row[t] = ri[e];
-        if (VALUES) val[t] = (double)v[e] * scale;
+        if (VALUES) raw[t] = v[e];
       }
     }
 #pragma unroll
     for (int t = 0; t < kVec; t++) {
       if (e0 + t * kWave < len) {
-        if ((uint32_t)row[t] < m)
-          ins(row[t], val[t]);
+        const int32_t r = opaque(row[t]);
+        if ((uint32_t)r < m)
+          ins(r, VALUES ? (double)opaque(raw[t]) * scale : 0.0);
         else
           flag_error(status, 3);
       }
@@ -231,18 +234,18 @@ __device__ __forceinline__ void traverse_product(const ProductArgs<VT> &a, int64
       sc.off[l] = off - excl;
       if (VALUES) sc.scale[l] = b;
       wave_sync();
-      flatten_rounds(
+      int oob = 0;
+      flatten_rounds<VT>(
           ls, excl, total, sc.mark, rounds_before, r_rank, r_stride, (uint32_t)a.m, status,
-          [&](int o, int e, int32_t &row, double &v) {
+          [&](int o, int e, int32_t &row, VT &raw) {
             int64_t q = sc.off[o] + e;
-            if ((uint64_t)q >= (uint64_t)a.nnzA) {
-              flag_error(status, 5);
-              q = 0;  // row 0 of a bounded read; the status word records the fault
-            }
+            oob |= (uint64_t)q >= (uint64_t)a.nnzA ? 1 : 0;
+            q = (uint64_t)q >= (uint64_t)a.nnzA ? 0 : q;  // a bounded read; the status word records the fault
             row = a.Ari[q];
-            if (VALUES) v = (double)a.Av[q] * sc.scale[o];
+            if (VALUES) raw = a.Av[q];
           },
-          ins);
+          [&](int o, VT raw) { return VALUES ? (double)raw * sc.scale[o] : 0.0; }, ins);
+      if (__ballot(oob) && l == 0) flag_error(status, 5);
       rounds_before += (total + kWave - 1) / kWave;
       wave_sync();
     }
@@ -315,13 +318,13 @@ __device__ __forceinline__ void traverse_merge(const PartDesc *P, int nparts, in
       sc.ri[l] = ri - excl;
       sc.v[l] = (const void *)(v - excl);
       wave_sync();
-      flatten_rounds(
+      flatten_rounds<VT>(
           ls, excl, total, sc.mark, rounds_before, r_rank, r_stride, (uint32_t)m, status,
-          [&](int o, int e, int32_t &row, double &v) {
+          [&](int o, int e, int32_t &row, VT &raw) {
             row = sc.ri[o][e];
-            v = (double)((const VT *)sc.v[o])[e];
+            raw = ((const VT *)sc.v[o])[e];
           },
-          ins);
+          [&](int, VT raw) { return (double)raw; }, ins);
       rounds_before += (total + kWave - 1) / kWave;
       wave_sync();
     }
@@ -684,8 +687,9 @@ __global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *l
 // ----------------------------------------------------------------------------
 template <class VT>
 __global__ __launch_bounds__(256) void k_slab_split(const int64_t *Acp, const int32_t *Ari, const VT *Av,
-                                                    int64_t klo, int64_t khi, int P, int32_t *soff,
-                                                    int32_t *s_ri, VT *s_v, const int32_t *heavy_count) {
+                                                    int64_t klo, int64_t khi, int64_t m, int P, int32_t *soff,
+                                                    int32_t *s_ri, VT *s_v, const int32_t *heavy_count,
+                                                    int32_t *status) {
   __shared__ int s_hist[4][kMaxSlabs + 1];
   const int w = threadIdx.x / kWave, l = lane();
   const int64_t k = klo + (int64_t)blockIdx.x * 4 + w;
@@ -694,10 +698,14 @@ __global__ __launch_bounds__(256) void k_slab_split(const int64_t *Acp, const in
   for (int t = l; t <= P; t += kWave) h[t] = 0;
   wave_sync();
   const int64_t a0 = Acp[k], a1 = Acp[k + 1];
+  bool bad = false;
   for (int64_t p = a0 + l; p < a1; p += kWave) {
-    const uint32_t sl = min((uint32_t)Ari[p] >> kSlabShift, (uint32_t)(P - 1));
+    const int32_t row = Ari[p];
+    bad |= row < 0 || row >= m;
+    const uint32_t sl = min((uint32_t)row >> kSlabShift, (uint32_t)(P - 1));
     atomicAdd(&h[sl], 1);
   }
+  if (__ballot(bad) && l == 0) flag_error(status, 3);
   wave_sync();
   int32_t *o = soff + (k - klo) * (int64_t)(P + 1);
   int carry = 0;
@@ -839,6 +847,156 @@ __global__ __launch_bounds__(kHvPlanThreads) void k_hv_plan(const int64_t *Bcp, 
   }
 }
 
+// Operands of the item kernels: the slabbed copy of A and B.  Rows of the
+// slabbed copy were checked against m by k_slab_split.
+template <class VT>
+struct HvArgs {
+  const int64_t *Acp;
+  const int32_t *Ari;  // slabbed rows
+  const VT *Av;        // slabbed values
+  const int64_t *Bcp;
+  const int32_t *Bri;
+  const VT *Bv;
+  const int32_t *off;  // [khi-klo][P+1] slab offsets
+  int64_t nnzA;
+  int32_t klo, khi, kdim, P;
+};
+
+// Visits the terms A(i,k) B(k,col) of k in B(:,col) with i in slabs
+// [sa, sb): ins(i, value).  Segment bounds are checked once per segment (the
+// element reads need no check); returns nonzero if an index was out of
+// range (that segment is skipped).  The nw waves of the workgroup split the
+// chunks of 64 entries of B(:,col) when there are at least 2*nw of them,
+// else they split the rounds of every chunk.  Short segments are flattened
+// into rounds of 64 elements (owner of each element from a ballot, or an LDS
+// marker and a max-scan when a segment starts inside the round), kPipe
+// rounds' gathers in flight; segments of kLongSeg or more elements are
+// streamed by the whole wave.
+template <class VT, class Ins>
+__device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t col, int sa, int sb, int w, int nw,
+                                           SegScratch &sc, Ins &&ins) {
+  const int l = lane();
+  const int64_t pbeg = a.Bcp[col], pend = a.Bcp[col + 1];
+  const int nchunk = (int)((pend - pbeg + kWave - 1) / kWave);
+  const bool csplit = nchunk >= 2 * nw;
+  const int c_rank = csplit ? w : 0, c_stride = csplit ? nw : 1;
+  const int r_rank = csplit ? 0 : w, r_stride = csplit ? 1 : nw;
+  int bad = 0;
+  int units = 0;  // rounds and long-segment blocks before the current chunk
+  for (int c = c_rank; c < nchunk; c += c_stride) {
+    const int64_t p = pbeg + (int64_t)c * kWave + l;
+    int len = 0;
+    int64_t off = 0;
+    double b = 0.0;
+    if (p < pend) {
+      const int32_t k = a.Bri[p];
+      if (k >= a.klo && k < a.khi) {
+        const int32_t *o = a.off + (int64_t)(k - a.klo) * (a.P + 1);
+        const int32_t s0 = o[sa], s1 = o[sb];
+        const int64_t a0 = a.Acp[k];
+        b = (double)a.Bv[p];
+        off = a0 + s0;
+        len = s1 - s0;
+        if (len < 0 || len >= kMaxAdeg || off < 0 || off + len > a.nnzA) {
+          bad = 1;
+          len = 0;
+          off = 0;
+        }
+      } else if (k < 0 || k >= a.kdim) {
+        bad = 1;
+      }
+    }
+    const bool lg = len >= kLongSeg;
+    const int ls = lg ? 0 : len;
+    const int incl = wave_incl_add(ls);
+    const int excl = incl - ls;
+    const int total = readlane(incl, 63);
+    if (total > 0) {
+      sc.off[l] = off - excl;
+      sc.scale[l] = b;
+      wave_sync();
+      int r0 = (r_rank - units) % r_stride;
+      if (r0 < 0) r0 += r_stride;
+      for (int r = r0; r * kWave < total; r += kPipe * r_stride) {
+        int own_[kPipe];
+#pragma unroll
+        for (int u = 0; u < kPipe; u++) {
+          const int fb = (r + u * r_stride) * kWave;
+          own_[u] = -1;
+          if (fb < total) {
+            const int last = min(fb + kWave - 1, total - 1);
+            const uint64_t started = __ballot(ls > 0 && excl <= fb);
+            const int carry = started ? 64 - __clzll((long long)started) : 0;
+            int own;
+            if (__ballot(ls > 0 && excl <= last) == started) {
+              own = carry;
+            } else {
+              if (ls > 0 && excl > fb && excl < fb + kWave) sc.mark[excl - fb] = l + 1;
+              wave_sync();
+              const int mk = sc.mark[l];
+              sc.mark[l] = 0;
+              own = max(wave_incl_max(mk), carry);
+              wave_sync();
+            }
+            if (fb + l < total) own_[u] = own - 1;
+          }
+        }
+        // gathers only; the loaded values are used after every load is issued
+        int64_t q_[kPipe];
+#pragma unroll
+        for (int u = 0; u < kPipe; u++) q_[u] = sc.off[max(own_[u], 0)] + (r + u * r_stride) * kWave + l;
+        int32_t row_[kPipe];
+        VT raw_[kPipe];
+#pragma unroll
+        for (int u = 0; u < kPipe; u++) {
+          row_[u] = 0;
+          raw_[u] = VT(0);
+          if (own_[u] >= 0) {
+            row_[u] = a.Ari[q_[u]];
+            raw_[u] = a.Av[q_[u]];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kPipe; u++)
+          if (own_[u] >= 0) ins(opaque(row_[u]), (double)opaque(raw_[u]) * sc.scale[own_[u]]);
+      }
+      units += (total + kWave - 1) / kWave;
+      wave_sync();
+    }
+    uint64_t lm = __ballot(lg);
+    while (lm) {
+      const int L = __builtin_ctzll(lm);
+      lm &= lm - 1;
+      const int64_t so = readlane64(off, L);
+      const int sn = readlane(len, L);
+      const double sbv = readlane_f64(b, L);
+      const int nblk = (sn + kBlk - 1) / kBlk;
+      int b0 = (r_rank - units) % r_stride;
+      if (b0 < 0) b0 += r_stride;
+      for (int blk = b0; blk < nblk; blk += r_stride) {
+        const int e0 = blk * kBlk + l;
+        int32_t row[kVec];
+        VT raw[kVec];
+#pragma unroll
+        for (int t = 0; t < kVec; t++) {
+          const int e = e0 + t * kWave;
+          row[t] = 0;
+          raw[t] = VT(0);
+          if (e < sn) {
+            row[t] = a.Ari[so + e];
+            raw[t] = a.Av[so + e];
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < kVec; t++)
+          if (e0 + t * kWave < sn) ins(opaque(row[t]), (double)opaque(raw[t]) * sbv);
+      }
+      units += nblk;
+    }
+  }
+  return bad;
+}
+
 // Items: persistent workgroups take items from a queue (the next index is
 // fetched while the current item runs).  A dense item accumulates slab sa in
 // a float64 array of kSlabRows rows plus an occupancy bitmap; a hash item
@@ -848,10 +1006,10 @@ __global__ __launch_bounds__(kHvPlanThreads) void k_hv_plan(const int64_t *Bcp, 
 constexpr int kHvThreads = 256;
 
 template <class VT>
-__global__ __launch_bounds__(kHvThreads) void k_hv_items(ProductArgs<VT> sa, SlabSel sel, int64_t c0,
-                                                         const int32_t *list, const uint2 *items, WsHeader *hdr,
-                                                         int64_t item_cap, const int64_t *c_colptr, int32_t *hv_cur,
-                                                         int32_t *out_ri, VT *out_v) {
+__global__ __launch_bounds__(kHvThreads) void k_hv_items(HvArgs<VT> a, int64_t c0, const int32_t *list,
+                                                         const uint2 *items, WsHeader *hdr, int64_t item_cap,
+                                                         const int64_t *c_colptr, int32_t *hv_cur, int32_t *out_ri,
+                                                         VT *out_v) {
   constexpr int NW = kHvThreads / kWave;
   constexpr int kWords = (int)(kSlabRows / 32);
   constexpr int kPer = kHvSlots / kHvThreads;
@@ -877,7 +1035,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(ProductArgs<VT> sa, Sla
     const int h = (int)rec.x;
     const int sa0 = (int)(rec.y & 0xfffu), sb0 = (int)((rec.y >> 12) & 0xfffu);
     const bool dense = ((rec.y >> 24) & 1u) != 0;
-    if (h < 0 || h >= nheavy || sa0 >= sb0 || sb0 > sel.P || (dense && sb0 != sa0 + 1)) {
+    if (h < 0 || h >= nheavy || sa0 >= sb0 || sb0 > a.P || (dense && sb0 != sa0 + 1)) {
       if (threadIdx.x == 0) flag_error(status, 9);
       __syncthreads();
       it = s_next;
@@ -885,71 +1043,68 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(ProductArgs<VT> sa, Sla
     }
     const int64_t jj = list[h];
     const int64_t col = c0 + jj;
-    SlabSel g = sel;
-    g.sa = sa0;
-    g.sb = sb0;
+    int bad;
+    int c = 0;
+    uint32_t word = 0;
+    const uint32_t rb = (uint32_t)sa0 << kSlabShift;
+    double *acc = (double *)s_tab;
+    uint32_t *bits = (uint32_t *)(s_tab + kSlabRows * 8);
+    int32_t *keys = (int32_t *)s_tab;
+    double *vals = (double *)(s_tab + kHvSlots * 4);
     if (dense) {
-      double *acc = (double *)s_tab;
-      uint32_t *bits = (uint32_t *)(s_tab + kSlabRows * 8);
       for (int q = threadIdx.x; q < (int)kSlabRows; q += kHvThreads) acc[q] = 0.0;
       if (threadIdx.x < kWords) bits[threadIdx.x] = 0u;
       __syncthreads();
-      const int64_t rb = (int64_t)sa0 << kSlabShift;
-      traverse_product_block<true, VT, true>(sa, col, w, NW, s_sc[w], status, [&](int32_t row, double v) {
-        const uint64_t r = (uint64_t)((int64_t)row - rb);
-        if (r < (uint64_t)kSlabRows) {
+      int outside = 0;
+      bad = hv_traverse<VT>(a, col, sa0, sb0, w, NW, s_sc[w], [&](int32_t row, double v) {
+        const uint32_t r = (uint32_t)row - rb;
+        if (r < (uint32_t)kSlabRows) {
           atomicAdd(&acc[r], v);
           atomicOr(&bits[r >> 5], 1u << (r & 31));
         } else {
-          flag_error(status, 6);
+          outside = 1;
         }
-      }, g);
+      });
+      bad |= outside;
       __syncthreads();
-      const uint32_t word = threadIdx.x < kWords ? bits[threadIdx.x] : 0u;
-      int total;
-      const int ex = block_excl<NW>(__popc(word), s_w, total);
-      if (threadIdx.x == 0) s_pos = total ? atomicAdd(&hv_cur[h], total) : 0;
-      __syncthreads();
-      const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
-      if ((int64_t)s_pos + total > cap) {
-        if (threadIdx.x == 0) flag_error(status, 4);
-      } else {
-        int64_t o = base + s_pos + ex;
-        uint32_t bw = word;
-        while (bw) {
-          const int b = __ffs(bw) - 1;
-          bw &= bw - 1;
-          const int r = (int)threadIdx.x * 32 + b;
-          out_ri[o] = (int32_t)(rb + r);
-          out_v[o] = (VT)acc[r];
-          o++;
-        }
-      }
+      word = threadIdx.x < kWords ? bits[threadIdx.x] : 0u;
+      c = __popc(word);
     } else {
-      int32_t *keys = (int32_t *)s_tab;
-      double *vals = (double *)(s_tab + kHvSlots * 4);
       for (int q = threadIdx.x; q < kHvSlots; q += kHvThreads) {
         keys[q] = kEmpty;
         vals[q] = 0.0;
       }
       __syncthreads();
-      traverse_product_block<true, VT, true>(sa, col, w, NW, s_sc[w], status, [&](int32_t row, double v) {
+      bad = hv_traverse<VT>(a, col, sa0, sb0, w, NW, s_sc[w], [&](int32_t row, double v) {
         ht_accumulate(keys, vals, kHvSlots, row, v);
-      }, g);
+      });
       __syncthreads();
       const int q0 = (int)threadIdx.x * kPer;
-      int c = 0;
 #pragma unroll
       for (int i = 0; i < kPer; i++) c += keys[q0 + i] != kEmpty ? 1 : 0;
-      int total;
-      const int ex = block_excl<NW>(c, s_w, total);
-      if (threadIdx.x == 0) s_pos = total ? atomicAdd(&hv_cur[h], total) : 0;
-      __syncthreads();
-      const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
-      if ((int64_t)s_pos + total > cap) {
-        if (threadIdx.x == 0) flag_error(status, 4);
+    }
+    if (__ballot(bad) && l == 0) flag_error(status, 5);
+    int total;
+    const int ex = block_excl<NW>(c, s_w, total);
+    if (threadIdx.x == 0) s_pos = total ? atomicAdd(&hv_cur[h], total) : 0;
+    __syncthreads();
+    const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
+    if ((int64_t)s_pos + total > cap) {
+      if (threadIdx.x == 0) flag_error(status, 4);
+    } else {
+      int64_t o = base + s_pos + ex;
+      if (dense) {
+        uint32_t bw = word;
+        while (bw) {
+          const int bi = __ffs(bw) - 1;
+          bw &= bw - 1;
+          const int r = (int)threadIdx.x * 32 + bi;
+          out_ri[o] = (int32_t)(rb + r);
+          out_v[o] = (VT)acc[r];
+          o++;
+        }
       } else {
-        int64_t o = base + s_pos + ex;
+        const int q0 = (int)threadIdx.x * kPer;
 #pragma unroll
         for (int i = 0; i < kPer; i++) {
           const int32_t key = keys[q0 + i];
@@ -1455,13 +1610,22 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
     if (khi > klo) {
       ProfScope prof("slab_split", st);
       hipLaunchKernelGGL(k_slab_split<VT>, dim3(grid_of(khi - klo, 4)), dim3(256), 0, st, A->colptr, A->rowidx,
-                         (const VT *)A->values, klo, khi, (int)L.P, soff, s_ri, s_v, hc);
+                         (const VT *)A->values, klo, khi, A->nrows, (int)L.P, soff, s_ri, s_v, hc, &hdr->status);
       LAUNCHCHK();
     }
-    ProductArgs<VT> sa = src.a;
-    sa.Ari = s_ri;
-    sa.Av = s_v;
-    SlabSel sel{soff, (int)L.P, 0, 0};
+    HvArgs<VT> ha;
+    ha.Acp = A->colptr;
+    ha.Ari = s_ri;
+    ha.Av = s_v;
+    ha.Bcp = B->colptr;
+    ha.Bri = B->rowidx;
+    ha.Bv = (const VT *)B->values;
+    ha.off = soff;
+    ha.nnzA = A->nnz;
+    ha.klo = (int32_t)klo;
+    ha.khi = (int32_t)khi;
+    ha.kdim = (int32_t)A->ncols;
+    ha.P = (int32_t)L.P;
     const int32_t *list = bins + (int64_t)(kNumBins - 1) * ncol;
     int32_t *hv_cur = (int32_t *)(ws + L.hv_cur);
     uint2 *items = (uint2 *)(ws + L.hv_items);
@@ -1483,7 +1647,7 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
         LAUNCHCHK();
       }
       ProfScope prof("heavy_items", st);
-      hipLaunchKernelGGL(k_hv_items<VT>, dim3(4 * device_cus()), dim3(kHvThreads), 0, st, sa, sel, c0, list,
+      hipLaunchKernelGGL(k_hv_items<VT>, dim3(4 * device_cus()), dim3(kHvThreads), 0, st, ha, c0, list,
                          (const uint2 *)items, hdr, icap, c_colptr, hv_cur, c_rowidx, (VT *)c_values);
       LAUNCHCHK();
     }
