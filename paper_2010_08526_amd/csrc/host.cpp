@@ -77,6 +77,8 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
         L->P = P;
         L->slab_off = off;
         off = align_up(off + sizeof(int32_t) * (size_t)(L->P + 1) * (size_t)A->ncols);
+        L->slab_offT = off;
+        off = align_up(off + sizeof(int32_t) * (size_t)(L->P + 1) * (size_t)A->ncols);
         L->slab_ri = off;
         off = align_up(off + sizeof(int32_t) * (size_t)A->nnz);
         L->slab_v = off;
@@ -84,7 +86,7 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
         L->hv_cur = off;
         off = align_up(off + sizeof(int32_t) * (size_t)ncol);
         L->hv_items = off;
-        off = align_up(off + 8 * (size_t)hv_item_cap(ncol, P));
+        off = align_up(off + 4 * (size_t)hv_item_cap(ncol, P));
       } else if ((op == SPGEMM_OP_NUMERIC || op == SPGEMM_OP_MERGE) && A->nrows > kNumCap[kNumBins - 2]) {
         L->slots = heavy_slots(A->nrows);
         L->nseg = (A->nrows + kHeavySeg - 1) / kHeavySeg;

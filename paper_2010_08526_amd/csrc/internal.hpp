@@ -60,10 +60,10 @@ constexpr uint64_t kHvItemBytes = uint64_t(64) << 20;  // item list of one chunk
 
 inline int64_t num_slabs(int64_t m) { return (m + kSlabRows - 1) / kSlabRows; }
 
-// Item list capacity (items of 8 bytes) for ncol columns and P slabs: a
-// chunk of heavy columns at most this many items over P covers them.
+// Slot table capacity (slots of 4 bytes) for ncol columns and P slabs: a
+// chunk of at most this many slots over P heavy columns is planned at once.
 inline int64_t hv_item_cap(int64_t ncol, int64_t P) {
-  const int64_t lim = (int64_t)(kHvItemBytes / 8);
+  const int64_t lim = (int64_t)(kHvItemBytes / 4);
   int64_t c = ncol * P;
   if (c > lim) c = lim;
   if (c < P) c = P;
@@ -105,8 +105,9 @@ struct WsLayout {
   size_t slab_off = 0;    // numeric: int32 [kcols][P+1] slab offsets of the left operand
   size_t slab_ri = 0;     // numeric: int32 [nnzA] slabbed rows
   size_t slab_v = 0;      // numeric: 8-byte [nnzA] slabbed values
+  size_t slab_offT = 0;   // numeric: int32 [P+1][kcols] the slab offsets, slab-major
   size_t hv_cur = 0;      // numeric: int32 [ncol] output cursor per heavy column
-  size_t hv_items = 0;    // numeric: uint2 [hv_item_cap] heavy items of one chunk
+  size_t hv_items = 0;    // numeric: uint32 [hv_item_cap] heavy item slots of one chunk
   int64_t P = 0;          // numeric: slabs (0 = heavy columns use global accumulators)
   size_t total = 0;
   int64_t slots = 0, nseg = 0, ncol = 0, m = 0;

@@ -730,11 +730,36 @@ __global__ __launch_bounds__(256) void k_slab_split(const int64_t *Acp, const in
   }
 }
 
+// Slab-major copy of the slab offsets: offT[s * kc + k] = off[k * (P+1) + s]
+// for s <= P and k < kc, through 64 x 64 tiles in LDS (both sides coalesced).
+__global__ __launch_bounds__(256) void k_off_transpose(const int32_t *off, int64_t kc, int P, int32_t *offT,
+                                                       const int32_t *heavy_count) {
+  __shared__ int32_t tile[64][65];
+  if (*heavy_count == 0) return;
+  const int64_t k0 = (int64_t)blockIdx.x * 64;
+  const int s0 = (int)blockIdx.y * 64;
+  const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
+  for (int r = ty; r < 64; r += 4) {  // rows k, columns s
+    const int64_t k = k0 + r;
+    const int sl = s0 + tx;
+    if (k < kc && sl <= P) tile[r][tx] = off[k * (P + 1) + sl];
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {  // rows s, columns k
+    const int sl = s0 + r;
+    const int64_t k = k0 + tx;
+    if (sl <= P && k < kc) offT[(int64_t)sl * kc + k] = tile[tx][r];
+  }
+}
+
 // Heavy columns: independent slab items (the constants are in internal.hpp).
-// An item is uint2 {x: position in the heavy list, y: slab range}; hv_enc
-// packs the range [sa, sb) and the dense flag.
+// The items of a chunk of Hc heavy columns live in a slot table
+// slots[hl * P + t] (hl = column within the chunk): nonzero iff an item of
+// that column starts at slab t; hv_enc packs its range [t, sb) and the dense
+// flag.  Every column has at most one item starting at each slab.
+constexpr uint32_t kHvValid = 1u << 31;
 __device__ __forceinline__ uint32_t hv_enc(int sa, int sb, bool dense) {
-  return (uint32_t)sa | ((uint32_t)sb << 12) | (dense ? (1u << 24) : 0u);
+  return kHvValid | (uint32_t)sa | ((uint32_t)sb << 12) | (dense ? (1u << 24) : 0u);
 }
 static_assert(kMaxSlabs < (1 << 12), "slab ids must fit 12 bits");
 
@@ -770,25 +795,24 @@ __global__ void k_hv_reset(WsHeader *h) {
 // a loop over B(:,col)).  Slabs are then cut into items in order: a slab
 // with F_s > kHvCap is a dense item, other slabs are joined while their
 // bounds add up to at most kHvCap (one hash item).  Wide columns (more than
-// kHvWideT entries in B(:,col)) make every slab a dense item.
+// kHvWideT entries in B(:,col)) make every slab a dense item.  The column's
+// P slots are written whole (zero where no item starts).
 constexpr int kHvPlanThreads = 256;
 
 __global__ __launch_bounds__(kHvPlanThreads) void k_hv_plan(const int64_t *Bcp, const int32_t *Bri, int64_t c0,
                                                             int64_t klo, int64_t khi, const int32_t *off, int P,
                                                             const int32_t *list, const int32_t *count_p, int64_t h0,
-                                                            int64_t h1, uint2 *items, int64_t item_cap,
-                                                            WsHeader *hdr) {
+                                                            int64_t h1, uint32_t *slots) {
   constexpr int NW = kHvPlanThreads / kWave;
   __shared__ int s_F[kMaxSlabs];
-  __shared__ uint32_t s_grp[kMaxSlabs];
-  __shared__ int s_ng, s_base;
+  __shared__ uint32_t s_slot[kMaxSlabs];
   const int w = threadIdx.x / kWave, l = lane();
   const int64_t count = min((int64_t)*count_p, h1);
-  int32_t *status = &hdr->status;
   for (int64_t h = h0 + blockIdx.x; h < count; h += gridDim.x) {
     const int64_t col = c0 + list[h];
     const int64_t pb = Bcp[col], pe = Bcp[col + 1];
     const bool wide = pe - pb > kHvWideT;
+    for (int t = threadIdx.x; t < P; t += kHvPlanThreads) s_slot[t] = 0u;
     if (!wide) {
       for (int sb = w * kWave; sb < P; sb += NW * kWave) {
         const int s = sb + l;
@@ -815,9 +839,8 @@ __global__ __launch_bounds__(kHvPlanThreads) void k_hv_plan(const int64_t *Bcp, 
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      int ng = 0;
       if (wide) {
-        for (int t = 0; t < P; t++) s_grp[ng++] = hv_enc(t, t + 1, true);
+        for (int t = 0; t < P; t++) s_slot[t] = hv_enc(t, t + 1, true);
       } else {
         int t = 0;
         while (t < P) {
@@ -825,24 +848,20 @@ __global__ __launch_bounds__(kHvPlanThreads) void k_hv_plan(const int64_t *Bcp, 
           if (f == 0) {
             t++;
           } else if (f > kHvCap) {
-            s_grp[ng++] = hv_enc(t, t + 1, true);
+            s_slot[t] = hv_enc(t, t + 1, true);
             t++;
           } else {
             int sum = f, t2 = t + 1;
             while (t2 < P && sum + s_F[t2] <= kHvCap) sum += s_F[t2++];
-            s_grp[ng++] = hv_enc(t, t2, false);
+            s_slot[t] = hv_enc(t, t2, false);
             t = t2;
           }
         }
       }
-      s_ng = ng;
-      s_base = ng ? atomicAdd(&hdr->items, ng) : 0;
-      if ((int64_t)s_base + ng > item_cap) flag_error(status, 9);
     }
     __syncthreads();
-    const int ng = s_ng, base = s_base;
-    if ((int64_t)base + ng <= item_cap)
-      for (int i = threadIdx.x; i < ng; i += kHvPlanThreads) items[base + i] = make_uint2((uint32_t)h, s_grp[i]);
+    uint32_t *dst = slots + (h - h0) * (int64_t)P;
+    for (int t = threadIdx.x; t < P; t += kHvPlanThreads) dst[t] = s_slot[t];
     __syncthreads();
   }
 }
@@ -857,7 +876,7 @@ struct HvArgs {
   const int64_t *Bcp;
   const int32_t *Bri;
   const VT *Bv;
-  const int32_t *off;  // [khi-klo][P+1] slab offsets
+  const int32_t *offT;  // [P+1][khi-klo] slab offsets, slab-major
   int64_t nnzA;
   int32_t klo, khi, kdim, P;
 };
@@ -891,8 +910,8 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t col, int
     if (p < pend) {
       const int32_t k = a.Bri[p];
       if (k >= a.klo && k < a.khi) {
-        const int32_t *o = a.off + (int64_t)(k - a.klo) * (a.P + 1);
-        const int32_t s0 = o[sa], s1 = o[sb];
+        const int64_t kc = a.khi - a.klo;
+        const int32_t s0 = a.offT[(int64_t)sa * kc + (k - a.klo)], s1 = a.offT[(int64_t)sb * kc + (k - a.klo)];
         const int64_t a0 = a.Acp[k];
         b = (double)a.Bv[p];
         off = a0 + s0;
@@ -997,19 +1016,23 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t col, int
   return bad;
 }
 
-// Items: persistent workgroups take items from a queue (the next index is
-// fetched while the current item runs).  A dense item accumulates slab sa in
-// a float64 array of kSlabRows rows plus an occupancy bitmap; a hash item
-// accumulates slabs [sa, sb) in a kHvSlots-slot table.  The item's rows are
-// appended to its column at a position reserved on the column's cursor
-// (dense items in row order, hash items in slot order).
+// Items: persistent workgroups take batches from a queue in slab-major
+// order: batch i covers slab t = i / nb of the chunk's columns
+// [64 (i % nb), 64 (i % nb) + 64), nb = ceil(Hc / 64), so that the
+// workgroups of the device work on the same few slabs of A at a time and
+// those slabs stay in L2.  The items of a batch (its nonzero slots) are
+// formed one after another by the whole workgroup.  A dense item accumulates
+// slab t in a float64 array of kSlabRows rows plus an occupancy bitmap; a
+// hash item accumulates slabs [t, sb) in a kHvSlots-slot table.  The item's
+// rows are appended to its column at a position reserved on the column's
+// cursor (dense items in row order, hash items in slot order).
 constexpr int kHvThreads = 256;
 
 template <class VT>
 __global__ __launch_bounds__(kHvThreads) void k_hv_items(HvArgs<VT> a, int64_t c0, const int32_t *list,
-                                                         const uint2 *items, WsHeader *hdr, int64_t item_cap,
-                                                         const int64_t *c_colptr, int32_t *hv_cur, int32_t *out_ri,
-                                                         VT *out_v) {
+                                                         const uint32_t *slots, int64_t h0, int64_t hc,
+                                                         WsHeader *hdr, const int64_t *c_colptr, int32_t *hv_cur,
+                                                         int32_t *out_ri, VT *out_v) {
   constexpr int NW = kHvThreads / kWave;
   constexpr int kWords = (int)(kSlabRows / 32);
   constexpr int kPer = kHvSlots / kHvThreads;
@@ -1019,105 +1042,127 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(HvArgs<VT> a, int64_t c
   __shared__ __align__(16) unsigned char s_tab[kSlabRows * 8 + kSlabRows / 8];
   __shared__ SegScratch s_sc[NW];
   __shared__ int s_w[NW];
-  __shared__ int s_next, s_pos;
+  __shared__ int s_batch, s_pos;
+  __shared__ uint32_t s_e[kWave];
+  __shared__ int32_t s_jj[kWave];
+  __shared__ unsigned long long s_mask;
   const int w = threadIdx.x / kWave, l = lane();
   int32_t *status = &hdr->status;
-  const int nitems = (int)min((int64_t)hdr->items, item_cap);
-  const int nheavy = hdr->bin_count[kNumBins - 1];
+  const int P = a.P;
+  const int64_t nheavy = hdr->bin_count[kNumBins - 1];
+  const int64_t nb = (hc + kWave - 1) / kWave;
+  const int64_t nbatch = nb * P;
   s_sc[w].mark[l] = 0;
-  if (threadIdx.x == 0) s_next = atomicAdd(&hdr->item_cursor, 1);
-  __syncthreads();
-  int it = s_next;
-  while (it < nitems) {
-    __syncthreads();  // every thread has taken s_next
-    if (threadIdx.x == 0) s_next = atomicAdd(&hdr->item_cursor, 1);
-    const uint2 rec = items[it];
-    const int h = (int)rec.x;
-    const int sa0 = (int)(rec.y & 0xfffu), sb0 = (int)((rec.y >> 12) & 0xfffu);
-    const bool dense = ((rec.y >> 24) & 1u) != 0;
-    if (h < 0 || h >= nheavy || sa0 >= sb0 || sb0 > a.P || (dense && sb0 != sa0 + 1)) {
-      if (threadIdx.x == 0) flag_error(status, 9);
-      __syncthreads();
-      it = s_next;
-      continue;
-    }
-    const int64_t jj = list[h];
-    const int64_t col = c0 + jj;
-    int bad;
-    int c = 0;
-    uint32_t word = 0;
-    const uint32_t rb = (uint32_t)sa0 << kSlabShift;
-    double *acc = (double *)s_tab;
-    uint32_t *bits = (uint32_t *)(s_tab + kSlabRows * 8);
-    int32_t *keys = (int32_t *)s_tab;
-    double *vals = (double *)(s_tab + kHvSlots * 4);
-    if (dense) {
-      for (int q = threadIdx.x; q < (int)kSlabRows; q += kHvThreads) acc[q] = 0.0;
-      if (threadIdx.x < kWords) bits[threadIdx.x] = 0u;
-      __syncthreads();
-      int outside = 0;
-      bad = hv_traverse<VT>(a, col, sa0, sb0, w, NW, s_sc[w], [&](int32_t row, double v) {
-        const uint32_t r = (uint32_t)row - rb;
-        if (r < (uint32_t)kSlabRows) {
-          atomicAdd(&acc[r], v);
-          atomicOr(&bits[r >> 5], 1u << (r & 31));
-        } else {
-          outside = 1;
-        }
-      });
-      bad |= outside;
-      __syncthreads();
-      word = threadIdx.x < kWords ? bits[threadIdx.x] : 0u;
-      c = __popc(word);
-    } else {
-      for (int q = threadIdx.x; q < kHvSlots; q += kHvThreads) {
-        keys[q] = kEmpty;
-        vals[q] = 0.0;
-      }
-      __syncthreads();
-      bad = hv_traverse<VT>(a, col, sa0, sb0, w, NW, s_sc[w], [&](int32_t row, double v) {
-        ht_accumulate(keys, vals, kHvSlots, row, v);
-      });
-      __syncthreads();
-      const int q0 = (int)threadIdx.x * kPer;
-#pragma unroll
-      for (int i = 0; i < kPer; i++) c += keys[q0 + i] != kEmpty ? 1 : 0;
-    }
-    if (__ballot(bad) && l == 0) flag_error(status, 5);
-    int total;
-    const int ex = block_excl<NW>(c, s_w, total);
-    if (threadIdx.x == 0) s_pos = total ? atomicAdd(&hv_cur[h], total) : 0;
+  double *acc = (double *)s_tab;
+  uint32_t *bits = (uint32_t *)(s_tab + kSlabRows * 8);
+  int32_t *keys = (int32_t *)s_tab;
+  double *vals = (double *)(s_tab + kHvSlots * 4);
+  for (;;) {
+    __syncthreads();  // the previous batch's s_batch, s_e, s_jj, s_mask are no longer read
+    if (threadIdx.x == 0) s_batch = atomicAdd(&hdr->item_cursor, 1);
     __syncthreads();
-    const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
-    if ((int64_t)s_pos + total > cap) {
-      if (threadIdx.x == 0) flag_error(status, 4);
-    } else {
-      int64_t o = base + s_pos + ex;
+    const int64_t bi = s_batch;
+    if (bi >= nbatch) break;
+    const int t = (int)(bi / nb);
+    const int64_t hb = (bi % nb) * kWave;
+    if (w == 0) {
+      const int64_t hl = hb + l;
+      uint32_t e = 0u;
+      int32_t jj = 0;
+      if (hl < hc && h0 + hl < nheavy) {
+        e = slots[hl * P + t];
+        jj = list[h0 + hl];
+      }
+      const uint64_t mk = __ballot((e & kHvValid) != 0u);
+      s_e[l] = e;
+      s_jj[l] = jj;
+      if (l == 0) s_mask = mk;
+    }
+    __syncthreads();
+    uint64_t mask = s_mask;
+    while (mask) {
+      const int j = __builtin_ctzll(mask);
+      mask &= mask - 1;
+      const uint32_t e = s_e[j];
+      const int64_t jj = s_jj[j];
+      const int sb0 = (int)((e >> 12) & 0xfffu);
+      const bool dense = ((e >> 24) & 1u) != 0;
+      if ((int)(e & 0xfffu) != t || sb0 <= t || sb0 > P || (dense && sb0 != t + 1)) {
+        if (threadIdx.x == 0) flag_error(status, 9);
+        continue;
+      }
+      const int64_t col = c0 + jj;
+      const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
+      int bad;
+      int c = 0;
+      uint32_t word = 0;
+      const uint32_t rb = (uint32_t)t << kSlabShift;
       if (dense) {
-        uint32_t bw = word;
-        while (bw) {
-          const int bi = __ffs(bw) - 1;
-          bw &= bw - 1;
-          const int r = (int)threadIdx.x * 32 + bi;
-          out_ri[o] = (int32_t)(rb + r);
-          out_v[o] = (VT)acc[r];
-          o++;
-        }
+        for (int q = threadIdx.x; q < (int)kSlabRows; q += kHvThreads) acc[q] = 0.0;
+        if (threadIdx.x < kWords) bits[threadIdx.x] = 0u;
+        __syncthreads();
+        int outside = 0;
+        bad = hv_traverse<VT>(a, col, t, sb0, w, NW, s_sc[w], [&](int32_t row, double v) {
+          const uint32_t r = (uint32_t)row - rb;
+          if (r < (uint32_t)kSlabRows) {
+            atomicAdd(&acc[r], v);
+            atomicOr(&bits[r >> 5], 1u << (r & 31));
+          } else {
+            outside = 1;
+          }
+        });
+        bad |= outside;
+        __syncthreads();
+        word = threadIdx.x < kWords ? bits[threadIdx.x] : 0u;
+        c = __popc(word);
       } else {
+        for (int q = threadIdx.x; q < kHvSlots; q += kHvThreads) {
+          keys[q] = kEmpty;
+          vals[q] = 0.0;
+        }
+        __syncthreads();
+        bad = hv_traverse<VT>(a, col, t, sb0, w, NW, s_sc[w], [&](int32_t row, double v) {
+          ht_accumulate(keys, vals, kHvSlots, row, v);
+        });
+        __syncthreads();
         const int q0 = (int)threadIdx.x * kPer;
 #pragma unroll
-        for (int i = 0; i < kPer; i++) {
-          const int32_t key = keys[q0 + i];
-          if (key != kEmpty) {
-            out_ri[o] = key;
-            out_v[o] = (VT)vals[q0 + i];
+        for (int i = 0; i < kPer; i++) c += keys[q0 + i] != kEmpty ? 1 : 0;
+      }
+      if (__ballot(bad) && l == 0) flag_error(status, 5);
+      int total;
+      const int ex = block_excl<NW>(c, s_w, total);
+      if (threadIdx.x == 0) s_pos = total ? atomicAdd(&hv_cur[jj], total) : 0;
+      __syncthreads();
+      if ((int64_t)s_pos + total > cap) {
+        if (threadIdx.x == 0) flag_error(status, 4);
+      } else {
+        int64_t o = base + s_pos + ex;
+        if (dense) {
+          uint32_t bw = word;
+          while (bw) {
+            const int bj = __ffs(bw) - 1;
+            bw &= bw - 1;
+            const int r = (int)threadIdx.x * 32 + bj;
+            out_ri[o] = (int32_t)(rb + r);
+            out_v[o] = (VT)acc[r];
             o++;
+          }
+        } else {
+          const int q0 = (int)threadIdx.x * kPer;
+#pragma unroll
+          for (int i = 0; i < kPer; i++) {
+            const int32_t key = keys[q0 + i];
+            if (key != kEmpty) {
+              out_ri[o] = key;
+              out_v[o] = (VT)vals[q0 + i];
+              o++;
+            }
           }
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
-    it = s_next;
   }
 }
 
@@ -1127,7 +1172,7 @@ __global__ void k_hv_check(const int32_t *list, const int32_t *count_p, const in
   const int count = *count_p;
   for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < count; h += gridDim.x * blockDim.x) {
     const int64_t jj = list[h];
-    if ((int64_t)hv_cur[h] != c_colptr[jj + 1] - c_colptr[jj]) flag_error(status, 4);
+    if ((int64_t)hv_cur[jj] != c_colptr[jj + 1] - c_colptr[jj]) flag_error(status, 4);
   }
 }
 
@@ -1612,6 +1657,9 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
       hipLaunchKernelGGL(k_slab_split<VT>, dim3(grid_of(khi - klo, 4)), dim3(256), 0, st, A->colptr, A->rowidx,
                          (const VT *)A->values, klo, khi, A->nrows, (int)L.P, soff, s_ri, s_v, hc, &hdr->status);
       LAUNCHCHK();
+      hipLaunchKernelGGL(k_off_transpose, dim3(grid_of(khi - klo, 64), (unsigned)((L.P + 1 + 63) / 64)), dim3(256),
+                         0, st, (const int32_t *)soff, khi - klo, (int)L.P, (int32_t *)(ws + L.slab_offT), hc);
+      LAUNCHCHK();
     }
     HvArgs<VT> ha;
     ha.Acp = A->colptr;
@@ -1620,7 +1668,7 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
     ha.Bcp = B->colptr;
     ha.Bri = B->rowidx;
     ha.Bv = (const VT *)B->values;
-    ha.off = soff;
+    ha.offT = (const int32_t *)(ws + L.slab_offT);
     ha.nnzA = A->nnz;
     ha.klo = (int32_t)klo;
     ha.khi = (int32_t)khi;
@@ -1628,7 +1676,7 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
     ha.P = (int32_t)L.P;
     const int32_t *list = bins + (int64_t)(kNumBins - 1) * ncol;
     int32_t *hv_cur = (int32_t *)(ws + L.hv_cur);
-    uint2 *items = (uint2 *)(ws + L.hv_items);
+    uint32_t *slots = (uint32_t *)(ws + L.hv_items);
     const int64_t icap = hv_item_cap(ncol, L.P);
     const int64_t H = std::max<int64_t>(1, icap / L.P);
     const int64_t hmax = heavy > 0 ? heavy : ncol;  // heavy < 0: the count is only on the device
@@ -1643,12 +1691,12 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
         ProfScope prof("heavy_plan", st);
         const unsigned pg = (unsigned)std::min<int64_t>(h1 - h0, 16 * (int64_t)device_cus());
         hipLaunchKernelGGL(k_hv_plan, dim3(pg), dim3(kHvPlanThreads), 0, st, B->colptr, B->rowidx, c0, klo, khi,
-                           (const int32_t *)soff, (int)L.P, list, hc, h0, h1, items, icap, hdr);
+                           (const int32_t *)soff, (int)L.P, list, hc, h0, h1, slots);
         LAUNCHCHK();
       }
       ProfScope prof("heavy_items", st);
       hipLaunchKernelGGL(k_hv_items<VT>, dim3(4 * device_cus()), dim3(kHvThreads), 0, st, ha, c0, list,
-                         (const uint2 *)items, hdr, icap, c_colptr, hv_cur, c_rowidx, (VT *)c_values);
+                         (const uint32_t *)slots, h0, h1 - h0, hdr, c_colptr, hv_cur, c_rowidx, (VT *)c_values);
       LAUNCHCHK();
     }
     hipLaunchKernelGGL(k_hv_check, dim3(grid_of(hmax, 256)), dim3(256), 0, st, list, hc, c_colptr,
