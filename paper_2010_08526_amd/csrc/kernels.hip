@@ -891,6 +891,10 @@ struct HvArgs {
 // marker and a max-scan when a segment starts inside the round), kPipe
 // rounds' gathers in flight; segments of kLongSeg or more elements are
 // streamed by the whole wave.
+constexpr int kHvPipe = 4;
+constexpr int kHvVec = 4;
+constexpr int kHvBlk = kWave * kHvVec;
+
 template <class VT, class Ins>
 __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t col, int sa, int sb, int w, int nw,
                                            SegScratch &sc, Ins &&ins) {
@@ -936,10 +940,10 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t col, int
       wave_sync();
       int r0 = (r_rank - units) % r_stride;
       if (r0 < 0) r0 += r_stride;
-      for (int r = r0; r * kWave < total; r += kPipe * r_stride) {
-        int own_[kPipe];
+      for (int r = r0; r * kWave < total; r += kHvPipe * r_stride) {
+        int own_[kHvPipe];
 #pragma unroll
-        for (int u = 0; u < kPipe; u++) {
+        for (int u = 0; u < kHvPipe; u++) {
           const int fb = (r + u * r_stride) * kWave;
           own_[u] = -1;
           if (fb < total) {
@@ -961,13 +965,13 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t col, int
           }
         }
         // gathers only; the loaded values are used after every load is issued
-        int64_t q_[kPipe];
+        int64_t q_[kHvPipe];
 #pragma unroll
-        for (int u = 0; u < kPipe; u++) q_[u] = sc.off[max(own_[u], 0)] + (r + u * r_stride) * kWave + l;
-        int32_t row_[kPipe];
-        VT raw_[kPipe];
+        for (int u = 0; u < kHvPipe; u++) q_[u] = sc.off[max(own_[u], 0)] + (r + u * r_stride) * kWave + l;
+        int32_t row_[kHvPipe];
+        VT raw_[kHvPipe];
 #pragma unroll
-        for (int u = 0; u < kPipe; u++) {
+        for (int u = 0; u < kHvPipe; u++) {
           row_[u] = 0;
           raw_[u] = VT(0);
           if (own_[u] >= 0) {
@@ -976,7 +980,7 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t col, int
           }
         }
 #pragma unroll
-        for (int u = 0; u < kPipe; u++)
+        for (int u = 0; u < kHvPipe; u++)
           if (own_[u] >= 0) ins(opaque(row_[u]), (double)opaque(raw_[u]) * sc.scale[own_[u]]);
       }
       units += (total + kWave - 1) / kWave;
@@ -989,15 +993,15 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t col, int
       const int64_t so = readlane64(off, L);
       const int sn = readlane(len, L);
       const double sbv = readlane_f64(b, L);
-      const int nblk = (sn + kBlk - 1) / kBlk;
+      const int nblk = (sn + kHvBlk - 1) / kHvBlk;
       int b0 = (r_rank - units) % r_stride;
       if (b0 < 0) b0 += r_stride;
       for (int blk = b0; blk < nblk; blk += r_stride) {
-        const int e0 = blk * kBlk + l;
-        int32_t row[kVec];
-        VT raw[kVec];
+        const int e0 = blk * kHvBlk + l;
+        int32_t row[kHvVec];
+        VT raw[kHvVec];
 #pragma unroll
-        for (int t = 0; t < kVec; t++) {
+        for (int t = 0; t < kHvVec; t++) {
           const int e = e0 + t * kWave;
           row[t] = 0;
           raw[t] = VT(0);
@@ -1007,7 +1011,7 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t col, int
           }
         }
 #pragma unroll
-        for (int t = 0; t < kVec; t++)
+        for (int t = 0; t < kHvVec; t++)
           if (e0 + t * kWave < sn) ins(opaque(row[t]), (double)opaque(raw[t]) * sbv);
       }
       units += nblk;
