@@ -77,8 +77,8 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
         L->P = P;
         L->slab_off = off;
         off = align_up(off + sizeof(int32_t) * (size_t)(L->P + 1) * (size_t)A->ncols);
-        L->slab_offT = off;
-        off = align_up(off + sizeof(int32_t) * (size_t)(L->P + 1) * (size_t)A->ncols);
+        L->slab_pack = off;
+        off = align_up(off + sizeof(uint64_t) * (size_t)L->P * (size_t)A->ncols);
         L->slab_ri = off;
         off = align_up(off + sizeof(int32_t) * (size_t)A->nnz);
         L->slab_v = off;

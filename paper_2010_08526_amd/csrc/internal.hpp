@@ -53,6 +53,7 @@ constexpr int kSlabShift = 12;
 constexpr int64_t kSlabRows = int64_t(1) << kSlabShift;
 constexpr int kMaxSlabs = 2048;  // rows up to kMaxSlabs * kSlabRows use slabs
 constexpr uint64_t kMaxSlabOffBytes = uint64_t(8) << 30;  // cap on the slab offset table
+constexpr int kSegLenBits = kSlabShift + 1;  // a segment of one slab holds at most kSlabRows entries
 constexpr int kHvSlots = 2560;
 constexpr int kHvCap = kHvSlots / 2;
 constexpr int64_t kHvWideT = 1024;
@@ -105,7 +106,7 @@ struct WsLayout {
   size_t slab_off = 0;    // numeric: int32 [kcols][P+1] slab offsets of the left operand
   size_t slab_ri = 0;     // numeric: int32 [nnzA] slabbed rows
   size_t slab_v = 0;      // numeric: 8-byte [nnzA] slabbed values
-  size_t slab_offT = 0;   // numeric: int32 [P+1][kcols] the slab offsets, slab-major
+  size_t slab_pack = 0;   // numeric: uint64 [P][kcols] slab segments, slab-major (start << kSegLenBits | len)
   size_t hv_cur = 0;      // numeric: int32 [ncol] output cursor per heavy column
   size_t hv_items = 0;    // numeric: uint32 [hv_item_cap] heavy item slots of one chunk
   int64_t P = 0;          // numeric: slabs (0 = heavy columns use global accumulators)

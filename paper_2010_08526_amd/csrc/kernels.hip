@@ -730,25 +730,35 @@ __global__ __launch_bounds__(256) void k_slab_split(const int64_t *Acp, const in
   }
 }
 
-// Slab-major copy of the slab offsets: offT[s * kc + k] = off[k * (P+1) + s]
-// for s <= P and k < kc, through 64 x 64 tiles in LDS (both sides coalesced).
-__global__ __launch_bounds__(256) void k_off_transpose(const int32_t *off, int64_t kc, int P, int32_t *offT,
-                                                       const int32_t *heavy_count) {
-  __shared__ int32_t tile[64][65];
+// Slab-major segment table: pack[s * kc + k] describes the entries of
+// A(:,klo+k) in slab s as (absolute start << kSegLenBits) | length, so that
+// one 8-byte load gives a segment.  Built from the slab offsets through
+// 64 x 64 tiles in LDS (both sides coalesced).
+__global__ __launch_bounds__(256) void k_seg_pack(const int32_t *off, const int64_t *Acp, int64_t klo, int64_t kc,
+                                                  int P, uint64_t *pack, const int32_t *heavy_count) {
+  __shared__ int32_t tile[64][66];
+  __shared__ int64_t s_a0[64];
   if (*heavy_count == 0) return;
   const int64_t k0 = (int64_t)blockIdx.x * 64;
   const int s0 = (int)blockIdx.y * 64;
   const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
-  for (int r = ty; r < 64; r += 4) {  // rows k, columns s
+  for (int r = ty; r < 64; r += 4) {  // rows k, columns s (65 of them: s0 .. s0 + 64)
     const int64_t k = k0 + r;
-    const int sl = s0 + tx;
-    if (k < kc && sl <= P) tile[r][tx] = off[k * (P + 1) + sl];
+    if (k < kc) {
+      const int sl = s0 + tx;
+      if (sl <= P) tile[r][tx] = off[k * (P + 1) + sl];
+      if (tx == 0 && s0 + 64 <= P) tile[r][64] = off[k * (P + 1) + s0 + 64];
+    }
   }
+  if (threadIdx.x < 64 && k0 + threadIdx.x < kc) s_a0[threadIdx.x] = Acp[klo + k0 + threadIdx.x];
   __syncthreads();
   for (int r = ty; r < 64; r += 4) {  // rows s, columns k
     const int sl = s0 + r;
     const int64_t k = k0 + tx;
-    if (sl <= P && k < kc) offT[(int64_t)sl * kc + k] = tile[tx][r];
+    if (sl < P && k < kc) {
+      const int32_t b0 = tile[tx][r], b1 = tile[tx][r + 1];
+      pack[(int64_t)sl * kc + k] = ((uint64_t)(s_a0[tx] + b0) << kSegLenBits) | (uint64_t)(uint32_t)(b1 - b0);
+    }
   }
 }
 
@@ -876,7 +886,7 @@ struct HvArgs {
   const int64_t *Bcp;
   const int32_t *Bri;
   const VT *Bv;
-  const int32_t *offT;  // [P+1][khi-klo] slab offsets, slab-major
+  const uint64_t *pack;  // [P][khi-klo] slab segments (start << kSegLenBits | len), slab-major
   int64_t nnzA;
   int32_t klo, khi, kdim, P;
 };
@@ -915,12 +925,18 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t col, int
       const int32_t k = a.Bri[p];
       if (k >= a.klo && k < a.khi) {
         const int64_t kc = a.khi - a.klo;
-        const int32_t s0 = a.offT[(int64_t)sa * kc + (k - a.klo)], s1 = a.offT[(int64_t)sb * kc + (k - a.klo)];
-        const int64_t a0 = a.Acp[k];
+        constexpr uint64_t kLenMask = (uint64_t(1) << kSegLenBits) - 1;
+        const uint64_t g0 = a.pack[(int64_t)sa * kc + (k - a.klo)];
+        int64_t end = (int64_t)(g0 >> kSegLenBits) + (int64_t)(g0 & kLenMask);
+        if (sb != sa + 1) {  // uniform: a hash item over several slabs also needs its last slab
+          const uint64_t g1 = a.pack[(int64_t)(sb - 1) * kc + (k - a.klo)];
+          end = (int64_t)(g1 >> kSegLenBits) + (int64_t)(g1 & kLenMask);
+        }
         b = (double)a.Bv[p];
-        off = a0 + s0;
-        len = s1 - s0;
-        if (len < 0 || len >= kMaxAdeg || off < 0 || off + len > a.nnzA) {
+        off = (int64_t)(g0 >> kSegLenBits);
+        const int64_t d = end - off;
+        len = (int)min(max(d, (int64_t)-1), (int64_t)kMaxAdeg);
+        if (d < 0 || len >= kMaxAdeg || off < 0 || off + len > a.nnzA) {
           bad = 1;
           len = 0;
           off = 0;
@@ -1661,8 +1677,8 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
       hipLaunchKernelGGL(k_slab_split<VT>, dim3(grid_of(khi - klo, 4)), dim3(256), 0, st, A->colptr, A->rowidx,
                          (const VT *)A->values, klo, khi, A->nrows, (int)L.P, soff, s_ri, s_v, hc, &hdr->status);
       LAUNCHCHK();
-      hipLaunchKernelGGL(k_off_transpose, dim3(grid_of(khi - klo, 64), (unsigned)((L.P + 1 + 63) / 64)), dim3(256),
-                         0, st, (const int32_t *)soff, khi - klo, (int)L.P, (int32_t *)(ws + L.slab_offT), hc);
+      hipLaunchKernelGGL(k_seg_pack, dim3(grid_of(khi - klo, 64), (unsigned)((L.P + 63) / 64)), dim3(256), 0, st,
+                         (const int32_t *)soff, A->colptr, klo, khi - klo, (int)L.P, (uint64_t *)(ws + L.slab_pack), hc);
       LAUNCHCHK();
     }
     HvArgs<VT> ha;
@@ -1672,7 +1688,7 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
     ha.Bcp = B->colptr;
     ha.Bri = B->rowidx;
     ha.Bv = (const VT *)B->values;
-    ha.offT = (const int32_t *)(ws + L.slab_offT);
+    ha.pack = (const uint64_t *)(ws + L.slab_pack);
     ha.nnzA = A->nnz;
     ha.klo = (int32_t)klo;
     ha.khi = (int32_t)khi;
