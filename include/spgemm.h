@@ -283,6 +283,16 @@ int spgemm_profile_report(char *buf_host, size_t buf_bytes);
  * range.  Clears the word.  The only call here that blocks the host. */
 int spgemm_ws_status(void *ws, void *stream);
 
+/* As spgemm_ws_status; *code_host (may be NULL) receives the device-side
+ * code that was recorded first (0 if none): 1 an index of B(:,j) outside
+ * A's columns, 2 a column of A longer than 2^25 entries, 3 a row index
+ * outside [0, nrows), 4 a column whose entries disagree with its count from
+ * the symbolic pass, 5 column pointers inconsistent with the arrays they
+ * index, 7 a column above the largest LDS table in a call without a host
+ * synchronization, 8 an output larger than the capacity given, 9 a
+ * malformed internal work item. */
+int spgemm_ws_status_code(void *ws, void *stream, int32_t *code_host);
+
 /* Testing hook, process-wide, not thread-safe: from now on every column is
  * placed in bin `bin` or a later one (bins are ordered by table capacity,
  * 0 = smallest, 5 = heavy), so each kernel can be exercised on small

@@ -19,7 +19,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "_lib", "libspgemm.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_2010_08526_amd.build`")
+    raise ImportError(f"{LIB_PATH} is missing; build it with `python paper_2010_08526_amd/build.py`")
 _lib = ctypes.CDLL(LIB_PATH)
 
 # ---------------------------------------------------------------- constants
@@ -48,6 +48,7 @@ _lib.spgemm_colptr.argtypes = [_vp, _i64, _vp, _vp, _sz, _vp]
 _lib.spgemm_numeric.argtypes = [_P, _P, _i64, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.spgemm_merge.argtypes = [_P, _i32, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.spgemm_ws_status.argtypes = [_vp, _vp]
+_lib.spgemm_ws_status_code.argtypes = [_vp, _vp, _vp]
 _lib.spgemm_batched_forward.argtypes = [_P, _P, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.spgemm_batched_masked_xty.argtypes = [_P, _P, _P, _vp, _vp, _sz, _vp]
 _lib.spgemm_batched_backward.argtypes = [_P, _P, _P, _vp, _vp, _vp, _vp, _sz, _vp]
@@ -143,6 +144,7 @@ def alloc_workspace(nbytes: int, device=None) -> torch.Tensor:
     """A 256-byte aligned device buffer (torch's allocator aligns to 512)."""
     t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device or "cuda")
     assert t.data_ptr() % 256 == 0
+    t[:4096].zero_()  # header: no status recorded before the first call
     return t
 
 
@@ -189,8 +191,16 @@ def ws_status(ws: torch.Tensor, stream=None) -> int:
     return int(_lib.spgemm_ws_status(_ptr(ws), _stream(stream)))
 
 
+def ws_status_code(ws: torch.Tensor, stream=None) -> tuple[int, int]:
+    """(status, first device-side code) of a workspace; clears the code."""
+    code = ctypes.c_int32(0)
+    rc = int(_lib.spgemm_ws_status_code(_ptr(ws), _stream(stream), ctypes.byref(code)))
+    return rc, int(code.value)
+
+
 def check_ws(ws: torch.Tensor, where: str = "device check", stream=None):
-    _check(ws_status(ws, stream), where)
+    rc, code = ws_status_code(ws, stream)
+    _check(rc, f"{where} (device code {code})" if code else where)
 
 
 # ------------------------------------------------------------ batch driver

@@ -1,6 +1,8 @@
 """Builds the HIP shared library libspgemm.so for gfx950, in-tree.
 
-    python -m paper_2010_08526_amd.build
+    python paper_2010_08526_amd/build.py
+
+(run as a file: importing the package would load the library it rebuilds)
 
 hipcc compiles the kernels (kernels.hip) and the host-only part (host.cpp)
 into one shared object with a plain C ABI (include/spgemm.h).  Packed FP32

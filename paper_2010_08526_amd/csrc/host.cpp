@@ -72,13 +72,15 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
       }
       const bool numeric = op == SPGEMM_OP_NUMERIC || op == SPGEMM_OP_BATCHED_FORWARD;
       const int64_t P = num_slabs(A->nrows);
+      // columns of A one call reads: one layer of ceil(k / n_layers) columns
+      const int64_t kcols = (A->ncols + n_layers - 1) / n_layers;
       if (numeric && A->nrows > kNumCap[kNumBins - 2] && P <= kMaxSlabs &&
-          sizeof(int32_t) * (uint64_t)(P + 1) * (uint64_t)A->ncols <= kMaxSlabOffBytes) {
+          sizeof(int32_t) * (uint64_t)(P + 1) * (uint64_t)kcols <= kMaxSlabOffBytes) {
         L->P = P;
         L->slab_off = off;
-        off = align_up(off + sizeof(int32_t) * (size_t)(L->P + 1) * (size_t)A->ncols);
+        off = align_up(off + sizeof(int32_t) * (size_t)(L->P + 1) * (size_t)kcols);
         L->slab_pack = off;
-        off = align_up(off + sizeof(uint64_t) * (size_t)L->P * (size_t)A->ncols);
+        off = align_up(off + sizeof(uint64_t) * (size_t)L->P * (size_t)kcols);
         L->slab_ri = off;
         off = align_up(off + sizeof(int32_t) * (size_t)A->nnz);
         L->slab_v = off;

@@ -1968,17 +1968,21 @@ int spgemm_debug_min_bin(int32_t bin) {
   return SPGEMM_OK;
 }
 
-int spgemm_ws_status(void *ws, void *stream) {
+int spgemm_ws_status_code(void *ws, void *stream, int32_t *code_host) {
+  if (code_host) *code_host = 0;
   if (!ws) return SPGEMM_E_WORKSPACE;
   WsHeader h;
   hipStream_t s = (hipStream_t)stream;
   int rc = read_header((WsHeader *)ws, s, &h);
   if (rc) return rc;
   if (h.status != 0) {
+    if (code_host) *code_host = h.status;
     hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)ws, 1, 0);
     return SPGEMM_E_DEVICE;
   }
   return SPGEMM_OK;
 }
+
+int spgemm_ws_status(void *ws, void *stream) { return spgemm_ws_status_code(ws, stream, nullptr); }
 
 }  // extern "C"

@@ -38,3 +38,23 @@ def assert_matches(C, P, dtype, what=""):
 
 def to_dev(M, device="cuda"):
     return M.to(device)
+
+
+def budget_for_batches(S, eng, plan, nb: int) -> int:
+    """Smallest HBM budget for which the planner picks at most nb batches
+    (bisection over the memory left to outputs)."""
+    total = int((8 * plan.nnz_host[-1] + 8).sum()) * max(1, plan.nnz_host.shape[0] - 1)
+    lo, hi, best = total // (nb + 1) + 1, total, None
+    while lo <= hi:
+        mid = (lo + hi) // 2
+        try:
+            b, _ = S.plan_batches(plan.nnz_host.reshape(-1), eng.B.ncols, eng.L, eng.vbytes, 0, mid, 0)
+        except S.SpgemmError:
+            lo = mid + 1
+            continue
+        if len(b) - 1 > nb:
+            lo = mid + 1
+        else:
+            best, hi = mid, mid - 1
+    assert best is not None
+    return eng.input_bytes + eng.reserve_bytes + best
