@@ -1070,6 +1070,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(HvArgs<VT> a, int64_t c
   int32_t *status = &hdr->status;
   const int P = a.P;
   const int64_t nheavy = hdr->bin_count[kNumBins - 1];
+  hc = min(hc, max(nheavy - h0, (int64_t)0));  // the device count bounds a chunk sized on the host
   const int64_t nb = (hc + kWave - 1) / kWave;
   const int64_t nbatch = nb * P;
   s_sc[w].mark[l] = 0;
