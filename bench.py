@@ -13,7 +13,11 @@ Also reported on the same GPU (same accuracy bar as the tests):
             alone vs forward + backward (gradients of a loss on P(C)).
   batched : 4096 Erdos-Renyi pairs (n_i log-uniform in [256, 65536], 4-32
             per column) as one HIP-graph replay vs a loop of 4096 plain
-            calls (column ranges of the same packed product).
+            calls (column ranges of the same packed product); forward +
+            fused backward as one graph.
+  layered : protein-like n = 2,000,000, 16 inner-dimension layers merged
+            sort-free under a 64 GB budget: symbolic, numeric partials and
+            merge phases.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
@@ -47,9 +51,11 @@ def _parse():
     p.add_argument("--batches", type=int, default=4)
     p.add_argument("--er-n", type=int, default=262_144)
     p.add_argument("--batch-count", type=int, default=4096)
+    p.add_argument("--protein-n", type=int, default=2_000_000)
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--no-extras", action="store_true", help="skip the fwd_bwd and batched sections")
+    p.add_argument("--no-extras", action="store_true", help="skip the fwd_bwd, batched and layered sections")
+    p.add_argument("--extras", default="fwd_bwd,batched,layered", help="comma-separated extra sections to run")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain device copy of known size (to scale HBM byte counters) and exit")
     return p.parse_args()
@@ -247,6 +253,67 @@ def fwd_bwd(args, torch, np, S, synth):
     return out
 
 
+# ------------------------------------------------------- layered + merge
+def layered(args, torch, np, S, synth):
+    """protein2m: C = A A with the inner dimension split into 16 layers whose
+    partial products are merged sort-free, under a 64 GB HBM budget."""
+    dev = torch.device("cuda:0")
+    w = synth.WORKLOADS["protein2m"]
+    t0 = time.time()
+    A = synth.protein_like(args.protein_n, w.seed, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    log(f"protein-like n={A.ncols} nnz={A.nnz} generated in {time.time() - t0:.1f}s")
+    L = 16
+    eng = S.Engine(A, A, L, budget_bytes=64 * 10**9)
+    stream = torch.cuda.current_stream()
+
+    def step(marks):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        pl = eng.plan()
+        e1.record(stream)
+        marks.append(("symbolic_and_plan", e0, e1))
+        for i in range(pl.nbatches):
+            eng.run_batch(pl, i, marks=marks)
+        return pl
+
+    step([])
+    torch.cuda.synchronize()
+    eng.check()
+    marks = []
+    S.profile_enable(True)
+    t = time.perf_counter()
+    pl = step(marks)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t
+    prof = S.profile_report()
+    S.profile_enable(False)
+    eng.check()
+    ph = {}
+    for name, a, b in marks:
+        ph[name] = ph.get(name, 0.0) + a.elapsed_time(b)
+    flops = pl.total_flops
+    r = 8
+    nnz_d = int(pl.nnz_host[:L].sum())
+    nnz_c = int(pl.nnz_host[L].sum())
+    merge_bytes = r * nnz_d + r * nnz_c + 8 * (L + 1) * A.ncols
+    num_bytes = pl.nbatches * r * A.nnz + r * A.nnz + r * nnz_d + 8 * L * A.ncols
+    out = {"workload": f"protein{args.protein_n}: Chung-Lu power-law (2.1, mean 50, cap 5000), symmetric, "
+                       "column-stochastic fp32; C=A*A with 16 inner-dimension layers merged sort-free, 64 GB budget",
+           "n": A.ncols, "nnz_A": A.nnz, "flops": flops, "nnz_partials": nnz_d, "nnz_C": nnz_c,
+           "layers": L, "batches": pl.nbatches, "budget_bytes": 64 * 10**9,
+           "ms": round(t_total * 1e3, 3), "GFLOPs": round(2 * flops / t_total / 1e9, 2),
+           "phases_ms": {k: round(v, 3) for k, v in ph.items()},
+           "kernels_ms": {k: round(v[0], 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
+           "numeric_GBps_compulsory": round(num_bytes / (ph["numeric"] / 1e3) / 1e9, 2),
+           "merge_GBps_compulsory": round(merge_bytes / (ph["merge"] / 1e3) / 1e9, 2)}
+    log(f"layered: {pl.nbatches} batches, {t_total * 1e3:.1f} ms, phases " +
+        ", ".join(f"{k}={v:.1f}ms" for k, v in ph.items()) + "; kernels " +
+        ", ".join(f"{k}={v[0]:.1f}ms" for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])[:12]))
+    return out
+
+
 # ------------------------------------------------------- batched vs plain
 def batched(args, torch, np, S, synth):
     import paper_2010_08526_amd.batched as Bt
@@ -259,10 +326,15 @@ def batched(args, torch, np, S, synth):
     flops = int((spec.n * spec.dA * spec.dB).sum())
     log(f"batch: {args.batch_count} instances, sum n={int(spec.n.sum())}, nnz(A)={A.nnz}, flops={flops:.4e}, "
         f"generated in {time.time() - t0:.1f}s")
-    eng = Bt.BatchedEngine(A, B)
+    eng = Bt.BatchedEngine(A, B, backward=True)
     tune = Bt.autotune(eng, reps=1, use_cache=False)
-    eng.capture(eng.forward)
     reps = max(3, args.steps)
+    # forward and backward as one graph; dC = C (the loss 0.5*||C||^2 on P(C),
+    # so that no target array is needed next to the 120 GB of C)
+    g_fb = eng.capture(lambda: (eng.forward(), eng.backward(eng.values[:eng.nnz_c])))
+    t_graph_fb = _timed(g_fb.replay, reps, torch)
+    eng.check()
+    eng.capture(eng.forward)
     t_graph = _timed(eng.replay, reps, torch)
     eng.check()
     nnz_c = eng.nnz_c
@@ -293,8 +365,13 @@ def batched(args, torch, np, S, synth):
            "batched_graph_ms": round(t_graph * 1e3, 3), "batched_GFLOPs": round(2 * flops / t_graph / 1e9, 2),
            "plain_loop_ms": round(t_plain * 1e3, 3), "plain_loop_GFLOPs": round(2 * flops / t_plain / 1e9, 2),
            "speedup_batched_over_plain": round(t_plain / t_graph, 2),
+           "batched_fwd_bwd_graph_ms": round(t_graph_fb * 1e3, 3),
+           "batched_fwd_bwd_GFLOPs": round(6 * flops / t_graph_fb / 1e9, 2),
+           "fwd_bwd_over_fwd_time": round(t_graph_fb / t_graph, 3),
+           "fwd_bwd_note": "graph of forward + fused backward with dC = C; GFLOP/s counts 3x forward flops",
            "autotuned_caps": tune["caps"]}
-    log(f"batched: graph {t_graph * 1e3:.1f} ms vs plain loop {t_plain * 1e3:.1f} ms")
+    log(f"batched: graph {t_graph * 1e3:.1f} ms vs plain loop {t_plain * 1e3:.1f} ms; fwd+bwd graph "
+        f"{t_graph_fb * 1e3:.1f} ms")
     return out
 
 
@@ -395,10 +472,10 @@ def main():
     res, A = headline(args, torch, np, S, synth)
     torch.cuda.empty_cache()
     if not args.no_extras:
-        res["fwd_bwd"] = fwd_bwd(args, torch, np, S, synth)
-        torch.cuda.empty_cache()
-        res["batched"] = batched(args, torch, np, S, synth)
-        torch.cuda.empty_cache()
+        for name, fn in (("fwd_bwd", fwd_bwd), ("batched", batched), ("layered", layered)):
+            if name in args.extras.split(","):
+                res[name] = fn(args, torch, np, S, synth)
+                torch.cuda.empty_cache()
     res["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(A, args.cpu_seconds)
     print(json.dumps(res), flush=True)
 

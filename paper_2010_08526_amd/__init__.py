@@ -300,20 +300,33 @@ class Engine:
             self._bufs = bufs
         return self._bufs
 
-    def run_batch(self, plan: Plan, i: int, stream=None) -> CSC:
-        """Forms batch i; the returned CSC views buffers reused by the next call."""
+    def run_batch(self, plan: Plan, i: int, stream=None, marks=None) -> CSC:
+        """Forms batch i; the returned CSC views buffers reused by the next call.
+        With ``marks`` (a list), (phase, start_event, end_event) tuples are
+        appended for the numeric and merge phases (HIP events on the stream)."""
         A, B, L = self.A, self.B, self.L
+
+        def mark():
+            if marks is None:
+                return None
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(stream if isinstance(stream, torch.cuda.Stream) else torch.cuda.current_stream())
+            return e
         c0, c1 = plan.bounds[i], plan.bounds[i + 1]
         w = c1 - c0
         bufs = self._buffers(plan)
         ccp, cri, cv = bufs["ccp"][:w + 1], bufs["cri"], bufs["cv"]
         if L == 1:
+            e0 = mark()
             colptr(self.nnz[0, c0:c1], ccp, self.ws_scan, stream)
             numeric(A, B, c0, c1, 0, 1, self.flops[c0:c1], ccp, cri, cv, self.ws_num, stream)
+            if marks is not None:
+                marks.append(("numeric", e0, mark()))
             nnzc = int(plan.batch_nnz[i, 0])
         else:
             parts = []
             off = 0
+            e0 = mark()
             for l in range(L):
                 dcp = bufs["dcp"][l, :w + 1]
                 colptr(self.nnz[l, c0:c1], dcp, self.ws_scan, stream)
@@ -323,8 +336,12 @@ class Engine:
                 numeric(A, B, c0, c1, l, L, self.flops[c0:c1], dcp, dri, dv, self.ws_num, stream)
                 parts.append(CSC(A.nrows, w, dcp, dri, dv))
                 off += cnt
+            e1 = mark()
             colptr(self.nnz[L, c0:c1], ccp, self.ws_scan, stream)
             merge(parts, ccp, cri, cv, self.ws_mrg, stream)
+            if marks is not None:
+                marks.append(("numeric", e0, e1))
+                marks.append(("merge", e1, mark()))
             nnzc = int(plan.batch_nnz[i, L])
         return CSC(A.nrows, w, ccp, cri[:nnzc], cv[:nnzc])
 

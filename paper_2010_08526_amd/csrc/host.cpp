@@ -89,6 +89,33 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
         off = align_up(off + sizeof(int32_t) * (size_t)ncol);
         L->hv_items = off;
         off = align_up(off + 4 * (size_t)hv_item_cap(ncol, P));
+        L->hv_wide = off;
+        off = align_up(off + sizeof(int32_t) * (size_t)ncol);
+      } else if (op == SPGEMM_OP_MERGE && A->nrows > kNumCap[kNumBins - 2] && P <= kMaxSlabs) {
+        // heavy merge columns: slab buckets of up to kMbBucket entries
+        const int64_t icap = hv_item_cap(ncol, P);
+        const int64_t hcap = std::max<int64_t>(1, icap / P);
+        L->P = P;
+        // a column holds at most one entry per row and part
+        int64_t cap = std::min<int64_t>(kMbBucket, ncol);
+        cap = std::min<int64_t>(kMbBucket, cap * n_layers);
+        L->mb_cap = std::min<int64_t>(kMbBucket, cap * A->nrows);
+        L->mb_len = off;
+        off = align_up(off + sizeof(int64_t) * (size_t)ncol);
+        L->mb_base = off;
+        off = align_up(off + sizeof(int64_t) * (size_t)(ncol + 1));
+        L->scan = off;
+        off = align_up(off + sizeof(int64_t) * (size_t)(ncol / 8192 + 2));
+        L->slab_off = off;
+        off = align_up(off + sizeof(int32_t) * (size_t)hcap * (size_t)(P + 1));
+        L->hv_items = off;
+        off = align_up(off + 4 * (size_t)icap);
+        L->hv_cur = off;
+        off = align_up(off + sizeof(int32_t) * (size_t)ncol);
+        L->slab_ri = off;
+        off = align_up(off + sizeof(int32_t) * (size_t)L->mb_cap);
+        L->slab_v = off;
+        off = align_up(off + sizeof(double) * (size_t)L->mb_cap);
       } else if ((op == SPGEMM_OP_NUMERIC || op == SPGEMM_OP_MERGE) && A->nrows > kNumCap[kNumBins - 2]) {
         L->slots = heavy_slots(A->nrows);
         L->nseg = (A->nrows + kHeavySeg - 1) / kHeavySeg;

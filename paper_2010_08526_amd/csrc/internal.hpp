@@ -48,7 +48,8 @@ constexpr int kMaxAdeg = 1 << 25;  // per-column degree of the left operand hand
 // consecutive slabs whose flop bounds add up to at most kHvCap (an LDS hash
 // table of kHvSlots slots), or one slab whose bound exceeds kHvCap (a dense
 // LDS accumulator of kSlabRows rows).  Columns with more than kHvWideT
-// entries in B(:,j) skip the bounds: every slab is a dense item.
+// entries in B(:,j) skip the bounds: they are formed kHvWideSlabs slabs at a
+// time on a larger dense LDS accumulator (one workgroup per CU).
 constexpr int kSlabShift = 12;
 constexpr int64_t kSlabRows = int64_t(1) << kSlabShift;
 constexpr int kMaxSlabs = 2048;  // rows up to kMaxSlabs * kSlabRows use slabs
@@ -58,6 +59,7 @@ constexpr int kHvSlots = 2560;
 constexpr int kHvCap = kHvSlots / 2;
 constexpr int64_t kHvWideT = 1024;
 constexpr uint64_t kHvItemBytes = uint64_t(64) << 20;  // item list of one chunk of heavy columns
+constexpr int64_t kMbBucket = int64_t(1) << 28;  // merge: entries bucketed at once (heavy columns)
 
 inline int64_t num_slabs(int64_t m) { return (m + kSlabRows - 1) / kSlabRows; }
 
@@ -80,7 +82,8 @@ struct WsHeader {
   int32_t items;        // heavy items listed for the current chunk
   int32_t item_cursor;  // work-queue position over those items
   int32_t cursor[kNumBins];  // work-queue positions of the persistent kernels
-  int32_t pad2[2];
+  int32_t nwide;        // wide heavy columns listed for the current chunk
+  int32_t wide_cursor;  // work-queue position over their items
 };
 constexpr size_t kHeaderBytes = 4096;
 
@@ -109,6 +112,10 @@ struct WsLayout {
   size_t slab_pack = 0;   // numeric: uint64 [P][kcols] slab segments, slab-major (start << kSegLenBits | len)
   size_t hv_cur = 0;      // numeric: int32 [ncol] output cursor per heavy column
   size_t hv_items = 0;    // numeric: uint32 [hv_item_cap] heavy item slots of one chunk
+  size_t hv_wide = 0;     // numeric: int32 [ncol] wide heavy columns of one chunk
+  size_t mb_len = 0;      // merge: int64 [ncol] entries of every heavy column over the parts
+  size_t mb_base = 0;     // merge: int64 [ncol+1] their exclusive scan
+  int64_t mb_cap = 0;     // merge: entries of the bucket region (slab_ri / slab_v)
   int64_t P = 0;          // numeric: slabs (0 = heavy columns use global accumulators)
   size_t total = 0;
   int64_t slots = 0, nseg = 0, ncol = 0, m = 0;

@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "device.hpp"
@@ -351,6 +352,8 @@ __global__ void k_init_header(WsHeader *h, int keep_clean, int keep_status = 0) 
     for (int b = 0; b < kNumBins; b++) h->cursor[b] = 0;
     h->items = 0;
     h->item_cursor = 0;
+    h->nwide = 0;
+    h->wide_cursor = 0;
     if (!keep_clean) h->clean_tag = 0;
   }
 }
@@ -796,6 +799,8 @@ __global__ void k_hv_reset(WsHeader *h) {
   if (threadIdx.x == 0) {
     h->items = 0;
     h->item_cursor = 0;
+    h->nwide = 0;
+    h->wide_cursor = 0;
   }
 }
 
@@ -805,14 +810,15 @@ __global__ void k_hv_reset(WsHeader *h) {
 // a loop over B(:,col)).  Slabs are then cut into items in order: a slab
 // with F_s > kHvCap is a dense item, other slabs are joined while their
 // bounds add up to at most kHvCap (one hash item).  Wide columns (more than
-// kHvWideT entries in B(:,col)) make every slab a dense item.  The column's
-// P slots are written whole (zero where no item starts).
+// kHvWideT entries in B(:,col)) are listed for k_hv_wide instead.  The
+// column's P slots are written whole (zero where no item starts).
 constexpr int kHvPlanThreads = 256;
 
 __global__ __launch_bounds__(kHvPlanThreads) void k_hv_plan(const int64_t *Bcp, const int32_t *Bri, int64_t c0,
                                                             int64_t klo, int64_t khi, const int32_t *off, int P,
                                                             const int32_t *list, const int32_t *count_p, int64_t h0,
-                                                            int64_t h1, uint32_t *slots) {
+                                                            int64_t h1, uint32_t *slots, int32_t *wlist,
+                                                            WsHeader *hdr) {
   constexpr int NW = kHvPlanThreads / kWave;
   __shared__ int s_F[kMaxSlabs];
   __shared__ uint32_t s_slot[kMaxSlabs];
@@ -849,8 +855,8 @@ __global__ __launch_bounds__(kHvPlanThreads) void k_hv_plan(const int64_t *Bcp, 
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      if (wide) {
-        for (int t = 0; t < P; t++) s_slot[t] = hv_enc(t, t + 1, true);
+      if (wide) {  // formed by k_hv_wide: listed, no slots
+        wlist[atomicAdd(&hdr->nwide, 1)] = (int32_t)h;
       } else {
         int t = 0;
         while (t < P) {
@@ -895,7 +901,7 @@ struct HvArgs {
 // [sa, sb): ins(i, value).  Segment bounds are checked once per segment (the
 // element reads need no check); returns nonzero if an index was out of
 // range (that segment is skipped).  The nw waves of the workgroup split the
-// chunks of 64 entries of B(:,col) when there are at least 2*nw of them,
+// chunks of 64 entries of B(:,col) when there are at least cs_min*nw of them,
 // else they split the rounds of every chunk.  Short segments are flattened
 // into rounds of 64 elements (owner of each element from a ballot, or an LDS
 // marker and a max-scan when a segment starts inside the round), kPipe
@@ -907,11 +913,11 @@ constexpr int kHvBlk = kWave * kHvVec;
 
 template <class VT, class Ins>
 __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t col, int sa, int sb, int w, int nw,
-                                           SegScratch &sc, Ins &&ins) {
+                                           int cs_min, SegScratch &sc, Ins &&ins) {
   const int l = lane();
   const int64_t pbeg = a.Bcp[col], pend = a.Bcp[col + 1];
   const int nchunk = (int)((pend - pbeg + kWave - 1) / kWave);
-  const bool csplit = nchunk >= 2 * nw;
+  const bool csplit = nchunk >= cs_min * nw;
   const int c_rank = csplit ? w : 0, c_stride = csplit ? nw : 1;
   const int r_rank = csplit ? 0 : w, r_stride = csplit ? 1 : nw;
   int bad = 0;
@@ -1048,8 +1054,21 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t col, int
 // cursor (dense items in row order, hash items in slot order).
 constexpr int kHvThreads = 256;
 
+// Item source of the numeric pass: the product terms of column c0 + jj.
 template <class VT>
-__global__ __launch_bounds__(kHvThreads) void k_hv_items(HvArgs<VT> a, int64_t c0, const int32_t *list,
+struct HvProductSrc {
+  HvArgs<VT> a;
+  int64_t c0;
+  int P;
+  template <class Ins>
+  __device__ __forceinline__ int visit(int64_t jj, int64_t hl, int sa, int sb, int w, int nw, SegScratch &sc,
+                                       Ins &&ins) const {
+    return hv_traverse<VT>(a, c0 + jj, sa, sb, w, nw, 2, sc, ins);
+  }
+};
+
+template <class VT, class Src>
+__global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t *list,
                                                          const uint32_t *slots, int64_t h0, int64_t hc,
                                                          WsHeader *hdr, const int64_t *c_colptr, int32_t *hv_cur,
                                                          int32_t *out_ri, VT *out_v) {
@@ -1068,7 +1087,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(HvArgs<VT> a, int64_t c
   __shared__ unsigned long long s_mask;
   const int w = threadIdx.x / kWave, l = lane();
   int32_t *status = &hdr->status;
-  const int P = a.P;
+  const int P = src.P;
   const int64_t nheavy = hdr->bin_count[kNumBins - 1];
   hc = min(hc, max(nheavy - h0, (int64_t)0));  // the device count bounds a chunk sized on the host
   const int64_t nb = (hc + kWave - 1) / kWave;
@@ -1106,13 +1125,13 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(HvArgs<VT> a, int64_t c
       mask &= mask - 1;
       const uint32_t e = s_e[j];
       const int64_t jj = s_jj[j];
+      const int64_t hl = hb + j;
       const int sb0 = (int)((e >> 12) & 0xfffu);
       const bool dense = ((e >> 24) & 1u) != 0;
       if ((int)(e & 0xfffu) != t || sb0 <= t || sb0 > P || (dense && sb0 != t + 1)) {
         if (threadIdx.x == 0) flag_error(status, 9);
         continue;
       }
-      const int64_t col = c0 + jj;
       const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
       int bad;
       int c = 0;
@@ -1123,7 +1142,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(HvArgs<VT> a, int64_t c
         if (threadIdx.x < kWords) bits[threadIdx.x] = 0u;
         __syncthreads();
         int outside = 0;
-        bad = hv_traverse<VT>(a, col, t, sb0, w, NW, s_sc[w], [&](int32_t row, double v) {
+        bad = src.visit(jj, hl, t, sb0, w, NW, s_sc[w], [&](int32_t row, double v) {
           const uint32_t r = (uint32_t)row - rb;
           if (r < (uint32_t)kSlabRows) {
             atomicAdd(&acc[r], v);
@@ -1142,7 +1161,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(HvArgs<VT> a, int64_t c
           vals[q] = 0.0;
         }
         __syncthreads();
-        bad = hv_traverse<VT>(a, col, t, sb0, w, NW, s_sc[w], [&](int32_t row, double v) {
+        bad = src.visit(jj, hl, t, sb0, w, NW, s_sc[w], [&](int32_t row, double v) {
           ht_accumulate(keys, vals, kHvSlots, row, v);
         });
         __syncthreads();
@@ -1183,6 +1202,385 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(HvArgs<VT> a, int64_t c
         }
       }
       __syncthreads();
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Heavy merge columns.  The entries of column jj of all parts are bucketed
+// by row slab into the workspace (one workgroup per column: slab histogram,
+// scan, scatter), which gives the exact entries of every slab; slabs are cut
+// into items as in the numeric pass (a slab with more than kHvCap entries is a
+// dense item, other slabs are joined while their entries add up to at most
+// kHvCap) and every item accumulates one contiguous range of the bucket.  The
+// scatter fills each item's range through one cursor (entries of the item's
+// slabs interleave there), so a column writes few streams at a time.
+// ----------------------------------------------------------------------------
+__global__ void k_mb_len(const PartDesc *parts, int nparts, const int32_t *list, const int32_t *count_p,
+                         int64_t *len) {
+  const int count = *count_p;
+  for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < count; h += gridDim.x * blockDim.x) {
+    const int64_t jj = list[h];
+    int64_t sum = 0;
+    for (int p = 0; p < nparts; p++) sum += parts[p].cp[jj + 1] - parts[p].cp[jj];
+    len[h] = sum;
+  }
+}
+
+constexpr int kMbThreads = 1024;
+
+// Runs of equal slab ids across the lanes of a wavefront (sl < 0: no entry).
+// Lane l heads a run if l == 0 or lane l-1 holds another id; run_head_lane
+// gives the head of the lane's run, slab_run_head returns whether the lane
+// heads a run of a valid id and that run's length.
+__device__ __forceinline__ uint64_t run_heads(int sl) {
+  const int l = lane();
+  const int prev = __shfl_up(sl, 1, kWave);
+  return __ballot(l == 0 || prev != sl);
+}
+
+__device__ __forceinline__ int run_head_lane(int sl) {
+  const int l = lane();
+  const uint64_t upto = l == 63 ? ~0ull : ((2ull << l) - 1);
+  return 63 - __clzll((long long)(run_heads(sl) & upto));
+}
+
+__device__ __forceinline__ bool slab_run_head(int sl, int &len) {
+  const int l = lane();
+  const uint64_t heads = run_heads(sl);
+  const uint64_t upto = l == 63 ? ~0ull : ((2ull << l) - 1);
+  const uint64_t above = heads & ~upto;
+  const int next = above ? __builtin_ctzll(above) : kWave;
+  len = next - l;
+  return ((heads >> l) & 1ull) && sl >= 0;
+}
+
+// The entries of column jj over a group of parts as one index space of
+// 64-entry chunks: chunk q lies in part p with cpre[p] <= q < cpre[p+1].
+constexpr int kMbParts = 256;  // parts whose column ranges sit in LDS at once
+constexpr int kMbUnroll = 4;   // chunks whose loads a wave keeps in flight
+
+struct MbParts {
+  int64_t pb[kMbParts];
+  const int32_t *ri[kMbParts];
+  const void *v[kMbParts];
+  int cpre[kMbParts + 1];
+  int64_t plen[kMbParts];
+};
+
+// Loads the column ranges of parts [g0, g0 + n) for column jj (n <= kMbParts)
+// and the chunk prefix; returns the number of chunks.  Contains barriers.
+__device__ __forceinline__ int mb_load_parts(const PartDesc *parts, int g0, int n, int64_t jj, MbParts &mp,
+                                             int *s_w) {
+  constexpr int NW = kMbThreads / kWave;
+  const int t = threadIdx.x;
+  int nch = 0;
+  if (t < n) {
+    const PartDesc d = parts[g0 + t];
+    const int64_t a0 = d.cp[jj], a1 = d.cp[jj + 1];
+    mp.pb[t] = a0;
+    mp.ri[t] = d.ri;
+    mp.v[t] = d.v;
+    mp.plen[t] = max(a1 - a0, (int64_t)0);
+    nch = (int)((mp.plen[t] + kWave - 1) / kWave);
+  }
+  int total;
+  const int ex = block_excl<NW>(nch, s_w, total);
+  if (t < n) mp.cpre[t] = ex;
+  if (t == 0) mp.cpre[n] = total;
+  __syncthreads();
+  return total;
+}
+
+// Part of chunk q: the last p with cpre[p] <= q (binary search over n parts).
+__device__ __forceinline__ int mb_part_of(const MbParts &mp, int n, int q) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (mp.cpre[mid] <= q)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <class VT>
+__global__ __launch_bounds__(kMbThreads) void k_mb_bucket(const PartDesc *parts, int nparts, int64_t m, int P,
+                                                          const int32_t *list, const int32_t *count_p, int64_t h0,
+                                                          int64_t h1, const int64_t *base, int64_t ecap,
+                                                          int32_t *soff, int32_t *brow, VT *bval, uint32_t *slots,
+                                                          int32_t *status) {
+  constexpr int NW = kMbThreads / kWave;
+  constexpr int kPerT = kMaxSlabs / kMbThreads;
+  static_assert(kMaxSlabs % kMbThreads == 0, "slabs split evenly over threads");
+  static_assert(kMbParts <= kMbThreads, "one part per thread when loading ranges");
+  __shared__ int s_cnt[kMaxSlabs];
+  __shared__ int s_cur[kMaxSlabs];
+  __shared__ uint32_t s_slot[kMaxSlabs];
+  __shared__ int s_map[kMaxSlabs];  // slab -> first slab of its item
+  __shared__ int s_w[NW];
+  __shared__ MbParts s_mp;
+  const int w = threadIdx.x / kWave, l = lane();
+  const int64_t count = min((int64_t)*count_p, h1);
+  const int64_t b0 = base[h0];
+  for (int64_t h = h0 + blockIdx.x; h < count; h += gridDim.x) {
+    const int64_t jj = list[h];
+    const int64_t bb = base[h] - b0, elen = base[h + 1] - base[h];
+    for (int t = threadIdx.x; t < kMaxSlabs; t += kMbThreads) {
+      s_cnt[t] = 0;
+      s_slot[t] = 0u;
+    }
+    __syncthreads();
+    // ---- count entries per slab
+    bool bad = false;
+    for (int g0 = 0; g0 < nparts; g0 += kMbParts) {
+      const int n = min(kMbParts, nparts - g0);
+      const int nch = mb_load_parts(parts, g0, n, jj, s_mp, s_w);
+      for (int q0 = w; q0 < nch; q0 += NW * kMbUnroll) {
+        int32_t row_[kMbUnroll];
+        bool ok_[kMbUnroll];
+#pragma unroll
+        for (int u = 0; u < kMbUnroll; u++) {
+          const int q = q0 + u * NW;
+          row_[u] = 0;
+          ok_[u] = false;
+          if (q < nch) {
+            const int pp = mb_part_of(s_mp, n, q);
+            const int64_t off = (int64_t)(q - s_mp.cpre[pp]) * kWave + l;
+            if (off < s_mp.plen[pp]) {
+              row_[u] = s_mp.ri[pp][s_mp.pb[pp] + off];
+              ok_[u] = true;
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kMbUnroll; u++) {
+          if (q0 + u * NW >= nch) break;  // uniform
+          const int32_t row = opaque(row_[u]);
+          int sl = -1;
+          if (ok_[u]) {
+            if (row >= 0 && (int64_t)row < m)
+              sl = row >> kSlabShift;
+            else
+              bad = true;
+          }
+          int len;
+          if (slab_run_head(sl, len)) atomicAdd(&s_cnt[sl], len);
+        }
+      }
+      __syncthreads();  // s_mp is reloaded by the next group
+    }
+    if (__ballot(bad) && l == 0) flag_error(status, 3);
+    // exclusive scan over the slabs: thread t owns slabs [t*kPerT, (t+1)*kPerT)
+    int loc = 0;
+    for (int i = 0; i < kPerT; i++) loc += s_cnt[threadIdx.x * kPerT + i];
+    int total;
+    int run = block_excl<NW>(loc, s_w, total);
+    int32_t *so = soff + (h - h0) * (int64_t)(P + 1);
+    for (int i = 0; i < kPerT; i++) {
+      const int t = threadIdx.x * kPerT + i;
+      const int c = s_cnt[t];
+      s_cur[t] = run;
+      if (t < P) so[t] = run;
+      run += c;
+    }
+    if (threadIdx.x == 0) so[P] = total;
+    const bool fits = bb + total <= ecap && total <= elen;
+    if (threadIdx.x == 0 && !fits) flag_error(status, 9);
+    __syncthreads();
+    if (threadIdx.x == 0) {  // items in slab order
+      int t = 0;
+      while (t < P) {
+        const int f = s_cnt[t];
+        if (f == 0) {
+          s_map[t] = t;
+          t++;
+        } else if (f > kHvCap) {
+          s_slot[t] = hv_enc(t, t + 1, true);
+          s_map[t] = t;
+          t++;
+        } else {
+          int sum = f, t2 = t + 1;
+          while (t2 < P && sum + s_cnt[t2] <= kHvCap) sum += s_cnt[t2++];
+          s_slot[t] = hv_enc(t, t2, false);
+          for (int u = t; u < t2; u++) s_map[u] = t;
+          t = t2;
+        }
+      }
+    }
+    __syncthreads();
+    uint32_t *dst = slots + (h - h0) * (int64_t)P;
+    for (int t = threadIdx.x; t < P; t += kMbThreads) dst[t] = fits ? s_slot[t] : 0u;
+    // ---- scatter into the items' ranges
+    if (fits) {
+      for (int g0 = 0; g0 < nparts; g0 += kMbParts) {
+        const int n = min(kMbParts, nparts - g0);
+        const int nch = mb_load_parts(parts, g0, n, jj, s_mp, s_w);
+        for (int q0 = w; q0 < nch; q0 += NW * kMbUnroll) {
+          int32_t row_[kMbUnroll];
+          VT val_[kMbUnroll];
+          bool ok_[kMbUnroll];
+#pragma unroll
+          for (int u = 0; u < kMbUnroll; u++) {
+            const int q = q0 + u * NW;
+            row_[u] = 0;
+            val_[u] = VT(0);
+            ok_[u] = false;
+            if (q < nch) {
+              const int pp = mb_part_of(s_mp, n, q);
+              const int64_t off = (int64_t)(q - s_mp.cpre[pp]) * kWave + l;
+              if (off < s_mp.plen[pp]) {
+                row_[u] = s_mp.ri[pp][s_mp.pb[pp] + off];
+                val_[u] = ((const VT *)s_mp.v[pp])[s_mp.pb[pp] + off];
+                ok_[u] = true;
+              }
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kMbUnroll; u++) {
+            if (q0 + u * NW >= nch) break;  // uniform
+            const int32_t row = opaque(row_[u]);
+            int sl = -1;
+            if (ok_[u] && row >= 0 && (int64_t)row < m) sl = s_map[row >> kSlabShift];  // the item's range
+            int len;
+            int pos = 0;
+            if (slab_run_head(sl, len)) pos = atomicAdd(&s_cur[sl], len);
+            // every lane of a run takes the head's position plus its distance to the head
+            const int head = run_head_lane(sl);
+            pos = __shfl(pos, head, kWave) + (l - head);
+            if (sl >= 0) {
+              brow[bb + pos] = row;
+              bval[bb + pos] = opaque(val_[u]);
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Item source of the merge: the bucket range of the item's slabs.
+template <class VT>
+struct MbSrc {
+  const int32_t *brow;
+  const VT *bval;
+  const int32_t *soff;
+  const int64_t *base;
+  int64_t h0;
+  int P;
+  template <class Ins>
+  __device__ __forceinline__ int visit(int64_t, int64_t hl, int sa, int sb, int w, int nw, SegScratch &,
+                                       Ins &&ins) const {
+    const int32_t *so = soff + hl * (int64_t)(P + 1);
+    const int64_t bb = base[h0 + hl] - base[h0];
+    const int64_t e0 = bb + so[sa], e1 = bb + so[sb];
+    constexpr int kV = 4;
+    const int l = lane();
+    for (int64_t q0 = e0 + (int64_t)w * kWave * kV + l; q0 < e1; q0 += (int64_t)nw * kWave * kV) {
+      int32_t row[kV];
+      VT raw[kV];
+#pragma unroll
+      for (int t = 0; t < kV; t++) {
+        const int64_t q = q0 + t * kWave;
+        row[t] = 0;
+        raw[t] = VT(0);
+        if (q < e1) {
+          row[t] = brow[q];
+          raw[t] = bval[q];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < kV; t++)
+        if (q0 + t * kWave < e1) ins(opaque(row[t]), (double)opaque(raw[t]));
+    }
+    return 0;
+  }
+};
+
+// Wide heavy columns (more than kHvWideT entries in B(:,j)): items of
+// kHvWideSlabs consecutive slabs on one dense float64 array of kHvWideRows
+// rows (one workgroup of 16 waves per CU), so that the entries of B(:,j) are
+// visited once per kHvWideSlabs slabs.  Items are taken in slab-major order:
+// item i is slab group i / nw of the (i % nw)-th listed wide column.
+constexpr int kHvWideSlabs = 4;
+constexpr int64_t kHvWideRows = kSlabRows * kHvWideSlabs;
+constexpr int kHvWideThreads = 1024;
+
+template <class VT>
+__global__ __launch_bounds__(kHvWideThreads) void k_hv_wide(HvArgs<VT> a, int64_t c0, const int32_t *list,
+                                                            const int32_t *wlist, int64_t wcap, WsHeader *hdr,
+                                                            const int64_t *c_colptr, int32_t *hv_cur,
+                                                            int32_t *out_ri, VT *out_v) {
+  constexpr int NW = kHvWideThreads / kWave;
+  constexpr int kWords = (int)(kHvWideRows / 32);
+  static_assert(kWords <= kHvWideThreads, "one bitmap word per thread");
+  __shared__ double s_acc[kHvWideRows];
+  __shared__ uint32_t s_bits[kWords];
+  __shared__ SegScratch s_sc[NW];
+  __shared__ int s_w[NW];
+  __shared__ int s_item, s_pos;
+  const int w = threadIdx.x / kWave, l = lane();
+  int32_t *status = &hdr->status;
+  const int P = a.P;
+  const int64_t nheavy = hdr->bin_count[kNumBins - 1];
+  const int64_t nwide = min((int64_t)hdr->nwide, wcap);
+  const int64_t nq = (P + kHvWideSlabs - 1) / kHvWideSlabs;
+  const int64_t nitems = nwide * nq;
+  s_sc[w].mark[l] = 0;
+  for (;;) {
+    __syncthreads();  // s_item of the previous item is no longer read
+    if (threadIdx.x == 0) s_item = atomicAdd(&hdr->wide_cursor, 1);
+    __syncthreads();
+    const int64_t it = s_item;
+    if (it >= nitems) break;
+    const int q = (int)(it / nwide);
+    const int64_t h = wlist[it % nwide];
+    if (h < 0 || h >= nheavy) {
+      if (threadIdx.x == 0) flag_error(status, 9);
+      continue;
+    }
+    const int64_t jj = list[h];
+    const int64_t col = c0 + jj;
+    const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
+    const int sa = q * kHvWideSlabs, sb = min(sa + kHvWideSlabs, P);
+    const uint32_t rb = (uint32_t)sa << kSlabShift;
+    for (int r = threadIdx.x; r < (int)kHvWideRows; r += kHvWideThreads) s_acc[r] = 0.0;
+    if (threadIdx.x < kWords) s_bits[threadIdx.x] = 0u;
+    __syncthreads();
+    int outside = 0;
+    int bad = hv_traverse<VT>(a, col, sa, sb, w, NW, 1, s_sc[w], [&](int32_t row, double v) {
+      const uint32_t r = (uint32_t)row - rb;
+      if (r < (uint32_t)kHvWideRows) {
+        atomicAdd(&s_acc[r], v);
+        atomicOr(&s_bits[r >> 5], 1u << (r & 31));
+      } else {
+        outside = 1;
+      }
+    });
+    bad |= outside;
+    __syncthreads();
+    if (__ballot(bad) && l == 0) flag_error(status, 5);
+    const uint32_t word = threadIdx.x < kWords ? s_bits[threadIdx.x] : 0u;
+    int total;
+    const int ex = block_excl<NW>(__popc(word), s_w, total);
+    if (threadIdx.x == 0) s_pos = total ? atomicAdd(&hv_cur[jj], total) : 0;
+    __syncthreads();
+    if ((int64_t)s_pos + total > cap) {
+      if (threadIdx.x == 0) flag_error(status, 4);
+    } else {
+      int64_t o = base + s_pos + ex;
+      uint32_t bw = word;
+      while (bw) {
+        const int bj = __ffs(bw) - 1;
+        bw &= bw - 1;
+        const int r = (int)threadIdx.x * 32 + bj;
+        out_ri[o] = (int32_t)(rb + r);
+        out_v[o] = (VT)s_acc[r];
+        o++;
+      }
     }
   }
 }
@@ -1594,9 +1992,12 @@ static int accumulate_pass(const Src &src, const int *cnt, const WsHeader &h, co
   const int64_t ncol = L.ncol;
   static const char *kNumNames[kNumBins - 1] = {"num_wave64", "num_wave256", "num_wave1024", "num_block4096",
                                                 "num_block10240"};
+  static const char *kMrgNames[kNumBins - 1] = {"mrg_wave64", "mrg_wave256", "mrg_wave1024", "mrg_block4096",
+                                                "mrg_block10240"};
+  const char *const *names = std::is_same<Src, MergeSrc<VT>>::value ? kMrgNames : kNumNames;
   for (int b = 0; b < kNumBins - 1; b++) {
     if (cnt[b] == 0) continue;
-    ProfScope prof(kNumNames[b], st);
+    ProfScope prof(names[b], st);
     const int32_t *list = bins + (int64_t)b * ncol;
     const int32_t *cp = &hdr->bin_count[b];
     switch (b) {
@@ -1698,6 +2099,7 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
     const int32_t *list = bins + (int64_t)(kNumBins - 1) * ncol;
     int32_t *hv_cur = (int32_t *)(ws + L.hv_cur);
     uint32_t *slots = (uint32_t *)(ws + L.hv_items);
+    int32_t *wlist = (int32_t *)(ws + L.hv_wide);
     const int64_t icap = hv_item_cap(ncol, L.P);
     const int64_t H = std::max<int64_t>(1, icap / L.P);
     const int64_t hmax = heavy > 0 ? heavy : ncol;  // heavy < 0: the count is only on the device
@@ -1712,11 +2114,18 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
         ProfScope prof("heavy_plan", st);
         const unsigned pg = (unsigned)std::min<int64_t>(h1 - h0, 16 * (int64_t)device_cus());
         hipLaunchKernelGGL(k_hv_plan, dim3(pg), dim3(kHvPlanThreads), 0, st, B->colptr, B->rowidx, c0, klo, khi,
-                           (const int32_t *)soff, (int)L.P, list, hc, h0, h1, slots);
+                           (const int32_t *)soff, (int)L.P, list, hc, h0, h1, slots, wlist, hdr);
+        LAUNCHCHK();
+      }
+      {
+        ProfScope prof("heavy_wide", st);
+        hipLaunchKernelGGL(k_hv_wide<VT>, dim3(device_cus()), dim3(kHvWideThreads), 0, st, ha, c0, list,
+                           (const int32_t *)wlist, ncol, hdr, c_colptr, hv_cur, c_rowidx, (VT *)c_values);
         LAUNCHCHK();
       }
       ProfScope prof("heavy_items", st);
-      hipLaunchKernelGGL(k_hv_items<VT>, dim3(4 * device_cus()), dim3(kHvThreads), 0, st, ha, c0, list,
+      HvProductSrc<VT> hsrc{ha, c0, (int)L.P};
+      hipLaunchKernelGGL((k_hv_items<VT, HvProductSrc<VT>>), dim3(4 * device_cus()), dim3(kHvThreads), 0, st, hsrc, list,
                          (const uint32_t *)slots, h0, h1 - h0, hdr, c_colptr, hv_cur, c_rowidx, (VT *)c_values);
       LAUNCHCHK();
     }
@@ -1756,7 +2165,62 @@ static int merge_typed(const spgemm_csc *parts, int32_t n_parts, const int64_t *
   src.P = pd;
   src.nparts = n_parts;
   src.m = L.m;
-  return accumulate_pass<VT>(src, cnt, h, L, ws, c_colptr, c_rowidx, (VT *)c_values, st);
+  const int heavy = cnt[kNumBins - 1];
+  const bool buckets = L.P > 0 && heavy > 0;
+  rc = accumulate_pass<VT>(src, cnt, h, L, ws, c_colptr, c_rowidx, (VT *)c_values, st, !buckets);
+  if (rc || !buckets) return rc;
+  // heavy columns through the slab buckets
+  const int32_t *list = bins + (int64_t)(kNumBins - 1) * L.ncol;
+  const int32_t *hcnt = &hdr->bin_count[kNumBins - 1];
+  int64_t *len = (int64_t *)(ws + L.mb_len);
+  int64_t *base = (int64_t *)(ws + L.mb_base);
+  int32_t *soff = (int32_t *)(ws + L.slab_off);
+  uint32_t *slots = (uint32_t *)(ws + L.hv_items);
+  int32_t *hv_cur = (int32_t *)(ws + L.hv_cur);
+  int32_t *brow = (int32_t *)(ws + L.slab_ri);
+  VT *bval = (VT *)(ws + L.slab_v);
+  int32_t *status = &hdr->status;
+  hipLaunchKernelGGL(k_mb_len, dim3(grid_of(heavy, 256)), dim3(256), 0, st, (const PartDesc *)pd, n_parts, list, hcnt,
+                     len);
+  LAUNCHCHK();
+  rc = launch_colptr_scan(len, heavy, base, (int64_t *)(ws + L.scan), st);
+  if (rc) return rc;
+  std::vector<int64_t> hb((size_t)heavy + 1);
+  HIPCHK(hipMemcpyAsync(hb.data(), base, sizeof(int64_t) * (heavy + 1), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid_of((L.ncol * 4 + 15) / 16, 256)), dim3(256), 0, st, (uint4 *)hv_cur,
+                     (L.ncol * 4 + 15) / 16);
+  LAUNCHCHK();
+  const int64_t hcap = std::max<int64_t>(1, hv_item_cap(L.ncol, L.P) / L.P);
+  const int64_t ecap = L.mb_cap;
+  for (int64_t h0 = 0; h0 < heavy;) {
+    int64_t h1 = h0 + 1;
+    while (h1 < heavy && h1 - h0 < hcap && hb[h1 + 1] - hb[h0] <= ecap) h1++;
+    if (hb[h1] - hb[h0] > ecap) {  // one column's entries exceed the bucket region
+      hipLaunchKernelGGL(k_flag_if_nonzero, dim3(1), dim3(64), 0, st, hcnt, status, 9);
+      LAUNCHCHK();
+      return SPGEMM_OK;
+    }
+    hipLaunchKernelGGL(k_hv_reset, dim3(1), dim3(64), 0, st, hdr);
+    LAUNCHCHK();
+    {
+      ProfScope prof("merge_bucket", st);
+      const unsigned g = (unsigned)std::min<int64_t>(h1 - h0, 16 * (int64_t)device_cus());
+      hipLaunchKernelGGL(k_mb_bucket<VT>, dim3(g), dim3(kMbThreads), 0, st, (const PartDesc *)pd, n_parts, L.m,
+                         (int)L.P, list, hcnt, h0, h1, (const int64_t *)base, ecap, soff, brow, bval, slots, status);
+      LAUNCHCHK();
+    }
+    ProfScope prof("merge_items", st);
+    MbSrc<VT> msrc{brow, bval, soff, base, h0, (int)L.P};
+    hipLaunchKernelGGL((k_hv_items<VT, MbSrc<VT>>), dim3(4 * device_cus()), dim3(kHvThreads), 0, st, msrc, list,
+                       (const uint32_t *)slots, h0, h1 - h0, hdr, c_colptr, hv_cur, c_rowidx, (VT *)c_values);
+    LAUNCHCHK();
+    h0 = h1;
+  }
+  hipLaunchKernelGGL(k_hv_check, dim3(grid_of(heavy, 256)), dim3(256), 0, st, list, hcnt, c_colptr,
+                     (const int32_t *)hv_cur, status);
+  LAUNCHCHK();
+  return SPGEMM_OK;
 }
 
 static_assert(sizeof(PartDesc) == kPartDescBytes, "part descriptor size");

@@ -193,6 +193,31 @@ def test_layers_with_batches_protein_like():
     assert_matches(C, oracle.spgemm(A, A), torch.float32, "protein")
 
 
+@pytest.mark.parametrize("which", ["protein", "rmat", "rmat_many_parts"])
+def test_merge_heavy_buckets_forced(which):
+    """Every merge column through the heavy path (slab buckets, dense and hash
+    items); with 70 layers the parts span more than one chunk of 64."""
+    print(f"case: merge buckets {which}", flush=True)
+    if which == "protein":
+        A, L = synth.protein_like(20000, 23), 3
+    elif which == "rmat":
+        A, L = synth.rmat(13, 16, 29, dtype=torch.float32), 5
+    else:
+        A, L = synth.rmat(13, 16, 31, dtype=torch.float32), 70
+    Ad = A.to("cuda")
+    eng = S.Engine(Ad, Ad, L, None)
+    pl = eng.plan()  # symbolic in the natural bins
+    S._lib.spgemm_debug_min_bin(5)
+    C = []
+    for i in range(pl.nbatches):
+        Cb = eng.run_batch(pl, i)
+        C.append(synth.CSC(Cb.nrows, Cb.ncols, Cb.colptr.clone(), Cb.rowidx.clone(), Cb.values.clone()))
+    S._lib.spgemm_debug_min_bin(0)
+    eng.check()
+    Cc = S._concat(C, A.nrows)
+    assert_matches(Cc, oracle.spgemm(A, A), torch.float32, f"merge buckets {which}")
+
+
 def test_symbolic_column_range():
     print("case: column range", flush=True)
     A = synth.rmat(12, 16, 21, dtype=torch.float32)
