@@ -111,6 +111,15 @@ __device__ __forceinline__ int wave_flatten(int len, int *mark, Body &&body) {
   return total;
 }
 
+// Load through a pointer that addresses device (global) memory.  A pointer
+// read from LDS or from memory is generic to the compiler, which then emits
+// flat loads; those also count against the LDS wait counter, so every later
+// LDS access waits for them and loads meant to overlap do not.
+template <class T>
+__device__ __forceinline__ T ld_global(const T *p) {
+  return *(const __attribute__((address_space(1))) T *)p;
+}
+
 // Returns v unchanged, but the compiler cannot move a use of the result above
 // this point: a gathered value used only after every gather of a batch has
 // been issued keeps those loads in flight together (no wait between them).

@@ -154,8 +154,8 @@ __device__ __forceinline__ void stream_segment(const int32_t *__restrict__ ri, c
       row[t] = 0;
       raw[t] = VT(0);
       if (e < len) {
-        row[t] = ri[e];
-        if (VALUES) raw[t] = v[e];
+        row[t] = ld_global(ri + e);
+        if (VALUES) raw[t] = ld_global(v + e);
       }
     }
 #pragma unroll
@@ -300,8 +300,8 @@ __device__ __forceinline__ void traverse_merge(const PartDesc *P, int nparts, in
     const int32_t *ri = nullptr;
     const VT *v = nullptr;
     if (p < nparts) {
-      const int64_t a0 = P[p].cp[col];
-      const int64_t d = P[p].cp[col + 1] - a0;
+      const int64_t a0 = ld_global(P[p].cp + col);
+      const int64_t d = ld_global(P[p].cp + (col + 1)) - a0;
       if (d < 0 || d >= kMaxAdeg) {
         flag_error(status, 2);
       } else {
@@ -322,8 +322,8 @@ __device__ __forceinline__ void traverse_merge(const PartDesc *P, int nparts, in
       flatten_rounds<VT>(
           ls, excl, total, sc.mark, rounds_before, r_rank, r_stride, (uint32_t)m, status,
           [&](int o, int e, int32_t &row, VT &raw) {
-            row = sc.ri[o][e];
-            raw = ((const VT *)sc.v[o])[e];
+            row = ld_global(sc.ri[o] + e);
+            raw = ld_global((const VT *)sc.v[o] + e);
           },
           [&](int, VT raw) { return (double)raw; }, ins);
       rounds_before += (total + kWave - 1) / kWave;
@@ -1222,7 +1222,7 @@ __global__ void k_mb_len(const PartDesc *parts, int nparts, const int32_t *list,
   for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < count; h += gridDim.x * blockDim.x) {
     const int64_t jj = list[h];
     int64_t sum = 0;
-    for (int p = 0; p < nparts; p++) sum += parts[p].cp[jj + 1] - parts[p].cp[jj];
+    for (int p = 0; p < nparts; p++) sum += ld_global(parts[p].cp + (jj + 1)) - ld_global(parts[p].cp + jj);
     len[h] = sum;
   }
 }
@@ -1258,7 +1258,8 @@ __device__ __forceinline__ bool slab_run_head(int sl, int &len) {
 // The entries of column jj over a group of parts as one index space of
 // 64-entry chunks: chunk q lies in part p with cpre[p] <= q < cpre[p+1].
 constexpr int kMbParts = 256;  // parts whose column ranges sit in LDS at once
-constexpr int kMbUnroll = 4;   // chunks whose loads a wave keeps in flight
+constexpr int kMbUnroll = 4;   // chunks whose loads a wave keeps in flight (scatter)
+constexpr int kMbUnrollCount = 4;  // the same for the count pass (rows only)
 
 struct MbParts {
   int64_t pb[kMbParts];
@@ -1277,7 +1278,7 @@ __device__ __forceinline__ int mb_load_parts(const PartDesc *parts, int g0, int 
   int nch = 0;
   if (t < n) {
     const PartDesc d = parts[g0 + t];
-    const int64_t a0 = d.cp[jj], a1 = d.cp[jj + 1];
+    const int64_t a0 = ld_global(d.cp + jj), a1 = ld_global(d.cp + (jj + 1));
     mp.pb[t] = a0;
     mp.ri[t] = d.ri;
     mp.v[t] = d.v;
@@ -1306,7 +1307,7 @@ __device__ __forceinline__ int mb_part_of(const MbParts &mp, int n, int q) {
 }
 
 template <class VT>
-__global__ __launch_bounds__(kMbThreads) void k_mb_bucket(const PartDesc *parts, int nparts, int64_t m, int P,
+__global__ __launch_bounds__(kMbThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_mb_bucket(const PartDesc *parts, int nparts, int64_t m, int P,
                                                           const int32_t *list, const int32_t *count_p, int64_t h0,
                                                           int64_t h1, const int64_t *base, int64_t ecap,
                                                           int32_t *soff, int32_t *brow, VT *bval, uint32_t *slots,
@@ -1337,11 +1338,11 @@ __global__ __launch_bounds__(kMbThreads) void k_mb_bucket(const PartDesc *parts,
     for (int g0 = 0; g0 < nparts; g0 += kMbParts) {
       const int n = min(kMbParts, nparts - g0);
       const int nch = mb_load_parts(parts, g0, n, jj, s_mp, s_w);
-      for (int q0 = w; q0 < nch; q0 += NW * kMbUnroll) {
-        int32_t row_[kMbUnroll];
-        bool ok_[kMbUnroll];
+      for (int q0 = w; q0 < nch; q0 += NW * kMbUnrollCount) {
+        int32_t row_[kMbUnrollCount];
+        bool ok_[kMbUnrollCount];
 #pragma unroll
-        for (int u = 0; u < kMbUnroll; u++) {
+        for (int u = 0; u < kMbUnrollCount; u++) {
           const int q = q0 + u * NW;
           row_[u] = 0;
           ok_[u] = false;
@@ -1349,13 +1350,13 @@ __global__ __launch_bounds__(kMbThreads) void k_mb_bucket(const PartDesc *parts,
             const int pp = mb_part_of(s_mp, n, q);
             const int64_t off = (int64_t)(q - s_mp.cpre[pp]) * kWave + l;
             if (off < s_mp.plen[pp]) {
-              row_[u] = s_mp.ri[pp][s_mp.pb[pp] + off];
+              row_[u] = ld_global(s_mp.ri[pp] + (s_mp.pb[pp] + off));
               ok_[u] = true;
             }
           }
         }
 #pragma unroll
-        for (int u = 0; u < kMbUnroll; u++) {
+        for (int u = 0; u < kMbUnrollCount; u++) {
           if (q0 + u * NW >= nch) break;  // uniform
           const int32_t row = opaque(row_[u]);
           int sl = -1;
@@ -1389,24 +1390,44 @@ __global__ __launch_bounds__(kMbThreads) void k_mb_bucket(const PartDesc *parts,
     const bool fits = bb + total <= ecap && total <= elen;
     if (threadIdx.x == 0 && !fits) flag_error(status, 9);
     __syncthreads();
-    if (threadIdx.x == 0) {  // items in slab order
+    if (w == 0) {  // items in slab order, formed by one wave 64 slabs at a time
       int t = 0;
       while (t < P) {
-        const int f = s_cnt[t];
-        if (f == 0) {
-          s_map[t] = t;
-          t++;
-        } else if (f > kHvCap) {
-          s_slot[t] = hv_enc(t, t + 1, true);
-          s_map[t] = t;
-          t++;
-        } else {
-          int sum = f, t2 = t + 1;
-          while (t2 < P && sum + s_cnt[t2] <= kHvCap) sum += s_cnt[t2++];
-          s_slot[t] = hv_enc(t, t2, false);
-          for (int u = t; u < t2; u++) s_map[u] = t;
-          t = t2;
+        const int u = t + l;
+        const int c = u < P ? s_cnt[u] : 0;
+        const uint64_t nz = __ballot(c > 0);
+        if (nz == 0) {  // no entries in these slabs
+          t += kWave;
+          continue;
         }
+        const int f = __builtin_ctzll(nz);
+        if (f > 0) {  // skip to the next slab with entries
+          t += f;
+          continue;
+        }
+        const int ct = readlane(c, 0);
+        if (ct > kHvCap) {
+          if (l == 0) {
+            s_slot[t] = hv_enc(t, t + 1, true);
+            s_map[t] = t;
+          }
+          t++;
+          continue;
+        }
+        // hash item [t, t2): the longest run of slabs whose entries add up to at most kHvCap
+        const int e0 = s_cur[t];
+        int t2 = t;
+        for (;;) {
+          const int v = t2 + l;
+          const bool ok = v < P && s_cur[v] + s_cnt[v] - e0 <= kHvCap;
+          const uint64_t okm = __ballot(ok);  // a prefix of the lanes: the sums grow with v
+          const int n = __popcll(okm);
+          if (ok) s_map[v] = t;
+          t2 += n;
+          if (n < kWave) break;
+        }
+        if (l == 0) s_slot[t] = hv_enc(t, t2, false);
+        t = t2;
       }
     }
     __syncthreads();
@@ -1431,8 +1452,8 @@ __global__ __launch_bounds__(kMbThreads) void k_mb_bucket(const PartDesc *parts,
               const int pp = mb_part_of(s_mp, n, q);
               const int64_t off = (int64_t)(q - s_mp.cpre[pp]) * kWave + l;
               if (off < s_mp.plen[pp]) {
-                row_[u] = s_mp.ri[pp][s_mp.pb[pp] + off];
-                val_[u] = ((const VT *)s_mp.v[pp])[s_mp.pb[pp] + off];
+                row_[u] = ld_global(s_mp.ri[pp] + (s_mp.pb[pp] + off));
+                val_[u] = ld_global((const VT *)s_mp.v[pp] + (s_mp.pb[pp] + off));
                 ok_[u] = true;
               }
             }
@@ -1907,10 +1928,10 @@ __global__ __launch_bounds__(256) void k_pack(const PackDesc *d, int count, int6
                                               VT *v_out) {
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
     const PackDesc q = d[i];
-    for (int64_t j = threadIdx.x; j < q.ncols; j += 256) cp_out[q.col_off + j] = q.nnz_off + q.cp[j];
+    for (int64_t j = threadIdx.x; j < q.ncols; j += 256) cp_out[q.col_off + j] = q.nnz_off + ld_global(q.cp + j);
     for (int64_t p = threadIdx.x; p < q.nnz; p += 256) {
-      ri_out[q.nnz_off + p] = (int32_t)(q.row_off + q.ri[p]);
-      if (v_out) v_out[q.nnz_off + p] = ((const VT *)q.v)[p];
+      ri_out[q.nnz_off + p] = (int32_t)(q.row_off + ld_global(q.ri + p));
+      if (v_out) v_out[q.nnz_off + p] = ld_global((const VT *)q.v + p);
     }
   }
 }
