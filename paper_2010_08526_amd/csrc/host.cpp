@@ -126,6 +126,23 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
         L->heavy_segcnt = off;
         off = align_up(off + sizeof(int64_t) * (size_t)L->slots * (size_t)L->nseg);
       }
+      if ((op == SPGEMM_OP_SYMBOLIC || op == SPGEMM_OP_NUMERIC) && n_layers > 1) {
+        // the entries of B(:, c0:c1) in one inner-dimension layer, as a CSC matrix
+        if (B->nnz < 0) return SPGEMM_E_INVAL;
+        L->bl_cap = B->nnz;
+        L->bl_cnt = off;
+        off = align_up(off + sizeof(int64_t) * (size_t)ncol);
+        L->bl_cp = off;
+        off = align_up(off + sizeof(int64_t) * (size_t)(ncol + 1));
+        L->bl_scan = off;
+        off = align_up(off + sizeof(int64_t) * (size_t)(ncol / 8192 + 2));
+        L->bl_ri = off;
+        off = align_up(off + sizeof(int32_t) * (size_t)B->nnz);
+        if (op == SPGEMM_OP_NUMERIC) {
+          L->bl_v = off;
+          off = align_up(off + sizeof(double) * (size_t)B->nnz);
+        }
+      }
       if (op == SPGEMM_OP_BATCHED_FORWARD) {
         L->scan = off;
         off = align_up(off + sizeof(int64_t) * (size_t)(ncol / 8192 + 2));

@@ -116,6 +116,12 @@ struct WsLayout {
   size_t mb_len = 0;      // merge: int64 [ncol] entries of every heavy column over the parts
   size_t mb_base = 0;     // merge: int64 [ncol+1] their exclusive scan
   int64_t mb_cap = 0;     // merge: entries of the bucket region (slab_ri / slab_v)
+  size_t bl_cnt = 0;      // layers: int64 [ncol] entries of one layer per column
+  size_t bl_cp = 0;       // layers: int64 [ncol+1] column pointers of the layer's share of B
+  size_t bl_scan = 0;     // layers: int64 block sums of that scan
+  size_t bl_ri = 0;       // layers: int32 [nnz(B)] rows of the layer's share of B
+  size_t bl_v = 0;        // layers: 8-byte [nnz(B)] values (numeric only)
+  int64_t bl_cap = 0;     // layers: entries the two arrays hold (0 = no split)
   int64_t P = 0;          // numeric: slabs (0 = heavy columns use global accumulators)
   size_t total = 0;
   int64_t slots = 0, nseg = 0, ncol = 0, m = 0;

@@ -1871,6 +1871,95 @@ int launch_colptr_scan(const int64_t *counts, int64_t n, int64_t *out, int64_t *
 }
 
 
+// One inner-dimension layer of the right operand: the entries of
+// B(:, c0 + jj), jj < ncol, whose row k lies in [klo, khi), in their order, as
+// a CSC matrix over the call's columns (column jj).  The passes of a layer
+// then read only its share of B instead of skipping the other layers'
+// entries column by column.  Rows outside [0, kdim) set status 1.
+__global__ __launch_bounds__(256) void k_layer_count(const int64_t *Bcp, const int32_t *Bri, int64_t c0,
+                                                     int64_t ncol, int64_t klo, int64_t khi, int64_t kdim,
+                                                     int64_t *cnt, int32_t *status) {
+  const int w = threadIdx.x / kWave, l = lane();
+  for (int64_t jj = (int64_t)blockIdx.x * 4 + w; jj < ncol; jj += (int64_t)gridDim.x * 4) {
+    const int64_t p0 = Bcp[c0 + jj], p1 = Bcp[c0 + jj + 1];
+    int64_t c = 0;
+    bool bad = false;
+    for (int64_t b = p0; b < p1; b += kWave) {
+      const int64_t p = b + l;
+      bool in = false;
+      if (p < p1) {
+        const int32_t k = Bri[p];
+        in = k >= klo && k < khi;
+        bad |= k < 0 || k >= kdim;
+      }
+      c += __popcll(__ballot(in));
+    }
+    if (__ballot(bad) && l == 0) flag_error(status, 1);
+    if (l == 0) cnt[jj] = c;
+  }
+}
+
+template <class VT>
+__global__ __launch_bounds__(256) void k_layer_fill(const int64_t *Bcp, const int32_t *Bri, const VT *Bv,
+                                                    int64_t c0, int64_t ncol, int64_t klo, int64_t khi,
+                                                    const int64_t *cp, int64_t cap, int32_t *ri_out, VT *v_out,
+                                                    int32_t *status) {
+  const int w = threadIdx.x / kWave, l = lane();
+  for (int64_t jj = (int64_t)blockIdx.x * 4 + w; jj < ncol; jj += (int64_t)gridDim.x * 4) {
+    const int64_t p0 = Bcp[c0 + jj], p1 = Bcp[c0 + jj + 1];
+    int64_t o = cp[jj];
+    const int64_t e = cp[jj + 1];
+    if (o < 0 || e < o || e > cap) {  // more entries than B declares
+      if (l == 0) flag_error(status, 8);
+      continue;
+    }
+    for (int64_t b = p0; b < p1; b += kWave) {
+      const int64_t p = b + l;
+      int32_t k = -1;
+      if (p < p1) k = Bri[p];
+      const bool in = k >= klo && k < khi;
+      const uint64_t mask = __ballot(in);
+      const int64_t pos = o + mbcnt(mask);
+      if (in && pos < e) {
+        ri_out[pos] = k;
+        if (v_out) v_out[pos] = Bv[p];
+      }
+      o += __popcll(mask);
+    }
+  }
+}
+
+// Builds the layer's share of B (columns [c0, c0 + ncol), rows [klo, khi)) in
+// the workspace and describes it in *Bl (column jj of Bl is column c0 + jj
+// of B; nnz is the capacity, an upper bound).
+template <class VT>
+static int build_layer(const spgemm_csc *B, int64_t c0, int64_t ncol, int64_t klo, int64_t khi, int64_t kdim,
+                       bool values, const WsLayout &L, char *ws, hipStream_t st, spgemm_csc *Bl) {
+  WsHeader *hdr = (WsHeader *)ws;
+  int64_t *cnt = (int64_t *)(ws + L.bl_cnt);
+  int64_t *cp = (int64_t *)(ws + L.bl_cp);
+  {
+    ProfScope prof("layer_split", st);
+    hipLaunchKernelGGL(k_layer_count, dim3(grid_of(ncol, 4)), dim3(256), 0, st, B->colptr, B->rowidx, c0, ncol, klo,
+                       khi, kdim, cnt, &hdr->status);
+    LAUNCHCHK();
+    int rc = launch_colptr_scan(cnt, ncol, cp, (int64_t *)(ws + L.bl_scan), st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_layer_fill<VT>, dim3(grid_of(ncol, 4)), dim3(256), 0, st, B->colptr, B->rowidx,
+                       values ? (const VT *)B->values : (const VT *)nullptr, c0, ncol, klo, khi, (const int64_t *)cp,
+                       L.bl_cap, (int32_t *)(ws + L.bl_ri), values ? (VT *)(ws + L.bl_v) : (VT *)nullptr,
+                       &hdr->status);
+    LAUNCHCHK();
+  }
+  *Bl = *B;
+  Bl->ncols = ncol;
+  Bl->nnz = L.bl_cap;
+  Bl->colptr = cp;
+  Bl->rowidx = (const int32_t *)(ws + L.bl_ri);
+  Bl->values = values ? (const void *)(ws + L.bl_v) : nullptr;
+  return SPGEMM_OK;
+}
+
 template <class VT>
 static ProductArgs<VT> product_args(const spgemm_csc *A, const spgemm_csc *B, int64_t klo, int64_t khi) {
   ProductArgs<VT> a;
@@ -1956,10 +2045,10 @@ static int bin_counts(WsHeader *hdr, hipStream_t st, bool sync, int *cnt, WsHead
 // One symbolic pass over inner range [klo, khi) writing one row of counts.
 static int symbolic_pass(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t ncol, int64_t klo,
                          int64_t khi, int64_t *flops_out, int64_t *nnz_row, const WsLayout &L, char *ws,
-                         hipStream_t st, bool sync) {
+                         hipStream_t st, bool sync, bool keep_status = false) {
   WsHeader *hdr = (WsHeader *)ws;
   int32_t *bins = (int32_t *)(ws + L.bins);
-  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, 0, 0);
+  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, 0, keep_status ? 1 : 0);
   LAUNCHCHK();
   const int64_t per_block = 4 * kBinColsPerWave;
   {
@@ -2279,7 +2368,12 @@ int spgemm_symbolic(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_
   const int64_t width = (kdim + n_layers - 1) / n_layers;
   for (int32_t l = 0; l < n_layers; l++) {
     const int64_t klo = std::min<int64_t>(kdim, (int64_t)l * width), khi = std::min<int64_t>(kdim, klo + width);
-    int rc = symbolic_pass(A, B, c0, ncol, klo, khi, nullptr, nnz_out + (int64_t)l * ncol, L, w, s, true);
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)w, 0, 0);
+    LAUNCHCHK();
+    spgemm_csc Bl;
+    int rc = build_layer<float>(B, c0, ncol, klo, khi, kdim, false, L, w, s, &Bl);
+    if (rc) return rc;
+    rc = symbolic_pass(A, &Bl, 0, ncol, klo, khi, nullptr, nnz_out + (int64_t)l * ncol, L, w, s, true, true);
     if (rc) return rc;
   }
   return symbolic_pass(A, B, c0, ncol, 0, kdim, flops_out, nnz_out + (int64_t)n_layers * ncol, L, w, s, true);
@@ -2311,6 +2405,21 @@ int spgemm_numeric(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t
   const int64_t width = (kdim + n_layers - 1) / n_layers;
   const int64_t klo = std::min<int64_t>(kdim, (int64_t)layer * width), khi = std::min<int64_t>(kdim, klo + width);
   hipStream_t s = (hipStream_t)stream;
+  if (n_layers > 1) {  // the layer's share of B first, then the passes over it
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)ws, 1, 0);
+    LAUNCHCHK();
+    spgemm_csc Bl;
+    if (A->dtype == SPGEMM_F32) {
+      st = build_layer<float>(B, c0, ncol, klo, khi, kdim, true, L, (char *)ws, s, &Bl);
+      if (st) return st;
+      return numeric_typed<float>(A, &Bl, 0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, (char *)ws, s, true,
+                                  true);
+    }
+    st = build_layer<double>(B, c0, ncol, klo, khi, kdim, true, L, (char *)ws, s, &Bl);
+    if (st) return st;
+    return numeric_typed<double>(A, &Bl, 0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, (char *)ws, s, true,
+                                 true);
+  }
   if (A->dtype == SPGEMM_F32)
     return numeric_typed<float>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, (char *)ws, s, true);
   return numeric_typed<double>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, (char *)ws, s, true);
