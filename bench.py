@@ -146,8 +146,10 @@ def headline(args, torch, np, S, synth):
     bcp = A.colptr.cpu().numpy()
     bdeg = np.diff(bcp)
     u = plan.nnz_host[0]
-    heavy = u > 5120
-    # per batch, the heavy columns' B entries and outputs, plus one read of A
+    # heavy columns the item kernel takes: more than 5120 rows out, at most 1024
+    # entries in B(:,j) (wider ones go to the dense-LDS wide kernel)
+    heavy = (u > 5120) & (bdeg <= 1024)
+    # per batch, those columns' B entries and outputs, plus one read of A
     per_batch = []
     for i in range(nb):
         c0, c1 = pl.bounds[i], pl.bounds[i + 1]
@@ -158,7 +160,8 @@ def headline(args, torch, np, S, synth):
     if dom_name == "heavy_items":
         # the heavy columns of every batch, spread evenly over the item launches
         alg_bytes_per_launch = float(sum(per_batch)) / launches
-        unit = ("heavy output columns: r*(nnz(B) + nnz(C)) of those columns + 8 per column + r*nnz(A) per batch, "
+        unit = ("item-kernel columns (more than 5120 rows out, at most 1024 entries in B(:,j)): "
+                "r*(nnz(B) + nnz(C)) of those columns + 8 per column + r*nnz(A) per batch, "
                 "summed over batches and divided by the item launches per step")
     else:
         alg_bytes_per_launch = num_bytes / launches
