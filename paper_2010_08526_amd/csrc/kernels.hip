@@ -897,8 +897,8 @@ struct HvArgs {
   int32_t klo, khi, kdim, P;
 };
 
-// Visits the terms A(i,k) B(k,col) of k in B(:,col) with i in slabs
-// [sa, sb): ins(i, value).  Segment bounds are checked once per segment (the
+// Visits the terms A(i,k) B(k,col) of k in B(:,col) = entries [pbeg, pend)
+// of B with i in slabs [sa, sb): ins(i, value).  Segment bounds are checked once per segment (the
 // element reads need no check); returns nonzero if an index was out of
 // range (that segment is skipped).  The nw waves of the workgroup split the
 // chunks of 64 entries of B(:,col) when there are at least cs_min*nw of them,
@@ -911,11 +911,50 @@ constexpr int kHvPipe = 4;
 constexpr int kHvVec = 4;
 constexpr int kHvBlk = kWave * kHvVec;
 
+// The first chunk of an item's B entries, as one wave reads it, loaded ahead
+// of the item in two steps (hv_pre_b: the entries; hv_pre_seg: their segment
+// words), so that the dependent loads B entry -> segment word of the next
+// item run while the current one finishes.
+template <class VT>
+struct HvPre {
+  int32_t k;
+  VT bv;
+  uint64_t g0, g1;
+};
+
+template <class VT>
+__device__ __forceinline__ void hv_pre_b(const HvArgs<VT> &a, int64_t pbeg, int64_t pend, int w, int nw,
+                                         int cs_min, HvPre<VT> &pre) {
+  const int nchunk = (int)((pend - pbeg + kWave - 1) / kWave);
+  const int c = nchunk >= cs_min * nw ? w : 0;
+  const int64_t p = pbeg + (int64_t)c * kWave + lane();
+  pre.k = -1;
+  pre.bv = VT(0);
+  if (p < pend) {
+    pre.k = a.Bri[p];
+    pre.bv = a.Bv[p];
+  }
+}
+
+template <class VT>
+__device__ __forceinline__ void hv_pre_seg(const HvArgs<VT> &a, int sa, int sb, HvPre<VT> &pre) {
+  pre.g0 = 0;
+  pre.g1 = 0;
+  const int32_t k = pre.k;
+  if (k >= a.klo && k < a.khi) {
+    const int64_t kc = a.khi - a.klo;
+    pre.g0 = a.pack[(int64_t)sa * kc + (k - a.klo)];
+    if (sb != sa + 1) pre.g1 = a.pack[(int64_t)(sb - 1) * kc + (k - a.klo)];
+  }
+}
+
+// pre: the wave's first chunk loaded ahead (same pbeg, pend, sa, sb, w, nw,
+// cs_min), or nullptr.
 template <class VT, class Ins>
-__device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t col, int sa, int sb, int w, int nw,
-                                           int cs_min, SegScratch &sc, Ins &&ins) {
+__device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t pbeg, int64_t pend, int sa, int sb, int w,
+                                           int nw, int cs_min, SegScratch &sc, const HvPre<VT> *pre,
+                                           Ins &&ins) {
   const int l = lane();
-  const int64_t pbeg = a.Bcp[col], pend = a.Bcp[col + 1];
   const int nchunk = (int)((pend - pbeg + kWave - 1) / kWave);
   const bool csplit = nchunk >= cs_min * nw;
   const int c_rank = csplit ? w : 0, c_stride = csplit ? nw : 1;
@@ -927,18 +966,30 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t col, int
     int len = 0;
     int64_t off = 0;
     double b = 0.0;
-    if (p < pend) {
-      const int32_t k = a.Bri[p];
+    int32_t k = -1;
+    VT bv = VT(0);
+    uint64_t g0 = 0, g1 = 0;
+    if (pre && c == c_rank) {  // uniform
+      k = pre->k;
+      bv = pre->bv;
+      g0 = pre->g0;
+      g1 = pre->g1;
+    } else if (p < pend) {
+      k = a.Bri[p];
+      bv = a.Bv[p];
       if (k >= a.klo && k < a.khi) {
         const int64_t kc = a.khi - a.klo;
+        g0 = a.pack[(int64_t)sa * kc + (k - a.klo)];
+        if (sb != sa + 1) g1 = a.pack[(int64_t)(sb - 1) * kc + (k - a.klo)];
+      }
+    }
+    if (p < pend) {
+      if (k >= a.klo && k < a.khi) {
         constexpr uint64_t kLenMask = (uint64_t(1) << kSegLenBits) - 1;
-        const uint64_t g0 = a.pack[(int64_t)sa * kc + (k - a.klo)];
-        int64_t end = (int64_t)(g0 >> kSegLenBits) + (int64_t)(g0 & kLenMask);
-        if (sb != sa + 1) {  // uniform: a hash item over several slabs also needs its last slab
-          const uint64_t g1 = a.pack[(int64_t)(sb - 1) * kc + (k - a.klo)];
-          end = (int64_t)(g1 >> kSegLenBits) + (int64_t)(g1 & kLenMask);
-        }
-        b = (double)a.Bv[p];
+        // a hash item over several slabs ends where its last slab's segment ends
+        const uint64_t ge = sb != sa + 1 ? g1 : g0;
+        const int64_t end = (int64_t)(ge >> kSegLenBits) + (int64_t)(ge & kLenMask);
+        b = (double)bv;
         off = (int64_t)(g0 >> kSegLenBits);
         const int64_t d = end - off;
         len = (int)min(max(d, (int64_t)-1), (int64_t)kMaxAdeg);
@@ -1060,10 +1111,21 @@ struct HvProductSrc {
   HvArgs<VT> a;
   int64_t c0;
   int P;
+  // the item's input range: the entries of B(:, c0 + jj)
+  __device__ __forceinline__ void range(int64_t jj, int64_t, int, int, int64_t &lo, int64_t &hi) const {
+    lo = a.Bcp[c0 + jj];
+    hi = a.Bcp[c0 + jj + 1];
+  }
+  using Pre = HvPre<VT>;
+  static constexpr int kCsMin = 2;
+  __device__ __forceinline__ void pre_b(int64_t lo, int64_t hi, int w, int nw, Pre &pre) const {
+    hv_pre_b<VT>(a, lo, hi, w, nw, kCsMin, pre);
+  }
+  __device__ __forceinline__ void pre_seg(int sa, int sb, Pre &pre) const { hv_pre_seg<VT>(a, sa, sb, pre); }
   template <class Ins>
-  __device__ __forceinline__ int visit(int64_t jj, int64_t hl, int sa, int sb, int w, int nw, SegScratch &sc,
-                                       Ins &&ins) const {
-    return hv_traverse<VT>(a, c0 + jj, sa, sb, w, nw, 2, sc, ins);
+  __device__ __forceinline__ int visit(int64_t lo, int64_t hi, int sa, int sb, int w, int nw, SegScratch &sc,
+                                       const Pre &pre, Ins &&ins) const {
+    return hv_traverse<VT>(a, lo, hi, sa, sb, w, nw, kCsMin, sc, &pre, ins);
   }
 };
 
@@ -1084,6 +1146,8 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
   __shared__ int s_batch, s_pos;
   __shared__ uint32_t s_e[kWave];
   __shared__ int32_t s_jj[kWave];
+  __shared__ int64_t s_lo[kWave], s_hi[kWave], s_cb[kWave];  // input range, output column start
+  __shared__ int32_t s_cn[kWave];                             // output column length
   __shared__ unsigned long long s_mask;
   const int w = threadIdx.x / kWave, l = lane();
   int32_t *status = &hdr->status;
@@ -1105,7 +1169,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
     if (bi >= nbatch) break;
     const int t = (int)(bi / nb);
     const int64_t hb = (bi % nb) * kWave;
-    if (w == 0) {
+    if (w == 0) {  // the batch's items: slot, column, input range and output column, one per lane
       const int64_t hl = hb + l;
       uint32_t e = 0u;
       int32_t jj = 0;
@@ -1113,26 +1177,57 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
         e = slots[hl * P + t];
         jj = list[h0 + hl];
       }
+      int64_t lo = 0, hi = 0, cb = 0, cn = 0;
+      const int sb0 = (int)((e >> 12) & 0xfffu);
+      if ((e & kHvValid) != 0u && (int)(e & 0xfffu) == t && sb0 > t && sb0 <= P) {
+        src.range(jj, hl, t, sb0, lo, hi);
+        cb = c_colptr[jj];
+        cn = c_colptr[jj + 1] - cb;
+      }
       const uint64_t mk = __ballot((e & kHvValid) != 0u);
       s_e[l] = e;
       s_jj[l] = jj;
+      s_lo[l] = lo;
+      s_hi[l] = hi;
+      s_cb[l] = cb;
+      s_cn[l] = (int32_t)min(cn, (int64_t)INT32_MAX);
       if (l == 0) s_mask = mk;
     }
     __syncthreads();
     uint64_t mask = s_mask;
+    // the first chunk of the next item is loaded ahead: its B entries while
+    // the current item finishes its accumulation, their segment words after
+    // its output is written
+    typename Src::Pre pre;
+    const auto pre_load = [&](int jn, bool seg_only) {
+      const uint32_t en = s_e[jn];
+      const int sbn = (int)((en >> 12) & 0xfffu);
+      if ((int)(en & 0xfffu) != t || sbn <= t || sbn > P) return;  // malformed: the item is skipped
+      if (!seg_only) src.pre_b(s_lo[jn], s_hi[jn], w, NW, pre);
+      else src.pre_seg(t, sbn, pre);
+    };
+    if (mask) {
+      pre_load(__builtin_ctzll(mask), false);
+      pre_load(__builtin_ctzll(mask), true);
+    }
     while (mask) {
       const int j = __builtin_ctzll(mask);
       mask &= mask - 1;
+      const int jn = mask ? __builtin_ctzll(mask) : -1;
       const uint32_t e = s_e[j];
       const int64_t jj = s_jj[j];
-      const int64_t hl = hb + j;
       const int sb0 = (int)((e >> 12) & 0xfffu);
       const bool dense = ((e >> 24) & 1u) != 0;
       if ((int)(e & 0xfffu) != t || sb0 <= t || sb0 > P || (dense && sb0 != t + 1)) {
         if (threadIdx.x == 0) flag_error(status, 9);
+        if (jn >= 0) {
+          pre_load(jn, false);
+          pre_load(jn, true);
+        }
         continue;
       }
-      const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
+      const int64_t base = s_cb[j], cap = s_cn[j];
+      const int64_t lo = s_lo[j], hi = s_hi[j];
       int bad;
       int c = 0;
       uint32_t word = 0;
@@ -1142,7 +1237,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
         if (threadIdx.x < kWords) bits[threadIdx.x] = 0u;
         __syncthreads();
         int outside = 0;
-        bad = src.visit(jj, hl, t, sb0, w, NW, s_sc[w], [&](int32_t row, double v) {
+        bad = src.visit(lo, hi, t, sb0, w, NW, s_sc[w], pre, [&](int32_t row, double v) {
           const uint32_t r = (uint32_t)row - rb;
           if (r < (uint32_t)kSlabRows) {
             atomicAdd(&acc[r], v);
@@ -1161,7 +1256,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
           vals[q] = 0.0;
         }
         __syncthreads();
-        bad = src.visit(jj, hl, t, sb0, w, NW, s_sc[w], [&](int32_t row, double v) {
+        bad = src.visit(lo, hi, t, sb0, w, NW, s_sc[w], pre, [&](int32_t row, double v) {
           ht_accumulate(keys, vals, kHvSlots, row, v);
         });
         __syncthreads();
@@ -1169,6 +1264,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
 #pragma unroll
         for (int i = 0; i < kPer; i++) c += keys[q0 + i] != kEmpty ? 1 : 0;
       }
+      if (jn >= 0) pre_load(jn, false);  // the next item's B entries
       if (__ballot(bad) && l == 0) flag_error(status, 5);
       int total;
       const int ex = block_excl<NW>(c, s_w, total);
@@ -1201,6 +1297,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
           }
         }
       }
+      if (jn >= 0) pre_load(jn, true);  // and their segment words
       __syncthreads();
     }
   }
@@ -1492,12 +1589,19 @@ struct MbSrc {
   const int64_t *base;
   int64_t h0;
   int P;
-  template <class Ins>
-  __device__ __forceinline__ int visit(int64_t, int64_t hl, int sa, int sb, int w, int nw, SegScratch &,
-                                       Ins &&ins) const {
+  // the item's input range: its slabs' part of the column's bucket
+  __device__ __forceinline__ void range(int64_t, int64_t hl, int sa, int sb, int64_t &lo, int64_t &hi) const {
     const int32_t *so = soff + hl * (int64_t)(P + 1);
     const int64_t bb = base[h0 + hl] - base[h0];
-    const int64_t e0 = bb + so[sa], e1 = bb + so[sb];
+    lo = bb + so[sa];
+    hi = bb + so[sb];
+  }
+  struct Pre {};  // nothing to load ahead: the range is the item's input
+  __device__ __forceinline__ void pre_b(int64_t, int64_t, int, int, Pre &) const {}
+  __device__ __forceinline__ void pre_seg(int, int, Pre &) const {}
+  template <class Ins>
+  __device__ __forceinline__ int visit(int64_t e0, int64_t e1, int, int, int w, int nw, SegScratch &, const Pre &,
+                                       Ins &&ins) const {
     constexpr int kV = 4;
     const int l = lane();
     for (int64_t q0 = e0 + (int64_t)w * kWave * kV + l; q0 < e1; q0 += (int64_t)nw * kWave * kV) {
@@ -1572,7 +1676,7 @@ __global__ __launch_bounds__(kHvWideThreads) void k_hv_wide(HvArgs<VT> a, int64_
     if (threadIdx.x < kWords) s_bits[threadIdx.x] = 0u;
     __syncthreads();
     int outside = 0;
-    int bad = hv_traverse<VT>(a, col, sa, sb, w, NW, 1, s_sc[w], [&](int32_t row, double v) {
+    int bad = hv_traverse<VT>(a, a.Bcp[col], a.Bcp[col + 1], sa, sb, w, NW, 1, s_sc[w], (const HvPre<VT> *)nullptr, [&](int32_t row, double v) {
       const uint32_t r = (uint32_t)row - rb;
       if (r < (uint32_t)kHvWideRows) {
         atomicAdd(&s_acc[r], v);
