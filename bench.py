@@ -151,10 +151,13 @@ def headline(args, torch, np, S, synth):
     heavy = (u > 5120) & (bdeg <= 1024)
     # per batch, those columns' B entries and outputs, plus one read of A
     per_batch = []
+    fcol = eng.flops.cpu().numpy()
+    gather = 0  # A entries fetched per multiplication by the item kernel (gather model)
     for i in range(nb):
         c0, c1 = pl.bounds[i], pl.bounds[i + 1]
         h = heavy[c0:c1]
         per_batch.append(r * int(bdeg[c0:c1][h].sum()) + r * int(u[c0:c1][h].sum()) + 8 * int(h.sum()) + r * A.nnz)
+        gather += r * int(fcol[c0:c1][h].sum())
     num_bytes = nb * r * A.nnz + r * A.nnz + r * nnz_c + 8 * (A.ncols + nb)  # whole numeric phase
     launches = max(1.0, dom_calls / args.steps)
     if dom_name == "heavy_items":
@@ -168,6 +171,8 @@ def headline(args, torch, np, S, synth):
         unit = "share of the numeric phase's compulsory bytes"
     avg_launch_s = dom_ms / dom_calls / 1e3
     achieved = alg_bytes_per_launch / avg_launch_s / 1e9
+    gather_gbs = (alg_bytes_per_launch + gather / launches) / avg_launch_s / 1e9 if dom_name == "heavy_items" else None
+    copy_gbs = measured_copy_gbs(torch)
     t_num = float(np.mean(phase["numeric"])) / 1e3
     res = {
         "metric": METRIC,
@@ -195,7 +200,12 @@ def headline(args, torch, np, S, synth):
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": measured_traffic(dom_name, f"rmat{args.scale}"),
                      "bytes_per_launch": int(alg_bytes_per_launch), "bytes_unit": unit,
-                     "avg_launch_ms": round(avg_launch_s * 1e3, 3), "launches_per_step": dom_calls / args.steps},
+                     "avg_launch_ms": round(avg_launch_s * 1e3, 3), "launches_per_step": dom_calls / args.steps,
+                     "gather_model_GBps": None if gather_gbs is None else round(gather_gbs, 2),
+                     "gather_model_note": "compulsory bytes plus r bytes of A per multiplication; caches can serve "
+                                          "these re-reads, so this model may exceed the peak",
+                     "measured_copy_GBps": round(copy_gbs, 1),
+                     "measured_copy_note": "device-to-device copy of 2 GiB (read + write bytes over time)"},
     }
     return res, A
 
@@ -428,6 +438,23 @@ def copy_calibration(torch):
         y.copy_(x)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "launches": 5}), flush=True)
+
+
+def measured_copy_gbs(torch, reps=5):
+    """Read + write bytes per second of a plain 2 GiB device copy."""
+    x = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda:0")
+    y = torch.empty_like(x)
+    x.fill_(1)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3
+    del x, y
+    return 2.0 * COPY_BYTES * reps / t / 1e9
 
 
 def source_digest():

@@ -254,3 +254,37 @@ def test_heavy_columns_tall_matrix_two_windows():
     assert nz[0].min() > 5120
     C, _ = _run(A, B)
     assert_matches(C, oracle.spgemm(A, B), torch.float32, "tall")
+
+
+@pytest.mark.parametrize("layers", [1, 4])
+def test_b_rows_outside_inner_dimension_flagged(layers):
+    """A row of B at or beyond k = ncols(A) is reported by the device-side
+    check (code 1), by the symbolic pass and, with layers, by each layer's
+    split of B in the symbolic and numeric passes; A's column pointers are
+    never read for it."""
+    print(f"case: bad B row, layers {layers}", flush=True)
+    A = synth.erdos_renyi(512, 512, 8, 5, torch.float32)
+    B = synth.erdos_renyi(512, 300, 6, 6, torch.float32)
+    ri = B.rowidx.clone()
+    ri[17] = 512 + 40  # rows within the column stay distinct
+    Ad, Bd = A.to("cuda"), B.to("cuda")
+    Bbad = synth.CSC(B.nrows, B.ncols, Bd.colptr, ri.to("cuda"), Bd.values)
+    n = B.ncols
+    rows = layers + 1 if layers > 1 else 1
+    ws = S.alloc_workspace(S.workspace_size(S.OP_SYMBOLIC, Ad, Bd, 0, n, layers))
+    fl = torch.zeros(n, dtype=torch.int64, device="cuda")
+    nz = torch.zeros((rows, n), dtype=torch.int64, device="cuda")
+    S.symbolic(Ad, Bbad, 0, n, layers, fl, nz, ws)
+    assert S.ws_status_code(ws) == (S.E_DEVICE, 1)
+    # numeric of layer 0 with the output layout of the valid B
+    _, nz_ok = _symbolic(A, B, layers)
+    cnt = torch.from_numpy(nz_ok[0]).to("cuda")
+    cp = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+    cp[1:] = torch.cumsum(cnt, 0)
+    total = int(cp[-1])
+    c_ri = torch.full((total + 64,), -5, dtype=torch.int32, device="cuda")
+    c_v = torch.zeros(total + 64, dtype=torch.float32, device="cuda")
+    wsn = S.alloc_workspace(S.workspace_size(S.OP_NUMERIC, Ad, Bd, 0, n, layers))
+    S.numeric(Ad, Bbad, 0, n, 0, layers, fl, cp, c_ri, c_v, wsn)
+    assert S.ws_status_code(wsn) == (S.E_DEVICE, 1)
+    assert torch.all(c_ri[total:] == -5)  # nothing written past the output
