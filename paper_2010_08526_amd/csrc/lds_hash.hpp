@@ -5,19 +5,15 @@
 
 namespace spg {
 
-__device__ __forceinline__ int32_t lds_load(int32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
-
-// Inserts `key`; returns true if this call created it.
+// Inserts `key`; returns true if this call created it.  Each probe is one
+// compare-and-swap (it finds the key, claims a free slot, or moves on), so
+// a new key costs one LDS round trip per probe rather than a load and a swap.
 __device__ __forceinline__ bool ht_insert_key(int32_t *keys, uint32_t T, int32_t key) {
   uint32_t h = hash_slot(key, T);
   for (uint32_t probe = 0; probe < T; probe++) {
-    const int32_t k = lds_load(&keys[h]);
-    if (k == key) return false;
-    if (k == kEmpty) {
-      const int32_t old = atomicCAS(&keys[h], kEmpty, key);
-      if (old == kEmpty) return true;
-      if (old == key) return false;
-    }
+    const int32_t old = atomicCAS(&keys[h], kEmpty, key);
+    if (old == kEmpty) return true;
+    if (old == key) return false;
     h = (h + 1 == T) ? 0 : h + 1;
   }
   return false;  // unreachable with tables at most half full
@@ -27,17 +23,10 @@ __device__ __forceinline__ bool ht_insert_key(int32_t *keys, uint32_t T, int32_t
 __device__ __forceinline__ void ht_accumulate(int32_t *keys, double *vals, uint32_t T, int32_t key, double v) {
   uint32_t h = hash_slot(key, T);
   for (uint32_t probe = 0; probe < T; probe++) {
-    const int32_t k = lds_load(&keys[h]);
-    if (k == key) {
+    const int32_t old = atomicCAS(&keys[h], kEmpty, key);
+    if (old == kEmpty || old == key) {
       atomicAdd(&vals[h], v);
       return;
-    }
-    if (k == kEmpty) {
-      const int32_t old = atomicCAS(&keys[h], kEmpty, key);
-      if (old == kEmpty || old == key) {
-        atomicAdd(&vals[h], v);
-        return;
-      }
     }
     h = (h + 1 == T) ? 0 : h + 1;
   }
