@@ -26,6 +26,10 @@ __device__ __forceinline__ int dpp0(int v) {
   return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, false);
 }
 
+// Value of lane l - 1 in lane l (0 in lane 0): the wavefront shift right by
+// one lane (DPP wave_shr:1), a VALU move with no LDS round trip.
+__device__ __forceinline__ int wave_prev(int v) { return dpp0<0x138>(v); }
+
 // Inclusive prefix sum over the 64 lanes: Hillis-Steele inside each 16-lane
 // row (row_shr 1, 2, 4, 8), then row 0's total into row 1 and row 2's total
 // into row 3 (row_bcast:15), then lane 31's running total into rows 2 and 3

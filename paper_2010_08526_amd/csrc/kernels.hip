@@ -1332,7 +1332,7 @@ constexpr int kMbThreads = 1024;
 // heads a run of a valid id and that run's length.
 __device__ __forceinline__ uint64_t run_heads(int sl) {
   const int l = lane();
-  const int prev = __shfl_up(sl, 1, kWave);
+  const int prev = wave_prev(sl);
   return __ballot(l == 0 || prev != sl);
 }
 
@@ -1567,7 +1567,7 @@ __global__ __launch_bounds__(kMbThreads) __attribute__((amdgpu_waves_per_eu(8)))
             // every lane of a run takes the head's position plus its distance to the head
             const int head = run_head_lane(sl);
             pos = __shfl(pos, head, kWave) + (l - head);
-            if (sl >= 0) {
+            if (sl >= 0 && pos < total) {  // positions stay inside the column's counted range
               brow[bb + pos] = row;
               bval[bb + pos] = opaque(val_[u]);
             }
