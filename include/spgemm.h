@@ -109,7 +109,10 @@ int spgemm_workspace_size(int op, const spgemm_csc *A, const spgemm_csc *B, int6
  * possibly empty; Sec. III-B, Alg. 2) and nnz_out holds (L+1) rows of
  * (c1-c0) int64 each: row l = nnz of column j of the layer product
  * A(:,K_l)*B(K_l,:), row L = nnz of C(:,j).  Counts come from hash tables,
- * not from bounds.  Asynchronous on `stream`. */
+ * not from bounds.  Synchronizes `stream` once per pass (per layer, and once
+ * for row L) to read the per-bin column counts that size the launches; the
+ * counts themselves stay on the device.  A row of B outside [0,k) sets the
+ * workspace status (code 1) and the entry is skipped. */
 int spgemm_symbolic(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t c1, int32_t n_layers,
                     int64_t *flops_out, int64_t *nnz_out, void *ws, size_t ws_bytes, void *stream);
 
@@ -150,9 +153,11 @@ int spgemm_colptr(const int64_t *counts, int64_t n, int64_t *colptr_out, void *w
  * which must come from the matching symbolic counts (spgemm_colptr of the
  * layer's row).  c_colptr has c1-c0+1 entries and may start at any offset.
  * Rows within each output column are in hash-table order.  `flops` is the
- * symbolic flops_out of the same columns (may be NULL).  Asynchronous; a
- * mismatch between counts and the product sets the workspace status
- * (spgemm_ws_status). */
+ * symbolic flops_out of the same columns (may be NULL).  Synchronizes
+ * `stream` to read the per-bin column counts (and, for heavy columns, their
+ * count) that size the launches.  With n_layers > 1 the layer's share of
+ * B(:, c0:c1) is first compacted into the workspace.  A mismatch between
+ * counts and the product sets the workspace status (spgemm_ws_status). */
 int spgemm_numeric(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t c1, int32_t layer,
                    int32_t n_layers, const int64_t *flops, const int64_t *c_colptr, int32_t *c_rowidx,
                    void *c_values, void *ws, size_t ws_bytes, void *stream);
@@ -162,7 +167,10 @@ int spgemm_numeric(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t
  * row added.  parts is a HOST array of n_parts descriptors (device arrays
  * inside), all with the same nrows, ncols and dtype, 1 <= n_parts <= 4096.
  * c_colptr (ncols+1) comes from the union counts (row L of the symbolic
- * output for the batch).  Output rows in hash-table order.  Asynchronous. */
+ * output for the batch).  Output rows in hash-table order.  Synchronizes
+ * `stream` to read the per-bin column counts and, for columns of more than
+ * 5120 rows, their total entry counts (to cut them into chunks that fit the
+ * workspace's bucket region). */
 int spgemm_merge(const spgemm_csc *parts, int32_t n_parts, const int64_t *c_colptr, int32_t *c_rowidx,
                  void *c_values, void *ws, size_t ws_bytes, void *stream);
 
