@@ -193,17 +193,20 @@ def test_layers_with_batches_protein_like():
     assert_matches(C, oracle.spgemm(A, A), torch.float32, "protein")
 
 
-@pytest.mark.parametrize("which", ["protein", "rmat", "rmat_many_parts"])
+@pytest.mark.parametrize("which", ["protein", "rmat", "rmat_many_parts", "rmat_300_parts"])
 def test_merge_heavy_buckets_forced(which):
     """Every merge column through the heavy path (slab buckets, dense and hash
-    items); with 70 layers the parts span more than one chunk of 64."""
+    items); with 70 layers the parts span more than one chunk of 64, with 300
+    more than one group of 256 part ranges staged in LDS."""
     print(f"case: merge buckets {which}", flush=True)
     if which == "protein":
         A, L = synth.protein_like(20000, 23), 3
     elif which == "rmat":
         A, L = synth.rmat(13, 16, 29, dtype=torch.float32), 5
-    else:
+    elif which == "rmat_many_parts":
         A, L = synth.rmat(13, 16, 31, dtype=torch.float32), 70
+    else:
+        A, L = synth.rmat(13, 16, 37, dtype=torch.float32), 300
     Ad = A.to("cuda")
     eng = S.Engine(Ad, Ad, L, None)
     pl = eng.plan()  # symbolic in the natural bins
