@@ -1136,8 +1136,11 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
                                                          int32_t *out_ri, VT *out_v) {
   constexpr int NW = kHvThreads / kWave;
   constexpr int kWords = (int)(kSlabRows / 32);
-  constexpr int kPer = kHvSlots / kHvThreads;
-  static_assert(kHvSlots % kHvThreads == 0, "hash slots split evenly over threads");
+  constexpr int kRowsPerWave = (int)kSlabRows / NW;
+  constexpr int kWordsPerWave = kRowsPerWave / 32;
+  constexpr int kSlotsPerWave = kHvSlots / NW;
+  static_assert(kRowsPerWave % kWave == 0 && kWordsPerWave <= kWave, "dense rows split evenly over waves");
+  static_assert(kSlotsPerWave % kWave == 0, "hash slots split evenly over waves");
   static_assert(kWords <= kHvThreads, "one bitmap word per thread");
   static_assert(kHvSlots * 12 <= kSlabRows * 8, "hash table fits the dense array");
   __shared__ __align__(16) unsigned char s_tab[kSlabRows * 8 + kSlabRows / 8];
@@ -1230,7 +1233,6 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
       const int64_t lo = s_lo[j], hi = s_hi[j];
       int bad;
       int c = 0;
-      uint32_t word = 0;
       const uint32_t rb = (uint32_t)t << kSlabShift;
       if (dense) {
         for (int q = threadIdx.x; q < (int)kSlabRows; q += kHvThreads) acc[q] = 0.0;
@@ -1248,8 +1250,9 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
         });
         bad |= outside;
         __syncthreads();
-        word = threadIdx.x < kWords ? bits[threadIdx.x] : 0u;
-        c = __popc(word);
+        // wave w owns rows [w * kRowsPerWave, +kRowsPerWave): bitmap words
+        // w * kWordsPerWave + lane
+        c = l < kWordsPerWave ? __popc(bits[w * kWordsPerWave + l]) : 0;
       } else {
         for (int q = threadIdx.x; q < kHvSlots; q += kHvThreads) {
           keys[q] = kEmpty;
@@ -1260,9 +1263,9 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
           ht_accumulate(keys, vals, kHvSlots, row, v);
         });
         __syncthreads();
-        const int q0 = (int)threadIdx.x * kPer;
+        // wave w owns slots [w * kSlotsPerWave, +kSlotsPerWave)
 #pragma unroll
-        for (int i = 0; i < kPer; i++) c += keys[q0 + i] != kEmpty ? 1 : 0;
+        for (int g = 0; g < kSlotsPerWave / kWave; g++) c += keys[w * kSlotsPerWave + g * kWave + l] != kEmpty ? 1 : 0;
       }
       if (jn >= 0) pre_load(jn, false);  // the next item's B entries
       if (__ballot(bad) && l == 0) flag_error(status, 5);
@@ -1273,27 +1276,35 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
       if ((int64_t)s_pos + total > cap) {
         if (threadIdx.x == 0) flag_error(status, 4);
       } else {
-        int64_t o = base + s_pos + ex;
+        // each wave writes its rows or slots 64 at a time to consecutive
+        // positions (coalesced), starting after the earlier waves' entries
+        int64_t o = base + s_pos + readlane(ex, 0);
         if (dense) {
-          uint32_t bw = word;
-          while (bw) {
-            const int bj = __ffs(bw) - 1;
-            bw &= bw - 1;
-            const int r = (int)threadIdx.x * 32 + bj;
-            out_ri[o] = (int32_t)(rb + r);
-            out_v[o] = (VT)acc[r];
-            o++;
+#pragma unroll 4
+          for (int g = 0; g < kRowsPerWave / kWave; g++) {
+            const int r = w * kRowsPerWave + g * kWave + l;
+            const bool occ = (bits[r >> 5] >> (r & 31)) & 1u;
+            const uint64_t mask = __ballot(occ);
+            if (occ) {
+              const int64_t q = o + mbcnt(mask);
+              out_ri[q] = (int32_t)(rb + r);
+              out_v[q] = (VT)acc[r];
+            }
+            o += __popcll(mask);
           }
         } else {
-          const int q0 = (int)threadIdx.x * kPer;
-#pragma unroll
-          for (int i = 0; i < kPer; i++) {
-            const int32_t key = keys[q0 + i];
-            if (key != kEmpty) {
-              out_ri[o] = key;
-              out_v[o] = (VT)vals[q0 + i];
-              o++;
+#pragma unroll 2
+          for (int g = 0; g < kSlotsPerWave / kWave; g++) {
+            const int q = w * kSlotsPerWave + g * kWave + l;
+            const int32_t key = keys[q];
+            const bool occ = key != kEmpty;
+            const uint64_t mask = __ballot(occ);
+            if (occ) {
+              const int64_t d = o + mbcnt(mask);
+              out_ri[d] = key;
+              out_v[d] = (VT)vals[q];
             }
+            o += __popcll(mask);
           }
         }
       }
