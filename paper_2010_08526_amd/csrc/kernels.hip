@@ -1652,7 +1652,10 @@ __global__ __launch_bounds__(kHvWideThreads) void k_hv_wide(HvArgs<VT> a, int64_
                                                             int32_t *out_ri, VT *out_v) {
   constexpr int NW = kHvWideThreads / kWave;
   constexpr int kWords = (int)(kHvWideRows / 32);
+  constexpr int kRowsPerWave = (int)kHvWideRows / NW;
+  constexpr int kWordsPerWave = kRowsPerWave / 32;
   static_assert(kWords <= kHvWideThreads, "one bitmap word per thread");
+  static_assert(kRowsPerWave % kWave == 0 && kWordsPerWave <= kWave, "rows split evenly over waves");
   __shared__ double s_acc[kHvWideRows];
   __shared__ uint32_t s_bits[kWords];
   __shared__ SegScratch s_sc[NW];
@@ -1699,23 +1702,28 @@ __global__ __launch_bounds__(kHvWideThreads) void k_hv_wide(HvArgs<VT> a, int64_
     bad |= outside;
     __syncthreads();
     if (__ballot(bad) && l == 0) flag_error(status, 5);
-    const uint32_t word = threadIdx.x < kWords ? s_bits[threadIdx.x] : 0u;
+    // wave w owns rows [w * kRowsPerWave, +kRowsPerWave) and writes them 64
+    // at a time to consecutive positions
+    const int c = l < kWordsPerWave ? __popc(s_bits[w * kWordsPerWave + l]) : 0;
     int total;
-    const int ex = block_excl<NW>(__popc(word), s_w, total);
+    const int ex = block_excl<NW>(c, s_w, total);
     if (threadIdx.x == 0) s_pos = total ? atomicAdd(&hv_cur[jj], total) : 0;
     __syncthreads();
     if ((int64_t)s_pos + total > cap) {
       if (threadIdx.x == 0) flag_error(status, 4);
     } else {
-      int64_t o = base + s_pos + ex;
-      uint32_t bw = word;
-      while (bw) {
-        const int bj = __ffs(bw) - 1;
-        bw &= bw - 1;
-        const int r = (int)threadIdx.x * 32 + bj;
-        out_ri[o] = (int32_t)(rb + r);
-        out_v[o] = (VT)s_acc[r];
-        o++;
+      int64_t o = base + s_pos + readlane(ex, 0);
+#pragma unroll 4
+      for (int g = 0; g < kRowsPerWave / kWave; g++) {
+        const int r = w * kRowsPerWave + g * kWave + l;
+        const bool occ = (s_bits[r >> 5] >> (r & 31)) & 1u;
+        const uint64_t mask = __ballot(occ);
+        if (occ) {
+          const int64_t d = o + mbcnt(mask);
+          out_ri[d] = (int32_t)(rb + r);
+          out_v[d] = (VT)s_acc[r];
+        }
+        o += __popcll(mask);
       }
     }
   }
