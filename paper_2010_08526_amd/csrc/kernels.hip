@@ -1100,9 +1100,9 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t pbeg, in
 // those slabs stay in L2.  The items of a batch (its nonzero slots) are
 // formed one after another by the whole workgroup.  A dense item accumulates
 // slab t in a float64 array of kSlabRows rows plus an occupancy bitmap; a
-// hash item accumulates slabs [t, sb) in a kHvSlots-slot table.  The item's
-// rows are appended to its column at a position reserved on the column's
-// cursor (dense items in row order, hash items in slot order).
+// hash item accumulates slabs [t, sb) in a kHvSlots-slot table.  Each wave
+// owns a quarter of the rows (or slots), reserves room for its entries on
+// the column's cursor and appends them in row (or slot) order.
 constexpr int kHvThreads = 256;
 
 // Item source of the numeric pass: the product terms of column c0 + jj.
@@ -1145,8 +1145,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
   static_assert(kHvSlots * 12 <= kSlabRows * 8, "hash table fits the dense array");
   __shared__ __align__(16) unsigned char s_tab[kSlabRows * 8 + kSlabRows / 8];
   __shared__ SegScratch s_sc[NW];
-  __shared__ int s_w[NW];
-  __shared__ int s_batch, s_pos;
+  __shared__ int s_batch;
   __shared__ uint32_t s_e[kWave];
   __shared__ int32_t s_jj[kWave];
   __shared__ int64_t s_lo[kWave], s_hi[kWave], s_cb[kWave];  // input range, output column start
@@ -1269,16 +1268,17 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
       }
       if (jn >= 0) pre_load(jn, false);  // the next item's B entries
       if (__ballot(bad) && l == 0) flag_error(status, 5);
-      int total;
-      const int ex = block_excl<NW>(c, s_w, total);
-      if (threadIdx.x == 0) s_pos = total ? atomicAdd(&hv_cur[jj], total) : 0;
-      __syncthreads();
-      if ((int64_t)s_pos + total > cap) {
-        if (threadIdx.x == 0) flag_error(status, 4);
+      // each wave reserves room for its own entries on the column's cursor
+      // (no workgroup scan or barrier) and writes its rows or slots 64 at a
+      // time to consecutive positions
+      const int cw = readlane(wave_incl_add(c), kWave - 1);
+      int pw = 0;
+      if (l == 0 && cw) pw = atomicAdd(&hv_cur[jj], cw);
+      pw = readlane(pw, 0);
+      if ((int64_t)pw + cw > cap) {
+        if (l == 0) flag_error(status, 4);
       } else {
-        // each wave writes its rows or slots 64 at a time to consecutive
-        // positions (coalesced), starting after the earlier waves' entries
-        int64_t o = base + s_pos + readlane(ex, 0);
+        int64_t o = base + pw;
         if (dense) {
 #pragma unroll 4
           for (int g = 0; g < kRowsPerWave / kWave; g++) {
@@ -1659,8 +1659,7 @@ __global__ __launch_bounds__(kHvWideThreads) void k_hv_wide(HvArgs<VT> a, int64_
   __shared__ double s_acc[kHvWideRows];
   __shared__ uint32_t s_bits[kWords];
   __shared__ SegScratch s_sc[NW];
-  __shared__ int s_w[NW];
-  __shared__ int s_item, s_pos;
+  __shared__ int s_item;
   const int w = threadIdx.x / kWave, l = lane();
   int32_t *status = &hdr->status;
   const int P = a.P;
@@ -1704,15 +1703,15 @@ __global__ __launch_bounds__(kHvWideThreads) void k_hv_wide(HvArgs<VT> a, int64_
     if (__ballot(bad) && l == 0) flag_error(status, 5);
     // wave w owns rows [w * kRowsPerWave, +kRowsPerWave) and writes them 64
     // at a time to consecutive positions
-    const int c = l < kWordsPerWave ? __popc(s_bits[w * kWordsPerWave + l]) : 0;
-    int total;
-    const int ex = block_excl<NW>(c, s_w, total);
-    if (threadIdx.x == 0) s_pos = total ? atomicAdd(&hv_cur[jj], total) : 0;
-    __syncthreads();
-    if ((int64_t)s_pos + total > cap) {
-      if (threadIdx.x == 0) flag_error(status, 4);
+    // (each wave reserves room for its own rows on the column's cursor)
+    const int cw = readlane(wave_incl_add(l < kWordsPerWave ? __popc(s_bits[w * kWordsPerWave + l]) : 0), kWave - 1);
+    int pw = 0;
+    if (l == 0 && cw) pw = atomicAdd(&hv_cur[jj], cw);
+    pw = readlane(pw, 0);
+    if ((int64_t)pw + cw > cap) {
+      if (l == 0) flag_error(status, 4);
     } else {
-      int64_t o = base + s_pos + readlane(ex, 0);
+      int64_t o = base + pw;
 #pragma unroll 4
       for (int g = 0; g < kRowsPerWave / kWave; g++) {
         const int r = w * kRowsPerWave + g * kWave + l;
