@@ -1234,7 +1234,8 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
       int c = 0;
       const uint32_t rb = (uint32_t)t << kSlabShift;
       if (dense) {
-        for (int q = threadIdx.x; q < (int)kSlabRows; q += kHvThreads) acc[q] = 0.0;
+        for (int q = threadIdx.x; q < (int)kSlabRows / 2; q += kHvThreads)  // 16-byte stores
+          reinterpret_cast<double2 *>(acc)[q] = make_double2(0.0, 0.0);
         if (threadIdx.x < kWords) bits[threadIdx.x] = 0u;
         __syncthreads();
         int outside = 0;
@@ -1253,10 +1254,10 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
         // w * kWordsPerWave + lane
         c = l < kWordsPerWave ? __popc(bits[w * kWordsPerWave + l]) : 0;
       } else {
-        for (int q = threadIdx.x; q < kHvSlots; q += kHvThreads) {
-          keys[q] = kEmpty;
-          vals[q] = 0.0;
-        }
+        for (int q = threadIdx.x; q < kHvSlots / 4; q += kHvThreads)  // 16-byte stores
+          reinterpret_cast<int4 *>(keys)[q] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
+        for (int q = threadIdx.x; q < kHvSlots / 2; q += kHvThreads)
+          reinterpret_cast<double2 *>(vals)[q] = make_double2(0.0, 0.0);
         __syncthreads();
         bad = src.visit(lo, hi, t, sb0, w, NW, s_sc[w], pre, [&](int32_t row, double v) {
           ht_accumulate(keys, vals, kHvSlots, row, v);
