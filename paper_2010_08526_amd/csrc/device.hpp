@@ -44,6 +44,25 @@ __device__ __forceinline__ int wave_incl_add(int v) {
   return v;
 }
 
+// Per-thread counts -> exclusive offset within the workgroup; `total` gets
+// the workgroup's sum.  Contains a barrier.
+template <int NW>
+__device__ __forceinline__ int block_excl(int c, int *s_w, int &total) {
+  const int w = threadIdx.x / kWave, l = lane();
+  const int incl = wave_incl_add(c);
+  if (l == kWave - 1) s_w[w] = incl;
+  __syncthreads();
+  int before = 0, tot = 0;
+#pragma unroll
+  for (int z = 0; z < NW; z++) {
+    const int v = s_w[z];
+    if (z < w) before += v;
+    tot += v;
+  }
+  total = tot;
+  return before + incl - c;
+}
+
 // Inclusive prefix maximum of non-negative values (0 is the identity).
 __device__ __forceinline__ int wave_incl_max(int v) {
   v = max(v, dpp0<0x111>(v));

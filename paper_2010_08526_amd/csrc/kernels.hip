@@ -596,28 +596,37 @@ __device__ __forceinline__ void init_mark(void *scratch) {
   ((int *)scratch)[lane()] = 0;  // both scratch layouts start with mark[64]
 }
 
-// Writes the occupied slots [s_lo, s_hi) of a table to the output column in
-// slot order; `counter` reserves output positions (wave-wide).
+// Writes the occupied slots [s_lo, s_hi) of a table, in slot order, to
+// consecutive output positions from o on (one wave; positions at or beyond
+// `end` are not written).  Returns the position after the last entry.
 template <class VT>
-__device__ __forceinline__ void compact_range(const int32_t *keys, const double *vals, int s_lo, int s_hi,
-                                              int64_t base, int64_t cap, int *counter, int32_t *out_ri,
-                                              VT *out_v) {
+__device__ __forceinline__ int64_t compact_run(const int32_t *keys, const double *vals, int s_lo, int s_hi,
+                                               int64_t o, int64_t end, int32_t *out_ri, VT *out_v) {
   const int l = lane();
   for (int s0 = s_lo; s0 < s_hi; s0 += kWave) {
     const int s = s0 + l;
     const int32_t key = s < s_hi ? keys[s] : kEmpty;
     const bool occ = key != kEmpty;
     const uint64_t mask = __ballot(occ);
-    if (!mask) continue;
-    int pos0 = 0;
-    if (l == 0) pos0 = atomicAdd(counter, __popcll(mask));
-    pos0 = readlane(pos0, 0);
-    const int64_t pos = pos0 + mbcnt(mask);
-    if (occ && pos < cap) {
-      out_ri[base + pos] = key;
-      out_v[base + pos] = (VT)vals[s];
+    const int64_t q = o + mbcnt(mask);
+    if (occ && q < end) {
+      out_ri[q] = key;
+      out_v[q] = (VT)vals[s];
     }
+    o += __popcll(mask);
   }
+  return o;
+}
+
+// Occupied slots of [s_lo, s_hi) (one wave; the count in every lane).
+__device__ __forceinline__ int count_run(const int32_t *keys, int s_lo, int s_hi) {
+  const int l = lane();
+  int c = 0;
+  for (int s0 = s_lo; s0 < s_hi; s0 += kWave) {
+    const int s = s0 + l;
+    c += __popcll(__ballot(s < s_hi && keys[s] != kEmpty));
+  }
+  return c;
 }
 
 template <int TBL, class VT, class Src>
@@ -627,7 +636,6 @@ __global__ __launch_bounds__(256) void k_num_wave(Src src, const int32_t *list, 
   __shared__ int32_t s_keys[4][TBL];
   __shared__ double s_vals[4][TBL];
   __shared__ __align__(16) char s_sc[4][kScratchBytes];
-  __shared__ int s_written[4];
   const int w = threadIdx.x / kWave, l = lane();
   const int count = *count_p;
   int32_t *keys = s_keys[w];
@@ -638,15 +646,14 @@ __global__ __launch_bounds__(256) void k_num_wave(Src src, const int32_t *list, 
       keys[s] = kEmpty;
       vals[s] = 0.0;
     }
-    if (l == 0) s_written[w] = 0;
     wave_sync();
     const int32_t jj = list[idx];
     src.visit(jj, 0, 1, 0, 1, s_sc[w], status, [&](int32_t row, double v) { ht_accumulate(keys, vals, TBL, row, v); });
     wave_sync();
     const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
-    compact_range<VT>(keys, vals, 0, TBL, base, cap, &s_written[w], out_ri, out_v);
-    wave_sync();
-    if (l == 0 && s_written[w] != cap) flag_error(status, 4);
+    // one wave owns the column: output positions follow a running count
+    const int64_t o = compact_run<VT>(keys, vals, 0, TBL, base, base + cap, out_ri, out_v);
+    if (l == 0 && o - base != cap) flag_error(status, 4);
     wave_sync();
   }
 }
@@ -659,8 +666,8 @@ __global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *l
   __shared__ int32_t s_keys[TBL];
   __shared__ double s_vals[TBL];
   __shared__ __align__(16) char s_sc[NW][kScratchBytes];
-  __shared__ int s_written;
-  const int w = threadIdx.x / kWave;
+  __shared__ int s_w[NW];
+  const int w = threadIdx.x / kWave, l = lane();
   const int count = *count_p;
   init_mark<VT>(s_sc[w]);
   for (int item = blockIdx.x; item < count; item += gridDim.x) {
@@ -668,17 +675,21 @@ __global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *l
       s_keys[s] = kEmpty;
       s_vals[s] = 0.0;
     }
-    if (threadIdx.x == 0) s_written = 0;
     __syncthreads();
     const int32_t jj = list[item];
     src.visit(jj, w, NW, 0, 1, s_sc[w], status,
               [&](int32_t row, double v) { ht_accumulate(s_keys, s_vals, TBL, row, v); });
     __syncthreads();
     const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
+    // wave w owns slots [w * PER, (w + 1) * PER): count them, scan the waves'
+    // counts, then write at a running position
     constexpr int PER = (TBL + NW - 1) / NW;
-    compact_range<VT>(s_keys, s_vals, w * PER, min(TBL, (w + 1) * PER), base, cap, &s_written, out_ri, out_v);
-    __syncthreads();
-    if (threadIdx.x == 0 && s_written != cap) flag_error(status, 4);
+    const int lo = w * PER, hi = min(TBL, (w + 1) * PER);
+    const int cw = count_run(s_keys, lo, hi);  // every lane of the wave takes part
+    int total;
+    const int ex = block_excl<NW>(l == 0 ? cw : 0, s_w, total);
+    compact_run<VT>(s_keys, s_vals, lo, hi, base + readlane(ex, 0), base + cap, out_ri, out_v);
+    if (threadIdx.x == 0 && total != cap) flag_error(status, 4);
     __syncthreads();
   }
 }
@@ -775,25 +786,6 @@ __device__ __forceinline__ uint32_t hv_enc(int sa, int sb, bool dense) {
   return kHvValid | (uint32_t)sa | ((uint32_t)sb << 12) | (dense ? (1u << 24) : 0u);
 }
 static_assert(kMaxSlabs < (1 << 12), "slab ids must fit 12 bits");
-
-// Per-thread counts -> exclusive offset within the workgroup; `total` gets
-// the workgroup's sum.  Contains a barrier.
-template <int NW>
-__device__ __forceinline__ int block_excl(int c, int *s_w, int &total) {
-  const int w = threadIdx.x / kWave, l = lane();
-  const int incl = wave_incl_add(c);
-  if (l == kWave - 1) s_w[w] = incl;
-  __syncthreads();
-  int before = 0, tot = 0;
-#pragma unroll
-  for (int z = 0; z < NW; z++) {
-    const int v = s_w[z];
-    if (z < w) before += v;
-    tot += v;
-  }
-  total = tot;
-  return before + incl - c;
-}
 
 __global__ void k_hv_reset(WsHeader *h) {
   if (threadIdx.x == 0) {
