@@ -633,8 +633,9 @@ template <int TBL, class VT, class Src>
 __global__ __launch_bounds__(256) void k_num_wave(Src src, const int32_t *list, const int32_t *count_p,
                                                   const int64_t *c_colptr, int32_t *out_ri, VT *out_v,
                                                   int32_t *status) {
-  __shared__ int32_t s_keys[4][TBL];
-  __shared__ double s_vals[4][TBL];
+  static_assert(TBL % 4 == 0, "tables cleared 16 bytes at a time");
+  __shared__ __align__(16) int32_t s_keys[4][TBL];
+  __shared__ __align__(16) double s_vals[4][TBL];
   __shared__ __align__(16) char s_sc[4][kScratchBytes];
   const int w = threadIdx.x / kWave, l = lane();
   const int count = *count_p;
@@ -642,10 +643,8 @@ __global__ __launch_bounds__(256) void k_num_wave(Src src, const int32_t *list, 
   double *vals = s_vals[w];
   init_mark<VT>(s_sc[w]);
   for (int idx = blockIdx.x * 4 + w; idx < count; idx += gridDim.x * 4) {
-    for (int s = l; s < TBL; s += kWave) {
-      keys[s] = kEmpty;
-      vals[s] = 0.0;
-    }
+    for (int s = l; s < TBL / 4; s += kWave) reinterpret_cast<int4 *>(keys)[s] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
+    for (int s = l; s < TBL / 2; s += kWave) reinterpret_cast<double2 *>(vals)[s] = make_double2(0.0, 0.0);
     wave_sync();
     const int32_t jj = list[idx];
     src.visit(jj, 0, 1, 0, 1, s_sc[w], status, [&](int32_t row, double v) { ht_accumulate(keys, vals, TBL, row, v); });
@@ -663,18 +662,18 @@ __global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *l
                                                        const int64_t *c_colptr, int32_t *out_ri, VT *out_v,
                                                        int32_t *status) {
   constexpr int NW = THREADS / kWave;
-  __shared__ int32_t s_keys[TBL];
-  __shared__ double s_vals[TBL];
+  static_assert(TBL % 4 == 0, "tables cleared 16 bytes at a time");
+  __shared__ __align__(16) int32_t s_keys[TBL];
+  __shared__ __align__(16) double s_vals[TBL];
   __shared__ __align__(16) char s_sc[NW][kScratchBytes];
   __shared__ int s_w[NW];
   const int w = threadIdx.x / kWave, l = lane();
   const int count = *count_p;
   init_mark<VT>(s_sc[w]);
   for (int item = blockIdx.x; item < count; item += gridDim.x) {
-    for (int s = threadIdx.x; s < TBL; s += THREADS) {
-      s_keys[s] = kEmpty;
-      s_vals[s] = 0.0;
-    }
+    for (int s = threadIdx.x; s < TBL / 4; s += THREADS)
+      reinterpret_cast<int4 *>(s_keys)[s] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
+    for (int s = threadIdx.x; s < TBL / 2; s += THREADS) reinterpret_cast<double2 *>(s_vals)[s] = make_double2(0.0, 0.0);
     __syncthreads();
     const int32_t jj = list[item];
     src.visit(jj, w, NW, 0, 1, s_sc[w], status,
