@@ -187,25 +187,79 @@ struct SlabSel {
 // r_stride > 1 every wave reads every chunk and the rounds are split.  With
 // SLAB, only the terms whose row lies in the selected slabs are visited
 // (a.Ari/a.Av then point at the slabbed copies).
+// A column and the first chunk of its B entries loaded ahead of the column's
+// turn, in dependent steps placed where the current column has other work:
+// lp_cols (B's column pointers), lp_b (the chunk's rows and values of B),
+// lp_a (A's column pointers of those rows).  The column pointers are loaded
+// per lane (vector loads, so they do not hold up LDS waits) and made uniform
+// in lp_b.
+template <class VT>
+struct LightPre {
+  int64_t pbeg, pend;
+  int32_t k;
+  VT bv;
+  int64_t a0, a1;
+};
+
+__device__ __forceinline__ int64_t first_lane64(int64_t v) {
+  return (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v) |
+         ((int64_t)__builtin_amdgcn_readfirstlane((int)((uint64_t)v >> 32)) << 32);
+}
+
+template <bool VALUES, class VT>
+__device__ __forceinline__ void lp_cols(const ProductArgs<VT> &a, int64_t col, LightPre<VT> &pre) {
+  const int64_t z = opaque((int64_t)0);  // a per-lane address: a vector load
+  pre.pbeg = ld_global(a.Bcp + col + z);
+  pre.pend = ld_global(a.Bcp + col + 1 + z);
+}
+
+template <bool VALUES, class VT>
+__device__ __forceinline__ void lp_b(const ProductArgs<VT> &a, LightPre<VT> &pre) {
+  pre.pbeg = first_lane64(pre.pbeg);
+  pre.pend = first_lane64(pre.pend);
+  const int64_t p = pre.pbeg + lane();
+  pre.k = -1;
+  pre.bv = VT(0);
+  if (p < pre.pend) {
+    pre.k = a.Bri[p];
+    if (VALUES) pre.bv = a.Bv[p];
+  }
+}
+
+template <bool VALUES, class VT>
+__device__ __forceinline__ void lp_a(const ProductArgs<VT> &a, LightPre<VT> &pre) {
+  const int32_t k = pre.k;
+  pre.a0 = 0;
+  pre.a1 = 0;
+  if (k >= 0 && (int64_t)k < a.kdim && k >= a.klo && k < a.khi) {
+    pre.a0 = a.Acp[k];
+    pre.a1 = a.Acp[k + 1];
+  }
+}
+
 template <bool VALUES, class VT, bool SLAB = false, class Ins>
 __device__ __forceinline__ void traverse_product(const ProductArgs<VT> &a, int64_t col, int64_t c_rank,
                                                  int64_t c_stride, int64_t r_rank, int64_t r_stride,
                                                  SegScratch &sc, int32_t *status, Ins &&ins,
-                                                 SlabSel sl = SlabSel{nullptr, 0, 0, 0}) {
+                                                 SlabSel sl = SlabSel{nullptr, 0, 0, 0},
+                                                 const LightPre<VT> *pre = nullptr) {
+  // pre (non-SLAB, c_rank = 0 only): the column's B range and its first
+  // chunk, loaded ahead by lp_cols / lp_b / lp_a
   const int l = lane();
-  const int64_t pbeg = a.Bcp[col], pend = a.Bcp[col + 1];
+  const int64_t pbeg = pre ? pre->pbeg : a.Bcp[col], pend = pre ? pre->pend : a.Bcp[col + 1];
   int64_t rounds_before = 0;
   for (int64_t base = pbeg + c_rank * kWave; base < pend; base += c_stride * kWave) {
     const int64_t p = base + l;
+    const bool first_pre = !SLAB && pre && base == pbeg;  // uniform
     int len = 0;
     int64_t off = 0;
     double b = 0.0;
     if (p < pend) {
-      const int32_t k = a.Bri[p];
+      const int32_t k = first_pre ? pre->k : a.Bri[p];
       if ((uint64_t)(uint32_t)k >= (uint64_t)a.kdim || k < 0) {
         flag_error(status, 1);
       } else if (k >= a.klo && k < a.khi) {
-        const int64_t a0 = a.Acp[k];
+        const int64_t a0 = first_pre ? pre->a0 : a.Acp[k];
         int64_t d;
         if (SLAB) {
           const int32_t *o = sl.off + (int64_t)(k - a.klo) * (sl.P + 1);
@@ -213,7 +267,7 @@ __device__ __forceinline__ void traverse_product(const ProductArgs<VT> &a, int64
           d = o[sl.sb] - s0;
           off = a0 + s0;
         } else {
-          d = a.Acp[k + 1] - a0;
+          d = (first_pre ? pre->a1 : a.Acp[k + 1]) - a0;
           off = a0;
         }
         if (d < 0 || d >= kMaxAdeg) {
@@ -221,7 +275,7 @@ __device__ __forceinline__ void traverse_product(const ProductArgs<VT> &a, int64
           off = 0;
         } else {
           len = (int)d;
-          if (VALUES) b = (double)a.Bv[p];
+          if (VALUES) b = (double)(first_pre ? pre->bv : a.Bv[p]);
         }
       }
     }
@@ -563,6 +617,17 @@ template <class VT>
 struct ProductSrc {
   ProductArgs<VT> a;
   int64_t c0;
+  using Pre = LightPre<VT>;
+  __device__ __forceinline__ void pre_cols(int64_t jj, Pre &pre) const { lp_cols<true, VT>(a, c0 + jj, pre); }
+  __device__ __forceinline__ void pre_b(Pre &pre) const { lp_b<true, VT>(a, pre); }
+  __device__ __forceinline__ void pre_a(Pre &pre) const { lp_a<true, VT>(a, pre); }
+  // one wave on the whole column, its first chunk loaded ahead
+  template <class Ins>
+  __device__ __forceinline__ void visit_pre(int64_t jj, const Pre &pre, void *scratch, int32_t *status,
+                                            Ins &&ins) const {
+    traverse_product<true, VT>(a, c0 + jj, 0, 1, 0, 1, *(SegScratch *)scratch, status, ins,
+                               SlabSel{nullptr, 0, 0, 0}, &pre);
+  }
   template <class Ins>
   __device__ __forceinline__ void visit(int64_t jj, int64_t c_rank, int64_t c_stride, int64_t r_rank,
                                         int64_t r_stride, void *scratch, int32_t *status, Ins &&ins) const {
@@ -579,6 +644,15 @@ struct MergeSrc {
   const PartDesc *P;
   int nparts;
   int64_t m;
+  struct Pre {};  // the part descriptors are the input: nothing to load ahead
+  __device__ __forceinline__ void pre_cols(int64_t, Pre &) const {}
+  __device__ __forceinline__ void pre_b(Pre &) const {}
+  __device__ __forceinline__ void pre_a(Pre &) const {}
+  template <class Ins>
+  __device__ __forceinline__ void visit_pre(int64_t jj, const Pre &, void *scratch, int32_t *status,
+                                            Ins &&ins) const {
+    visit(jj, 0, 1, 0, 1, scratch, status, ins);
+  }
   template <class Ins>
   __device__ __forceinline__ void visit(int64_t jj, int64_t c_rank, int64_t c_stride, int64_t r_rank,
                                         int64_t r_stride, void *scratch, int32_t *status, Ins &&ins) const {
@@ -642,16 +716,45 @@ __global__ __launch_bounds__(256) void k_num_wave(Src src, const int32_t *list, 
   int32_t *keys = s_keys[w];
   double *vals = s_vals[w];
   init_mark<VT>(s_sc[w]);
-  for (int idx = blockIdx.x * 4 + w; idx < count; idx += gridDim.x * 4) {
+  // columns idx, idx + stride, ...: while one is processed, the next one's
+  // output range, B range and first chunk are loaded (Src::pre_*), and the
+  // list entry of the one after
+  const int stride = gridDim.x * 4;
+  int idx = blockIdx.x * 4 + w;
+  const int64_t z = opaque((int64_t)0);  // per-lane addresses: vector loads
+  typename Src::Pre pre;
+  int32_t jn = 0;
+  int64_t cb = 0, ce = 0;
+  if (idx < count) {
+    jn = __builtin_amdgcn_readfirstlane(ld_global(list + idx + z));
+    src.pre_cols(jn, pre);
+    cb = ld_global(c_colptr + jn + z);
+    ce = ld_global(c_colptr + jn + 1 + z);
+    src.pre_b(pre);
+    src.pre_a(pre);
+  }
+  int32_t jn2 = idx + stride < count ? ld_global(list + idx + stride + z) : 0;
+  for (; idx < count; idx += stride) {
+    const int32_t jj = jn;
+    const int64_t base = first_lane64(cb), cap = first_lane64(ce) - base;
+    const typename Src::Pre cur = pre;
+    const bool more = idx + stride < count;  // uniform
+    if (more) {
+      jn = __builtin_amdgcn_readfirstlane(jn2);
+      src.pre_cols(jn, pre);
+      cb = ld_global(c_colptr + jn + z);
+      ce = ld_global(c_colptr + jn + 1 + z);
+      jn2 = idx + 2 * stride < count ? ld_global(list + idx + 2 * stride + z) : 0;
+    }
     for (int s = l; s < TBL / 4; s += kWave) reinterpret_cast<int4 *>(keys)[s] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
     for (int s = l; s < TBL / 2; s += kWave) reinterpret_cast<double2 *>(vals)[s] = make_double2(0.0, 0.0);
     wave_sync();
-    const int32_t jj = list[idx];
-    src.visit(jj, 0, 1, 0, 1, s_sc[w], status, [&](int32_t row, double v) { ht_accumulate(keys, vals, TBL, row, v); });
+    src.visit_pre(jj, cur, s_sc[w], status, [&](int32_t row, double v) { ht_accumulate(keys, vals, TBL, row, v); });
+    if (more) src.pre_b(pre);
     wave_sync();
-    const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
     // one wave owns the column: output positions follow a running count
     const int64_t o = compact_run<VT>(keys, vals, 0, TBL, base, base + cap, out_ri, out_v);
+    if (more) src.pre_a(pre);
     if (l == 0 && o - base != cap) flag_error(status, 4);
     wave_sync();
   }
