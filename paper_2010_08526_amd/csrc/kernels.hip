@@ -213,11 +213,14 @@ __device__ __forceinline__ void lp_cols(const ProductArgs<VT> &a, int64_t col, L
   pre.pend = ld_global(a.Bcp + col + 1 + z);
 }
 
+// The chunk is the one wave w of nw reads first: w when the column has at
+// least 2 nw chunks (the waves split the chunks), else chunk 0.
 template <bool VALUES, class VT>
-__device__ __forceinline__ void lp_b(const ProductArgs<VT> &a, LightPre<VT> &pre) {
+__device__ __forceinline__ void lp_b(const ProductArgs<VT> &a, LightPre<VT> &pre, int w, int nw) {
   pre.pbeg = first_lane64(pre.pbeg);
   pre.pend = first_lane64(pre.pend);
-  const int64_t p = pre.pbeg + lane();
+  const int64_t nchunks = (pre.pend - pre.pbeg + kWave - 1) / kWave;
+  const int64_t p = pre.pbeg + (nchunks >= 2 * nw ? (int64_t)w * kWave : 0) + lane();
   pre.k = -1;
   pre.bv = VT(0);
   if (p < pre.pend) {
@@ -243,14 +246,14 @@ __device__ __forceinline__ void traverse_product(const ProductArgs<VT> &a, int64
                                                  SegScratch &sc, int32_t *status, Ins &&ins,
                                                  SlabSel sl = SlabSel{nullptr, 0, 0, 0},
                                                  const LightPre<VT> *pre = nullptr) {
-  // pre (non-SLAB, c_rank = 0 only): the column's B range and its first
-  // chunk, loaded ahead by lp_cols / lp_b / lp_a
+  // pre (non-SLAB): the column's B range and this wave's first chunk,
+  // loaded ahead by lp_cols / lp_b / lp_a
   const int l = lane();
   const int64_t pbeg = pre ? pre->pbeg : a.Bcp[col], pend = pre ? pre->pend : a.Bcp[col + 1];
   int64_t rounds_before = 0;
   for (int64_t base = pbeg + c_rank * kWave; base < pend; base += c_stride * kWave) {
     const int64_t p = base + l;
-    const bool first_pre = !SLAB && pre && base == pbeg;  // uniform
+    const bool first_pre = !SLAB && pre && base == pbeg + c_rank * kWave;  // uniform
     int len = 0;
     int64_t off = 0;
     double b = 0.0;
@@ -331,12 +334,13 @@ __device__ __forceinline__ void traverse_product(const ProductArgs<VT> &a, int64
 template <bool VALUES, class VT, bool SLAB = false, class Ins>
 __device__ __forceinline__ void traverse_product_block(const ProductArgs<VT> &a, int64_t col, int w, int nw,
                                                        SegScratch &sc, int32_t *status, Ins &&ins,
-                                                       SlabSel sl = SlabSel{nullptr, 0, 0, 0}) {
-  const int64_t nchunks = (a.Bcp[col + 1] - a.Bcp[col] + kWave - 1) / kWave;
+                                                       SlabSel sl = SlabSel{nullptr, 0, 0, 0},
+                                                       const LightPre<VT> *pre = nullptr) {
+  const int64_t nchunks = ((pre ? pre->pend - pre->pbeg : a.Bcp[col + 1] - a.Bcp[col]) + kWave - 1) / kWave;
   if (nchunks >= 2 * nw)
-    traverse_product<VALUES, VT, SLAB>(a, col, w, nw, 0, 1, sc, status, ins, sl);
+    traverse_product<VALUES, VT, SLAB>(a, col, w, nw, 0, 1, sc, status, ins, sl, pre);
   else
-    traverse_product<VALUES, VT, SLAB>(a, col, 0, 1, w, nw, sc, status, ins, sl);
+    traverse_product<VALUES, VT, SLAB>(a, col, 0, 1, w, nw, sc, status, ins, sl, pre);
 }
 
 // Visits every stored entry of column `col` of the parts: ins(i, value).
@@ -619,7 +623,7 @@ struct ProductSrc {
   int64_t c0;
   using Pre = LightPre<VT>;
   __device__ __forceinline__ void pre_cols(int64_t jj, Pre &pre) const { lp_cols<true, VT>(a, c0 + jj, pre); }
-  __device__ __forceinline__ void pre_b(Pre &pre) const { lp_b<true, VT>(a, pre); }
+  __device__ __forceinline__ void pre_b(Pre &pre, int w, int nw) const { lp_b<true, VT>(a, pre, w, nw); }
   __device__ __forceinline__ void pre_a(Pre &pre) const { lp_a<true, VT>(a, pre); }
   // one wave on the whole column, its first chunk loaded ahead
   template <class Ins>
@@ -627,6 +631,13 @@ struct ProductSrc {
                                             Ins &&ins) const {
     traverse_product<true, VT>(a, c0 + jj, 0, 1, 0, 1, *(SegScratch *)scratch, status, ins,
                                SlabSel{nullptr, 0, 0, 0}, &pre);
+  }
+  // the waves of a workgroup on one column (chunks or rounds split)
+  template <class Ins>
+  __device__ __forceinline__ void visit_pre_block(int64_t jj, const Pre &pre, int w, int nw, void *scratch,
+                                                  int32_t *status, Ins &&ins) const {
+    traverse_product_block<true, VT>(a, c0 + jj, w, nw, *(SegScratch *)scratch, status, ins,
+                                     SlabSel{nullptr, 0, 0, 0}, &pre);
   }
   template <class Ins>
   __device__ __forceinline__ void visit(int64_t jj, int64_t c_rank, int64_t c_stride, int64_t r_rank,
@@ -646,12 +657,17 @@ struct MergeSrc {
   int64_t m;
   struct Pre {};  // the part descriptors are the input: nothing to load ahead
   __device__ __forceinline__ void pre_cols(int64_t, Pre &) const {}
-  __device__ __forceinline__ void pre_b(Pre &) const {}
+  __device__ __forceinline__ void pre_b(Pre &, int, int) const {}
   __device__ __forceinline__ void pre_a(Pre &) const {}
   template <class Ins>
   __device__ __forceinline__ void visit_pre(int64_t jj, const Pre &, void *scratch, int32_t *status,
                                             Ins &&ins) const {
     visit(jj, 0, 1, 0, 1, scratch, status, ins);
+  }
+  template <class Ins>
+  __device__ __forceinline__ void visit_pre_block(int64_t jj, const Pre &, int w, int nw, void *scratch,
+                                                  int32_t *status, Ins &&ins) const {
+    visit(jj, w, nw, 0, 1, scratch, status, ins);
   }
   template <class Ins>
   __device__ __forceinline__ void visit(int64_t jj, int64_t c_rank, int64_t c_stride, int64_t r_rank,
@@ -730,7 +746,7 @@ __global__ __launch_bounds__(256) void k_num_wave(Src src, const int32_t *list, 
     src.pre_cols(jn, pre);
     cb = ld_global(c_colptr + jn + z);
     ce = ld_global(c_colptr + jn + 1 + z);
-    src.pre_b(pre);
+    src.pre_b(pre, 0, 1);
     src.pre_a(pre);
   }
   int32_t jn2 = idx + stride < count ? ld_global(list + idx + stride + z) : 0;
@@ -750,7 +766,7 @@ __global__ __launch_bounds__(256) void k_num_wave(Src src, const int32_t *list, 
     for (int s = l; s < TBL / 2; s += kWave) reinterpret_cast<double2 *>(vals)[s] = make_double2(0.0, 0.0);
     wave_sync();
     src.visit_pre(jj, cur, s_sc[w], status, [&](int32_t row, double v) { ht_accumulate(keys, vals, TBL, row, v); });
-    if (more) src.pre_b(pre);
+    if (more) src.pre_b(pre, 0, 1);
     wave_sync();
     // one wave owns the column: output positions follow a running count
     const int64_t o = compact_run<VT>(keys, vals, 0, TBL, base, base + cap, out_ri, out_v);
@@ -773,16 +789,42 @@ __global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *l
   const int w = threadIdx.x / kWave, l = lane();
   const int count = *count_p;
   init_mark<VT>(s_sc[w]);
-  for (int item = blockIdx.x; item < count; item += gridDim.x) {
+  // columns item, item + gridDim.x, ...: the next column's output range, B
+  // range and each wave's first chunk are loaded while one is processed
+  const int64_t z = opaque((int64_t)0);  // per-lane addresses: vector loads
+  int item = blockIdx.x;
+  typename Src::Pre pre;
+  int32_t jn = 0;
+  int64_t cb = 0, ce = 0;
+  if (item < count) {
+    jn = __builtin_amdgcn_readfirstlane(ld_global(list + item + z));
+    src.pre_cols(jn, pre);
+    cb = ld_global(c_colptr + jn + z);
+    ce = ld_global(c_colptr + jn + 1 + z);
+    src.pre_b(pre, w, NW);
+    src.pre_a(pre);
+  }
+  int32_t jn2 = item + (int)gridDim.x < count ? ld_global(list + item + gridDim.x + z) : 0;
+  for (; item < count; item += gridDim.x) {
+    const int32_t jj = jn;
+    const int64_t base = first_lane64(cb), cap = first_lane64(ce) - base;
+    const typename Src::Pre cur = pre;
+    const bool more = item + (int)gridDim.x < count;  // uniform
+    if (more) {
+      jn = __builtin_amdgcn_readfirstlane(jn2);
+      src.pre_cols(jn, pre);
+      cb = ld_global(c_colptr + jn + z);
+      ce = ld_global(c_colptr + jn + 1 + z);
+      jn2 = item + 2 * (int)gridDim.x < count ? ld_global(list + item + 2 * gridDim.x + z) : 0;
+    }
     for (int s = threadIdx.x; s < TBL / 4; s += THREADS)
       reinterpret_cast<int4 *>(s_keys)[s] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
     for (int s = threadIdx.x; s < TBL / 2; s += THREADS) reinterpret_cast<double2 *>(s_vals)[s] = make_double2(0.0, 0.0);
     __syncthreads();
-    const int32_t jj = list[item];
-    src.visit(jj, w, NW, 0, 1, s_sc[w], status,
-              [&](int32_t row, double v) { ht_accumulate(s_keys, s_vals, TBL, row, v); });
+    src.visit_pre_block(jj, cur, w, NW, s_sc[w], status,
+                        [&](int32_t row, double v) { ht_accumulate(s_keys, s_vals, TBL, row, v); });
+    if (more) src.pre_b(pre, w, NW);
     __syncthreads();
-    const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
     // wave w owns slots [w * PER, (w + 1) * PER): count them, scan the waves'
     // counts, then write at a running position
     constexpr int PER = (TBL + NW - 1) / NW;
@@ -791,6 +833,7 @@ __global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *l
     int total;
     const int ex = block_excl<NW>(l == 0 ? cw : 0, s_w, total);
     compact_run<VT>(s_keys, s_vals, lo, hi, base + readlane(ex, 0), base + cap, out_ri, out_v);
+    if (more) src.pre_a(pre);
     if (threadIdx.x == 0 && total != cap) flag_error(status, 4);
     __syncthreads();
   }
