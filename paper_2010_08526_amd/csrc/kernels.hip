@@ -528,16 +528,39 @@ __global__ __launch_bounds__(256) void k_sym_wave(ProductArgs<float> a, int64_t 
   int32_t *keys = s_keys[w];
   SegScratch &sc = s_sc[w];
   sc.mark[l] = 0;
-  for (int idx = blockIdx.x * 4 + w; idx < count; idx += gridDim.x * 4) {
+  // the next column's B range and first chunk are loaded while one is counted
+  const int stride = gridDim.x * 4;
+  int idx = blockIdx.x * 4 + w;
+  const int64_t z = opaque((int64_t)0);  // per-lane addresses: vector loads
+  LightPre<float> pre;
+  int32_t jn = 0;
+  if (idx < count) {
+    jn = __builtin_amdgcn_readfirstlane(ld_global(list + idx + z));
+    lp_cols<false, float>(a, c0 + jn, pre);
+    lp_b<false, float>(a, pre, 0, 1);
+    lp_a<false, float>(a, pre);
+  }
+  int32_t jn2 = idx + stride < count ? ld_global(list + idx + stride + z) : 0;
+  for (; idx < count; idx += stride) {
+    const int32_t jj = jn;
+    const LightPre<float> cur = pre;
+    const bool more = idx + stride < count;  // uniform
+    if (more) {
+      jn = __builtin_amdgcn_readfirstlane(jn2);
+      lp_cols<false, float>(a, c0 + jn, pre);
+      jn2 = idx + 2 * stride < count ? ld_global(list + idx + 2 * stride + z) : 0;
+    }
     for (int s = l; s < TBL; s += kWave) keys[s] = kEmpty;
     wave_sync();
-    const int32_t jj = list[idx];
     int cnt = 0;
-    traverse_product<false, float>(a, c0 + jj, 0, 1, 0, 1, sc, status, [&](int32_t row, double) {
-      cnt += ht_insert_key(keys, TBL, row) ? 1 : 0;
-    });
+    traverse_product<false, float>(
+        a, c0 + jj, 0, 1, 0, 1, sc, status,
+        [&](int32_t row, double) { cnt += ht_insert_key(keys, TBL, row) ? 1 : 0; }, SlabSel{nullptr, 0, 0, 0},
+        &cur);
+    if (more) lp_b<false, float>(a, pre, 0, 1);
     cnt = wave_sum_i32(cnt);
     if (l == 0) nnz_out[jj] = cnt;
+    if (more) lp_a<false, float>(a, pre);
     wave_sync();
   }
 }
@@ -553,19 +576,42 @@ __global__ __launch_bounds__(THREADS) void k_sym_block(ProductArgs<float> a, int
   const int w = threadIdx.x / kWave, l = lane();
   const int count = *count_p;
   s_sc[w].mark[l] = 0;
-  for (int item = blockIdx.x; item < count; item += gridDim.x) {
+  // the next column's B range and each wave's first chunk are loaded while
+  // one is counted
+  const int64_t z = opaque((int64_t)0);  // per-lane addresses: vector loads
+  int item = blockIdx.x;
+  LightPre<float> pre;
+  int32_t jn = 0;
+  if (item < count) {
+    jn = __builtin_amdgcn_readfirstlane(ld_global(list + item + z));
+    lp_cols<false, float>(a, c0 + jn, pre);
+    lp_b<false, float>(a, pre, w, NW);
+    lp_a<false, float>(a, pre);
+  }
+  int32_t jn2 = item + (int)gridDim.x < count ? ld_global(list + item + gridDim.x + z) : 0;
+  for (; item < count; item += gridDim.x) {
+    const int32_t jj = jn;
+    const LightPre<float> cur = pre;
+    const bool more = item + (int)gridDim.x < count;  // uniform
+    if (more) {
+      jn = __builtin_amdgcn_readfirstlane(jn2);
+      lp_cols<false, float>(a, c0 + jn, pre);
+      jn2 = item + 2 * (int)gridDim.x < count ? ld_global(list + item + 2 * gridDim.x + z) : 0;
+    }
     for (int s = threadIdx.x; s < TBL; s += THREADS) s_keys[s] = kEmpty;
     if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
-    const int32_t jj = list[item];
     int cnt = 0;
-    traverse_product_block<false, float>(a, c0 + jj, w, NW, s_sc[w], status, [&](int32_t row, double) {
-      cnt += ht_insert_key(s_keys, TBL, row) ? 1 : 0;
-    });
+    traverse_product_block<false, float>(
+        a, c0 + jj, w, NW, s_sc[w], status,
+        [&](int32_t row, double) { cnt += ht_insert_key(s_keys, TBL, row) ? 1 : 0; }, SlabSel{nullptr, 0, 0, 0},
+        &cur);
+    if (more) lp_b<false, float>(a, pre, w, NW);
     cnt = wave_sum_i32(cnt);
     if (l == 0) atomicAdd(&s_cnt, cnt);
     __syncthreads();
     if (threadIdx.x == 0) nnz_out[jj] = s_cnt;
+    if (more) lp_a<false, float>(a, pre);
     __syncthreads();
   }
 }
