@@ -529,8 +529,8 @@ __global__ __launch_bounds__(256) void k_sym_wave(ProductArgs<float> a, int64_t 
   SegScratch &sc = s_sc[w];
   sc.mark[l] = 0;
   // the next column's B range and first chunk are loaded while one is counted
-  const int stride = gridDim.x * 4;
-  int idx = blockIdx.x * 4 + w;
+  const int64_t stride = (int64_t)gridDim.x * 4;  // 64-bit: no overflow near 2^31 columns
+  int64_t idx = (int64_t)blockIdx.x * 4 + w;
   const int64_t z = opaque((int64_t)0);  // per-lane addresses: vector loads
   LightPre<float> pre;
   int32_t jn = 0;
@@ -579,7 +579,7 @@ __global__ __launch_bounds__(THREADS) void k_sym_block(ProductArgs<float> a, int
   // the next column's B range and each wave's first chunk are loaded while
   // one is counted
   const int64_t z = opaque((int64_t)0);  // per-lane addresses: vector loads
-  int item = blockIdx.x;
+  int64_t item = blockIdx.x;  // 64-bit: no overflow near 2^31 columns
   LightPre<float> pre;
   int32_t jn = 0;
   if (item < count) {
@@ -588,15 +588,15 @@ __global__ __launch_bounds__(THREADS) void k_sym_block(ProductArgs<float> a, int
     lp_b<false, float>(a, pre, w, NW);
     lp_a<false, float>(a, pre);
   }
-  int32_t jn2 = item + (int)gridDim.x < count ? ld_global(list + item + gridDim.x + z) : 0;
+  int32_t jn2 = item + (int64_t)gridDim.x < count ? ld_global(list + item + (int64_t)gridDim.x + z) : 0;
   for (; item < count; item += gridDim.x) {
     const int32_t jj = jn;
     const LightPre<float> cur = pre;
-    const bool more = item + (int)gridDim.x < count;  // uniform
+    const bool more = item + (int64_t)gridDim.x < count;  // uniform
     if (more) {
       jn = __builtin_amdgcn_readfirstlane(jn2);
       lp_cols<false, float>(a, c0 + jn, pre);
-      jn2 = item + 2 * (int)gridDim.x < count ? ld_global(list + item + 2 * gridDim.x + z) : 0;
+      jn2 = item + 2 * (int64_t)gridDim.x < count ? ld_global(list + item + 2 * (int64_t)gridDim.x + z) : 0;
     }
     for (int s = threadIdx.x; s < TBL; s += THREADS) s_keys[s] = kEmpty;
     if (threadIdx.x == 0) s_cnt = 0;
@@ -781,8 +781,8 @@ __global__ __launch_bounds__(256) void k_num_wave(Src src, const int32_t *list, 
   // columns idx, idx + stride, ...: while one is processed, the next one's
   // output range, B range and first chunk are loaded (Src::pre_*), and the
   // list entry of the one after
-  const int stride = gridDim.x * 4;
-  int idx = blockIdx.x * 4 + w;
+  const int64_t stride = (int64_t)gridDim.x * 4;  // 64-bit: no overflow near 2^31 columns
+  int64_t idx = (int64_t)blockIdx.x * 4 + w;
   const int64_t z = opaque((int64_t)0);  // per-lane addresses: vector loads
   typename Src::Pre pre;
   int32_t jn = 0;
@@ -838,7 +838,7 @@ __global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *l
   // columns item, item + gridDim.x, ...: the next column's output range, B
   // range and each wave's first chunk are loaded while one is processed
   const int64_t z = opaque((int64_t)0);  // per-lane addresses: vector loads
-  int item = blockIdx.x;
+  int64_t item = blockIdx.x;  // 64-bit: no overflow near 2^31 columns
   typename Src::Pre pre;
   int32_t jn = 0;
   int64_t cb = 0, ce = 0;
@@ -850,18 +850,18 @@ __global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *l
     src.pre_b(pre, w, NW);
     src.pre_a(pre);
   }
-  int32_t jn2 = item + (int)gridDim.x < count ? ld_global(list + item + gridDim.x + z) : 0;
+  int32_t jn2 = item + (int64_t)gridDim.x < count ? ld_global(list + item + (int64_t)gridDim.x + z) : 0;
   for (; item < count; item += gridDim.x) {
     const int32_t jj = jn;
     const int64_t base = first_lane64(cb), cap = first_lane64(ce) - base;
     const typename Src::Pre cur = pre;
-    const bool more = item + (int)gridDim.x < count;  // uniform
+    const bool more = item + (int64_t)gridDim.x < count;  // uniform
     if (more) {
       jn = __builtin_amdgcn_readfirstlane(jn2);
       src.pre_cols(jn, pre);
       cb = ld_global(c_colptr + jn + z);
       ce = ld_global(c_colptr + jn + 1 + z);
-      jn2 = item + 2 * (int)gridDim.x < count ? ld_global(list + item + 2 * gridDim.x + z) : 0;
+      jn2 = item + 2 * (int64_t)gridDim.x < count ? ld_global(list + item + 2 * (int64_t)gridDim.x + z) : 0;
     }
     for (int s = threadIdx.x; s < TBL / 4; s += THREADS)
       reinterpret_cast<int4 *>(s_keys)[s] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
