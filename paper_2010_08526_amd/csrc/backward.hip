@@ -414,9 +414,27 @@ struct FbArgs {
   int64_t m, kdim, nnzA;
 };
 
+// Scratch of one wave for the fused backward: the segments of a chunk of
+// B(:,j) (A entries of column k), flattened into rounds of 64 products.
+struct FbScratch {
+  int mark[kWave];
+  int64_t off[kWave];   // first A entry of the lane's segment minus its exclusive prefix
+  double scale[kWave];  // B(k,j) of the lane's segment
+  double db[kWave];     // the segment's dB(k,j) partial sum
+};
+constexpr int kFbPipe = 4;  // rounds whose gathers are in flight together
+
+// Entries (k,j) of B(:,j), 64 per chunk (chunk c by the wave with
+// c % c_stride == c_rank).  Segments A(:,k) shorter than kLongDot are
+// flattened into rounds of 64 products, one per lane (owner of each product
+// from a ballot, or an LDS marker and a max-scan when a segment starts inside
+// the round), so a column with few entries of B still fills the wave; each
+// product adds to dA(i,k) (float64 global atomics) and to its segment's
+// dB(k,j) (float64 LDS atomics).  Long segments are walked by the whole wave
+// with a wave reduction.  look(row) returns dC(row, j).
 template <class VT, class Look>
 __device__ __forceinline__ void fbwd_column(const FbArgs<VT> &a, int64_t j, int c_rank, int c_stride, int32_t *status,
-                                            Look &&look) {
+                                            FbScratch &sc, Look &&look) {
   const int l = lane();
   const int64_t pb = a.Bcp[j], pe = a.Bcp[j + 1];
   for (int64_t base = pb + (int64_t)c_rank * kWave; base < pe; base += (int64_t)c_stride * kWave) {
@@ -439,36 +457,65 @@ __device__ __forceinline__ void fbwd_column(const FbArgs<VT> &a, int64_t j, int 
     }
     const int len = (int)(x1 - x0);
     const bool lg = len >= kLongDot;
-    if (p < pe && !lg) {
-      double s = 0.0;
-      for (int t0 = 0; t0 < len; t0 += kDotUnroll) {
-        int32_t r[kDotUnroll];
-        VT av[kDotUnroll];
+    const int ls = (p < pe && !lg) ? len : 0;
+    const int incl = wave_incl_add(ls);
+    const int excl = incl - ls;
+    const int total = readlane(incl, kWave - 1);
+    sc.off[l] = x0 - excl;
+    sc.scale[l] = bkj;
+    sc.db[l] = 0.0;
+    wave_sync();
+    for (int r = 0; r * kWave < total; r += kFbPipe) {
+      int own_[kFbPipe];
 #pragma unroll
-        for (int t = 0; t < kDotUnroll; t++) {
-          r[t] = -1;
-          av[t] = VT(0);
-          if (t0 + t < len) {
-            r[t] = a.Ari[x0 + t0 + t];
-            av[t] = a.Av[x0 + t0 + t];
+      for (int u = 0; u < kFbPipe; u++) {
+        const int fb = (r + u) * kWave;
+        own_[u] = -1;
+        if (fb < total) {
+          const int last = min(fb + kWave - 1, total - 1);
+          const uint64_t started = __ballot(ls > 0 && excl <= fb);
+          const int carry = started ? 64 - __clzll((long long)started) : 0;
+          int own = carry;
+          if (__ballot(ls > 0 && excl <= last) != started) {
+            if (ls > 0 && excl > fb && excl < fb + kWave) sc.mark[excl - fb] = l + 1;
+            wave_sync();
+            const int mk = sc.mark[l];
+            sc.mark[l] = 0;
+            own = max(wave_incl_max(mk), carry);
+            wave_sync();
           }
+          if (fb + l < total) own_[u] = own - 1;
         }
+      }
+      int64_t q_[kFbPipe];
+      int32_t row_[kFbPipe];
+      VT av_[kFbPipe];
 #pragma unroll
-        for (int t = 0; t < kDotUnroll; t++) {
-          if (t0 + t < len) {
-            const int32_t rt = opaque(r[t]);
-            if ((uint32_t)rt < (uint32_t)a.m) {
-              const double g = look(rt);
-              s += (double)opaque(av[t]) * g;
-              atomicAdd(&a.dA[x0 + t0 + t], bkj * g);
-            } else {
-              flag_error(status, 3);
-            }
+      for (int u = 0; u < kFbPipe; u++) {
+        q_[u] = sc.off[max(own_[u], 0)] + (r + u) * kWave + l;
+        row_[u] = -1;
+        av_[u] = VT(0);
+        if (own_[u] >= 0) {
+          row_[u] = a.Ari[q_[u]];
+          av_[u] = a.Av[q_[u]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kFbPipe; u++) {
+        if (own_[u] >= 0) {
+          const int32_t rt = opaque(row_[u]);
+          if ((uint32_t)rt < (uint32_t)a.m) {
+            const double g = look(rt);
+            atomicAdd(&a.dA[q_[u]], sc.scale[own_[u]] * g);
+            atomicAdd(&sc.db[own_[u]], (double)opaque(av_[u]) * g);
+          } else {
+            flag_error(status, 3);
           }
         }
       }
-      a.dB[p] = (VT)s;
     }
+    wave_sync();
+    if (p < pe && !lg) a.dB[p] = (VT)sc.db[l];
     uint64_t lm = __ballot(p < pe && lg);
     while (lm) {
       const int L = __builtin_ctzll(lm);
@@ -489,6 +536,7 @@ __device__ __forceinline__ void fbwd_column(const FbArgs<VT> &a, int64_t j, int 
       for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
       if (l == 0) a.dB[base + L] = (VT)s;
     }
+    wave_sync();  // sc is rewritten by the next chunk
   }
 }
 
@@ -497,10 +545,12 @@ __global__ __launch_bounds__(256) void k_fbwd_wave(FbArgs<VT> a, const int32_t *
                                                    int32_t *status) {
   __shared__ int32_t s_keys[4][TBL];
   __shared__ double s_vals[4][TBL];
+  __shared__ FbScratch s_fb[4];
   const int w = threadIdx.x / kWave, l = lane();
   const int count = *count_p;
   int32_t *keys = s_keys[w];
   double *vals = s_vals[w];
+  s_fb[w].mark[l] = 0;
   for (int idx = blockIdx.x * 4 + w; idx < count; idx += gridDim.x * 4) {
     for (int s = l; s < TBL; s += kWave) {
       keys[s] = kEmpty;
@@ -516,7 +566,7 @@ __global__ __launch_bounds__(256) void k_fbwd_wave(FbArgs<VT> a, const int32_t *
         flag_error(status, 3);
     }
     wave_sync();
-    fbwd_column(a, j, 0, 1, status, [&](int32_t r) { return ht_lookup(keys, vals, TBL, r); });
+    fbwd_column(a, j, 0, 1, status, s_fb[w], [&](int32_t r) { return ht_lookup(keys, vals, TBL, r); });
     wave_sync();
   }
 }
@@ -527,8 +577,10 @@ __global__ __launch_bounds__(THREADS) void k_fbwd_block(FbArgs<VT> a, const int3
   constexpr int NW = THREADS / kWave;
   __shared__ int32_t s_keys[TBL];
   __shared__ double s_vals[TBL];
+  __shared__ FbScratch s_fb[NW];
   const int w = threadIdx.x / kWave;
   const int count = *count_p;
+  s_fb[w].mark[lane()] = 0;
   for (int item = blockIdx.x; item < count; item += gridDim.x) {
     for (int s = threadIdx.x; s < TBL; s += THREADS) {
       s_keys[s] = kEmpty;
@@ -544,7 +596,7 @@ __global__ __launch_bounds__(THREADS) void k_fbwd_block(FbArgs<VT> a, const int3
         flag_error(status, 3);
     }
     __syncthreads();
-    fbwd_column(a, j, w, NW, status, [&](int32_t r) { return ht_lookup(s_keys, s_vals, TBL, r); });
+    fbwd_column(a, j, w, NW, status, s_fb[w], [&](int32_t r) { return ht_lookup(s_keys, s_vals, TBL, r); });
     __syncthreads();
   }
 }
