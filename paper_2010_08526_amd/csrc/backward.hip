@@ -130,16 +130,28 @@ __global__ __launch_bounds__(256) void k_mxty_bin(const int64_t *Ycp, const int6
   if (bin >= 0) bins[(int64_t)bin * ncol + s_base[bin] + s_pos[t]] = (int32_t)j;
 }
 
-constexpr int kDotUnroll = 8;
 constexpr int kLongDot = 64;
+
+// Scratch of one wave for the masked dot products and the fused backward:
+// the segments of a chunk of 64 entries (a column of X or A each), flattened
+// into rounds of 64 products.
+struct FbScratch {
+  int mark[kWave];
+  int64_t off[kWave];   // first A entry of the lane's segment minus its exclusive prefix
+  double scale[kWave];  // B(k,j) of the lane's segment (fused backward)
+  double db[kWave];     // the segment's dot product, summed by LDS atomics
+};
+constexpr int kFbPipe = 4;  // rounds whose gathers are in flight together
 
 // Dot products for the entries [pb, pe) of M(:,j) taken in chunks of 64
 // (chunk c by the wave with c % c_stride == c_rank).  Short X columns are
-// summed by their lane, kDotUnroll loads at a time; long ones by the whole
-// wave with a wave reduction.  look(row) returns Y(row, j).
+// flattened into rounds of 64 products, one per lane (owners as in the
+// forward traversal), and each entry's sum is gathered by LDS atomics; long
+// ones are summed by the whole wave with a wave reduction.  look(row)
+// returns Y(row, j).
 template <class VT, class Look>
 __device__ __forceinline__ void mxty_dots(const MxtyArgs<VT> &a, int64_t pb, int64_t pe, int c_rank, int c_stride,
-                                          int32_t *status, Look &&look) {
+                                          int32_t *status, FbScratch &sc, Look &&look) {
   const int l = lane();
   for (int64_t base = pb + (int64_t)c_rank * kWave; base < pe; base += (int64_t)c_stride * kWave) {
     const int64_t p = base + l;
@@ -159,33 +171,60 @@ __device__ __forceinline__ void mxty_dots(const MxtyArgs<VT> &a, int64_t pb, int
     }
     const int len = (int)(x1 - x0);
     const bool lg = len >= kLongDot;
-    if (p < pe && !lg) {
-      double s = 0.0;
-      for (int t0 = 0; t0 < len; t0 += kDotUnroll) {
-        int32_t r[kDotUnroll];
-        VT xv[kDotUnroll];
+    const int ls = (p < pe && !lg) ? len : 0;
+    const int incl = wave_incl_add(ls);
+    const int excl = incl - ls;
+    const int total = readlane(incl, kWave - 1);
+    sc.off[l] = x0 - excl;
+    sc.db[l] = 0.0;
+    wave_sync();
+    for (int r = 0; r * kWave < total; r += kFbPipe) {
+      int own_[kFbPipe];
 #pragma unroll
-        for (int t = 0; t < kDotUnroll; t++) {
-          r[t] = -1;
-          xv[t] = VT(0);
-          if (t0 + t < len) {
-            r[t] = a.Xri[x0 + t0 + t];
-            xv[t] = a.Xv[x0 + t0 + t];
+      for (int u = 0; u < kFbPipe; u++) {
+        const int fb = (r + u) * kWave;
+        own_[u] = -1;
+        if (fb < total) {
+          const int last = min(fb + kWave - 1, total - 1);
+          const uint64_t started = __ballot(ls > 0 && excl <= fb);
+          const int carry = started ? 64 - __clzll((long long)started) : 0;
+          int own = carry;
+          if (__ballot(ls > 0 && excl <= last) != started) {
+            if (ls > 0 && excl > fb && excl < fb + kWave) sc.mark[excl - fb] = l + 1;
+            wave_sync();
+            const int mk = sc.mark[l];
+            sc.mark[l] = 0;
+            own = max(wave_incl_max(mk), carry);
+            wave_sync();
           }
-        }
-#pragma unroll
-        for (int t = 0; t < kDotUnroll; t++) {
-          if (t0 + t < len) {
-            const int32_t rt = opaque(r[t]);
-            if ((uint32_t)rt < (uint32_t)a.m)
-              s += (double)opaque(xv[t]) * look(rt);
-            else
-              flag_error(status, 3);
-          }
+          if (fb + l < total) own_[u] = own - 1;
         }
       }
-      a.out[p] = (VT)s;
+      int32_t row_[kFbPipe];
+      VT xv_[kFbPipe];
+#pragma unroll
+      for (int u = 0; u < kFbPipe; u++) {
+        row_[u] = -1;
+        xv_[u] = VT(0);
+        if (own_[u] >= 0) {
+          const int64_t q = sc.off[own_[u]] + (r + u) * kWave + l;
+          row_[u] = a.Xri[q];
+          xv_[u] = a.Xv[q];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kFbPipe; u++) {
+        if (own_[u] >= 0) {
+          const int32_t rt = opaque(row_[u]);
+          if ((uint32_t)rt < (uint32_t)a.m)
+            atomicAdd(&sc.db[own_[u]], (double)opaque(xv_[u]) * look(rt));
+          else
+            flag_error(status, 3);
+        }
+      }
     }
+    wave_sync();
+    if (p < pe && !lg) a.out[p] = (VT)sc.db[l];
     uint64_t lm = __ballot(p < pe && lg);
     while (lm) {
       const int L = __builtin_ctzll(lm);
@@ -219,6 +258,7 @@ __device__ __forceinline__ void mxty_dots(const MxtyArgs<VT> &a, int64_t pb, int
       for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
       if (l == 0) a.out[base + L] = (VT)s;
     }
+    wave_sync();  // sc is rewritten by the next chunk
   }
 }
 
@@ -228,10 +268,12 @@ __global__ __launch_bounds__(256) void k_mxty_wave(MxtyArgs<VT> a, const int32_t
                                                    int32_t *status) {
   __shared__ int32_t s_keys[4][TBL];
   __shared__ double s_vals[4][TBL];
+  __shared__ FbScratch s_fb[4];
   const int w = threadIdx.x / kWave, l = lane();
   const int count = *count_p;
   int32_t *keys = s_keys[w];
   double *vals = s_vals[w];
+  s_fb[w].mark[l] = 0;
   for (int idx = blockIdx.x * 4 + w; idx < count; idx += gridDim.x * 4) {
     for (int s = l; s < TBL; s += kWave) {
       keys[s] = kEmpty;
@@ -247,7 +289,7 @@ __global__ __launch_bounds__(256) void k_mxty_wave(MxtyArgs<VT> a, const int32_t
         flag_error(status, 3);
     }
     wave_sync();
-    mxty_dots(a, a.Mcp[j], a.Mcp[j + 1], 0, 1, status, [&](int32_t r) { return ht_lookup(keys, vals, TBL, r); });
+    mxty_dots(a, a.Mcp[j], a.Mcp[j + 1], 0, 1, status, s_fb[w], [&](int32_t r) { return ht_lookup(keys, vals, TBL, r); });
     wave_sync();
   }
 }
@@ -259,8 +301,10 @@ __global__ __launch_bounds__(THREADS) void k_mxty_block(MxtyArgs<VT> a, const in
   constexpr int NW = THREADS / kWave;
   __shared__ int32_t s_keys[TBL];
   __shared__ double s_vals[TBL];
+  __shared__ FbScratch s_fb[NW];
   const int w = threadIdx.x / kWave;
   const int count = *count_p;
+  s_fb[w].mark[lane()] = 0;
   for (int item = blockIdx.x; item < count; item += gridDim.x) {
     for (int s = threadIdx.x; s < TBL; s += THREADS) {
       s_keys[s] = kEmpty;
@@ -276,7 +320,7 @@ __global__ __launch_bounds__(THREADS) void k_mxty_block(MxtyArgs<VT> a, const in
         flag_error(status, 3);
     }
     __syncthreads();
-    mxty_dots(a, a.Mcp[j], a.Mcp[j + 1], w, NW, status, [&](int32_t r) { return ht_lookup(s_keys, s_vals, TBL, r); });
+    mxty_dots(a, a.Mcp[j], a.Mcp[j + 1], w, NW, status, s_fb[w], [&](int32_t r) { return ht_lookup(s_keys, s_vals, TBL, r); });
     __syncthreads();
   }
 }
@@ -300,12 +344,14 @@ __global__ __launch_bounds__(256) void k_mxty_heavy_fill(MxtyArgs<VT> a, const i
 template <class VT>
 __global__ __launch_bounds__(256) void k_mxty_heavy_dot(MxtyArgs<VT> a, const int32_t *list, int first, int ns,
                                                         const double *dense, int parts, int32_t *status) {
+  __shared__ FbScratch s_fb[4];
   const int slot = blockIdx.x / parts, part = blockIdx.x % parts;
   if (slot >= ns) return;
   const int32_t j = list[first + slot];
   const double *d = dense + (int64_t)slot * a.m;
   const int w = threadIdx.x / kWave;
-  mxty_dots(a, a.Mcp[j], a.Mcp[j + 1], part * 4 + w, parts * 4, status, [&](int32_t r) { return d[r]; });
+  s_fb[w].mark[lane()] = 0;
+  mxty_dots(a, a.Mcp[j], a.Mcp[j + 1], part * 4 + w, parts * 4, status, s_fb[w], [&](int32_t r) { return d[r]; });
 }
 
 static unsigned mx_grid(int cnt, bool wave_kernel, int blocks_per_cu) {
@@ -414,15 +460,6 @@ struct FbArgs {
   int64_t m, kdim, nnzA;
 };
 
-// Scratch of one wave for the fused backward: the segments of a chunk of
-// B(:,j) (A entries of column k), flattened into rounds of 64 products.
-struct FbScratch {
-  int mark[kWave];
-  int64_t off[kWave];   // first A entry of the lane's segment minus its exclusive prefix
-  double scale[kWave];  // B(k,j) of the lane's segment
-  double db[kWave];     // the segment's dB(k,j) partial sum
-};
-constexpr int kFbPipe = 4;  // rounds whose gathers are in flight together
 
 // Entries (k,j) of B(:,j), 64 per chunk (chunk c by the wave with
 // c % c_stride == c_rank).  Segments A(:,k) shorter than kLongDot are
