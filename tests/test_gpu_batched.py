@@ -160,3 +160,31 @@ def test_autotune_changes_speed_not_results():
         eng.forward()
         got = host_sorted(eng.C)
         assert np.array_equal(got[1], ref[1]) and np.allclose(got[2], ref[2], rtol=1e-6, atol=0)
+
+
+def test_fused_backward_skewed_rmat():
+    """Fused backward on a skewed product: hub columns of A (64 or more
+    entries, walked by the whole wave) next to short ones (flattened into
+    rounds) in the same chunks of B(:,j)."""
+    print("case: fused backward rmat", flush=True)
+    Ah = synth.rmat(12, 8, 41, dtype=torch.float64)
+    A = Ah.to("cuda")
+    assert int(np.diff(Ah.colptr.numpy()).max()) >= 64
+    eng = Bt.BatchedEngine(A, A, backward=True)
+    eng.forward()
+    C = eng.C
+    col = torch.repeat_interleave(torch.arange(C.ncols, device="cuda"), C.colptr[1:] - C.colptr[:-1])
+    T = synth.target_values(C.rowidx, col, C.ncols, 5, torch.float64)
+    dC = (C.values - T).contiguous()
+    dA, dB = eng.backward(dC)
+    eng.check()
+    tA, tB = S.Backward(A, A, C)(dC)
+    assert torch.allclose(dA, tA, rtol=1e-11, atol=1e-12) and torch.allclose(dB, tB, rtol=1e-11, atol=1e-12)
+    P = oracle.spgemm(Ah, Ah)
+    pc = np.repeat(np.arange(P.ncols), np.diff(P.colptr))
+    Th = synth.target_values(torch.from_numpy(P.rowidx.astype(np.int64)), torch.from_numpy(pc), P.ncols, 5,
+                             torch.float64).numpy()
+    dCo = oracle.Mat(P.nrows, P.ncols, P.colptr, P.rowidx, P.values - Th)
+    gA, gB = oracle.grad_a(Ah, Ah, dCo), oracle.grad_b(Ah, Ah, dCo)
+    assert np.allclose(dA.cpu().numpy(), gA, rtol=1e-10, atol=1e-10)
+    assert np.allclose(dB.cpu().numpy(), gB, rtol=1e-10, atol=1e-10)
