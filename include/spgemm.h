@@ -301,6 +301,18 @@ int spgemm_ws_status(void *ws, void *stream);
  * malformed internal work item. */
 int spgemm_ws_status_code(void *ws, void *stream, int32_t *code_host);
 
+/* What a workspace keeps between calls: consecutive spgemm_numeric calls on
+ * one workspace with the same left operand and layer share the copy of A
+ * grouped by row slab that the heavy-column path builds (the copy is
+ * rebuilt unless a fingerprint of A's columns of the layer, formed on the
+ * device at every call from the column pointers, rows and value bits, equals
+ * the one it was built from; any other operation on the workspace clears
+ * it).  spgemm_ws_invalidate clears it explicitly, so that the next numeric
+ * call rebuilds it (for instance at the start of each product, to time a
+ * product on its own).  Asynchronous: one small kernel on `stream`, no
+ * allocation and no memset, so it can be captured in a graph. */
+int spgemm_ws_invalidate(void *ws, void *stream);
+
 /* Testing hook, process-wide, not thread-safe: from now on every column is
  * placed in bin `bin` or a later one (bins are ordered by table capacity,
  * 0 = smallest, 5 = heavy), so each kernel can be exercised on small

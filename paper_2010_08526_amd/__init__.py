@@ -49,6 +49,7 @@ _lib.spgemm_numeric.argtypes = [_P, _P, _i64, _i64, _i32, _i32, _vp, _vp, _vp, _
 _lib.spgemm_merge.argtypes = [_P, _i32, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.spgemm_ws_status.argtypes = [_vp, _vp]
 _lib.spgemm_ws_status_code.argtypes = [_vp, _vp, _vp]
+_lib.spgemm_ws_invalidate.argtypes = [_vp, _vp]
 _lib.spgemm_batched_forward.argtypes = [_P, _P, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.spgemm_batched_masked_xty.argtypes = [_P, _P, _P, _vp, _vp, _sz, _vp]
 _lib.spgemm_batched_backward.argtypes = [_P, _P, _P, _vp, _vp, _vp, _vp, _sz, _vp]
@@ -191,6 +192,11 @@ def ws_status(ws: torch.Tensor, stream=None) -> int:
     return int(_lib.spgemm_ws_status(_ptr(ws), _stream(stream)))
 
 
+def ws_invalidate(ws: torch.Tensor, stream=None):
+    """Drops what the workspace keeps between numeric calls (the slabbed copy of A)."""
+    _check(_lib.spgemm_ws_invalidate(_ptr(ws), _stream(stream)), "spgemm_ws_invalidate")
+
+
 def ws_status_code(ws: torch.Tensor, stream=None) -> tuple[int, int]:
     """(status, first device-side code) of a workspace; clears the code."""
     code = ctypes.c_int32(0)
@@ -272,6 +278,8 @@ class Engine:
     # -- passes --------------------------------------------------------------
     def plan(self, stream=None) -> Plan:
         A, B, n = self.A, self.B, self.B.ncols
+        # a product starts from scratch: its batches share one slabbed copy of A
+        ws_invalidate(self.ws_num, stream)
         symbolic(A, B, 0, n, self.L, self.flops, self.nnz, self.ws_sym, stream)
         nnz_host = self.nnz.cpu().numpy()
         bounds, tot = plan_batches(nnz_host.reshape(-1), n, self.L, self.vbytes, self.input_bytes, self.budget_bytes,

@@ -64,18 +64,16 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
       if (A->nrows < 0 || A->nrows > INT32_MAX) return SPGEMM_E_OVERFLOW;
       L->ncol = ncol;
       L->m = A->nrows;
-      L->bins = off;
-      off = align_up(off + sizeof(int32_t) * kNumBins * (size_t)ncol);
-      if (op == SPGEMM_OP_MERGE) {
-        L->parts = off;
-        off = align_up(off + kPartDescBytes * (size_t)n_layers);
-      }
       const bool numeric = op == SPGEMM_OP_NUMERIC || op == SPGEMM_OP_BATCHED_FORWARD;
       const int64_t P = num_slabs(A->nrows);
       // columns of A one call reads: one layer of ceil(k / n_layers) columns
       const int64_t kcols = (A->ncols + n_layers - 1) / n_layers;
-      if (numeric && A->nrows > kNumCap[kNumBins - 2] && P <= kMaxSlabs &&
-          sizeof(int32_t) * (uint64_t)(P + 1) * (uint64_t)kcols <= kMaxSlabOffBytes) {
+      const bool slabs = numeric && A->nrows > kNumCap[kNumBins - 2] && P <= kMaxSlabs &&
+                         sizeof(int32_t) * (uint64_t)(P + 1) * (uint64_t)kcols <= kMaxSlabOffBytes;
+      if (slabs) {
+        // the slabbed copy of A depends only on A and the layer: it comes
+        // first, so that calls on other column ranges find it at the same
+        // offsets (and may reuse it)
         L->P = P;
         L->slab_off = off;
         off = align_up(off + sizeof(int32_t) * (size_t)(L->P + 1) * (size_t)kcols);
@@ -85,6 +83,14 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
         off = align_up(off + sizeof(int32_t) * (size_t)A->nnz);
         L->slab_v = off;
         off = align_up(off + sizeof(double) * (size_t)A->nnz);
+      }
+      L->bins = off;
+      off = align_up(off + sizeof(int32_t) * kNumBins * (size_t)ncol);
+      if (op == SPGEMM_OP_MERGE) {
+        L->parts = off;
+        off = align_up(off + kPartDescBytes * (size_t)n_layers);
+      }
+      if (slabs) {
         L->hv_cur = off;
         off = align_up(off + sizeof(int32_t) * (size_t)ncol);
         L->hv_items = off;

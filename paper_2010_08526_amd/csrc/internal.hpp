@@ -84,6 +84,8 @@ struct WsHeader {
   int32_t cursor[kNumBins];  // work-queue positions of the persistent kernels
   int32_t nwide;        // wide heavy columns listed for the current chunk
   int32_t wide_cursor;  // work-queue position over their items
+  uint64_t left_tag;    // fingerprint (| 1) of the source of the slabbed copy of A in the workspace; 0 = none
+  uint64_t left_new;    // fingerprint of the current call's left operand (summed by k_left_sum)
 };
 constexpr size_t kHeaderBytes = 4096;
 

@@ -403,9 +403,11 @@ __device__ __forceinline__ void traverse_merge(const PartDesc *P, int nparts, in
 // ============================================================================
 // Small kernels: header init, fills.
 // ============================================================================
-__global__ void k_init_header(WsHeader *h, int keep_clean, int keep_status = 0) {
+__global__ void k_init_header(WsHeader *h, int keep_clean, int keep_status = 0, int keep_left = 0) {
   if (threadIdx.x == 0) {
     if (!keep_status) h->status = 0;
+    if (!keep_left) h->left_tag = 0;  // every other operation may overwrite the slabbed copy
+    h->left_new = 0;
     for (int b = 0; b < kNumBins; b++) h->bin_count[b] = 0;
     for (int b = 0; b < kNumBins; b++) h->cursor[b] = 0;
     h->items = 0;
@@ -890,15 +892,63 @@ __global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *l
 // are bucketed by row slab (a counting sort on row >> kSlabShift inside each
 // column; one wavefront per column).
 // ----------------------------------------------------------------------------
+// The slabbed copy of A (k_slab_split, k_seg_pack) depends only on A's
+// columns [klo, khi) and the slab count, so consecutive numeric calls on one
+// workspace (the batches of one product) can share it.  k_left_sum forms a
+// fingerprint of those columns on the device: every column pointer and
+// every entry (row and value bits) is mixed with its position by the
+// MurmurHash3 64-bit finalizer and summed, with A's pointers, sizes, the
+// layer and the slab count in the seed.  The copy is rebuilt unless the
+// workspace holds one made from a source with the same fingerprint; any
+// other operation on the workspace clears the tag.
+__device__ __host__ __forceinline__ uint64_t fmix64(uint64_t x) {
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdull;
+  x ^= x >> 33;
+  x *= 0xc4ceb9fe1a85ec53ull;
+  x ^= x >> 33;
+  return x;
+}
+__device__ __forceinline__ uint64_t value_bits(float v) { return (uint64_t)__float_as_uint(v); }
+__device__ __forceinline__ uint64_t value_bits(double v) { return (uint64_t)__double_as_longlong(v); }
+
+template <class VT>
+__global__ __launch_bounds__(256) void k_left_sum(const int64_t *Acp, const int32_t *Ari, const VT *Av, int64_t klo,
+                                                  int64_t khi, uint64_t seed, WsHeader *h,
+                                                  const int32_t *heavy_count) {
+  if (*heavy_count == 0) return;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nth = (int64_t)gridDim.x * blockDim.x;
+  uint64_t s = 0;
+  for (int64_t k = klo + tid; k <= khi; k += nth) s += fmix64(seed ^ fmix64((uint64_t)k) ^ (uint64_t)Acp[k]);
+  const int64_t e0 = Acp[klo], e1 = Acp[khi];
+  for (int64_t p = e0 + tid; p < e1; p += nth)
+    s += fmix64(seed + fmix64((uint64_t)p) + (((uint64_t)(uint32_t)Ari[p] << 32) ^ value_bits(Av[p])));
+  for (int o = 32; o > 0; o >>= 1) s += (uint64_t)__shfl_xor((long long)s, o, kWave);
+  if (lane() == 0) atomicAdd((unsigned long long *)&h->left_new, (unsigned long long)s);
+}
+
+__device__ __forceinline__ bool left_is_current(const WsHeader *h) { return h->left_tag == (h->left_new | 1ull); }
+
+// After the copy is (re)built or found current: tag it, unless a check
+// failed (then the copy is not trusted again).  No heavy columns: nothing
+// was touched, the tag stays.
+__global__ void k_left_forget(WsHeader *h) {
+  if (threadIdx.x == 0) h->left_tag = 0;
+}
+
+__global__ void k_left_set(WsHeader *h, const int32_t *heavy_count) {
+  if (threadIdx.x == 0 && *heavy_count != 0) h->left_tag = h->status == 0 ? (h->left_new | 1ull) : 0ull;
+}
+
 template <class VT>
 __global__ __launch_bounds__(256) void k_slab_split(const int64_t *Acp, const int32_t *Ari, const VT *Av,
                                                     int64_t klo, int64_t khi, int64_t m, int P, int32_t *soff,
                                                     int32_t *s_ri, VT *s_v, const int32_t *heavy_count,
-                                                    int32_t *status) {
+                                                    int32_t *status, const WsHeader *hdr) {
   __shared__ int s_hist[4][kMaxSlabs + 1];
   const int w = threadIdx.x / kWave, l = lane();
   const int64_t k = klo + (int64_t)blockIdx.x * 4 + w;
-  if (k >= khi || *heavy_count == 0) return;
+  if (k >= khi || *heavy_count == 0 || left_is_current(hdr)) return;
   int *h = s_hist[w];
   for (int t = l; t <= P; t += kWave) h[t] = 0;
   wave_sync();
@@ -940,10 +990,11 @@ __global__ __launch_bounds__(256) void k_slab_split(const int64_t *Acp, const in
 // one 8-byte load gives a segment.  Built from the slab offsets through
 // 64 x 64 tiles in LDS (both sides coalesced).
 __global__ __launch_bounds__(256) void k_seg_pack(const int32_t *off, const int64_t *Acp, int64_t klo, int64_t kc,
-                                                  int P, uint64_t *pack, const int32_t *heavy_count) {
+                                                  int P, uint64_t *pack, const int32_t *heavy_count,
+                                                  const WsHeader *hdr) {
   __shared__ int32_t tile[64][66];
   __shared__ int64_t s_a0[64];
-  if (*heavy_count == 0) return;
+  if (*heavy_count == 0 || left_is_current(hdr)) return;
   const int64_t k0 = (int64_t)blockIdx.x * 64;
   const int s0 = (int)blockIdx.y * 64;
   const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
@@ -2468,7 +2519,7 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
                          char *ws, hipStream_t st, bool sync, bool keep_status = false) {
   WsHeader *hdr = (WsHeader *)ws;
   int32_t *bins = (int32_t *)(ws + L.bins);
-  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, 1, keep_status ? 1 : 0);
+  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, 1, keep_status ? 1 : 0, 1);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_bin<false>, dim3(grid_of(ncol, 4 * kBinColsPerWave)), dim3(256), 0, st, A->colptr, B->colptr,
                      B->rowidx, c0, ncol, klo, khi, (int64_t)A->ncols, A->nrows, c_colptr, (int64_t *)nullptr,
@@ -2492,11 +2543,23 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
     const int32_t *hc = &hdr->bin_count[kNumBins - 1];
     if (khi > klo) {
       ProfScope prof("slab_split", st);
+      uint64_t seed = 0x5eed;
+      for (uint64_t x : {(uint64_t)(uintptr_t)A->colptr, (uint64_t)(uintptr_t)A->rowidx, (uint64_t)(uintptr_t)A->values,
+                         (uint64_t)A->nnz, (uint64_t)A->nrows, (uint64_t)klo, (uint64_t)khi, (uint64_t)L.P,
+                         (uint64_t)sizeof(VT), (uint64_t)L.slab_off, (uint64_t)L.slab_pack})
+        seed = fmix64(seed ^ x);
+      hipLaunchKernelGGL(k_left_sum<VT>, dim3((unsigned)(4 * device_cus())), dim3(256), 0, st, A->colptr, A->rowidx,
+                         (const VT *)A->values, klo, khi, seed, hdr, hc);
+      LAUNCHCHK();
       hipLaunchKernelGGL(k_slab_split<VT>, dim3(grid_of(khi - klo, 4)), dim3(256), 0, st, A->colptr, A->rowidx,
-                         (const VT *)A->values, klo, khi, A->nrows, (int)L.P, soff, s_ri, s_v, hc, &hdr->status);
+                         (const VT *)A->values, klo, khi, A->nrows, (int)L.P, soff, s_ri, s_v, hc, &hdr->status,
+                         (const WsHeader *)hdr);
       LAUNCHCHK();
       hipLaunchKernelGGL(k_seg_pack, dim3(grid_of(khi - klo, 64), (unsigned)((L.P + 63) / 64)), dim3(256), 0, st,
-                         (const int32_t *)soff, A->colptr, klo, khi - klo, (int)L.P, (uint64_t *)(ws + L.slab_pack), hc);
+                         (const int32_t *)soff, A->colptr, klo, khi - klo, (int)L.P, (uint64_t *)(ws + L.slab_pack), hc,
+                         (const WsHeader *)hdr);
+      LAUNCHCHK();
+      hipLaunchKernelGGL(k_left_set, dim3(1), dim3(64), 0, st, hdr, hc);
       LAUNCHCHK();
     }
     HvArgs<VT> ha;
@@ -2712,7 +2775,7 @@ int spgemm_numeric(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t
   const int64_t klo = std::min<int64_t>(kdim, (int64_t)layer * width), khi = std::min<int64_t>(kdim, klo + width);
   hipStream_t s = (hipStream_t)stream;
   if (n_layers > 1) {  // the layer's share of B first, then the passes over it
-    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)ws, 1, 0);
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)ws, 1, 0, 1);
     LAUNCHCHK();
     spgemm_csc Bl;
     if (A->dtype == SPGEMM_F32) {
@@ -2866,6 +2929,13 @@ int spgemm_batch_pack(const spgemm_csc *instances, int32_t count, int64_t *colpt
 int spgemm_debug_min_bin(int32_t bin) {
   if (bin < 0 || bin >= kNumBins) return SPGEMM_E_INVAL;
   g_min_bin = bin;
+  return SPGEMM_OK;
+}
+
+int spgemm_ws_invalidate(void *ws, void *stream) {
+  if (!ws) return SPGEMM_E_WORKSPACE;
+  hipLaunchKernelGGL(k_left_forget, dim3(1), dim3(64), 0, (hipStream_t)stream, (WsHeader *)ws);
+  LAUNCHCHK();
   return SPGEMM_OK;
 }
 
