@@ -151,6 +151,7 @@ def test_numeric_and_merge_validation_before_launch():
     assert lib.spgemm_colptr(0x1, 10, None, 0x10000, 1 << 20, None) == S.E_INVAL
     assert lib.spgemm_colptr(0x1, 10, 0x1, 0x10000, 8, None) == S.E_WORKSPACE
     assert lib.spgemm_ws_status(None, None) == S.E_WORKSPACE
+    assert lib.spgemm_ws_invalidate(None, None) == S.E_WORKSPACE
 
 
 def test_workspace_size_depends_on_shapes():
