@@ -54,8 +54,8 @@ def _parse():
     p.add_argument("--protein-n", type=int, default=2_000_000)
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--no-extras", action="store_true", help="skip the fwd_bwd, batched and layered sections")
-    p.add_argument("--extras", default="fwd_bwd,batched,layered", help="comma-separated extra sections to run")
+    p.add_argument("--no-extras", action="store_true", help="skip the fwd_bwd, batched, layered and bsweep sections")
+    p.add_argument("--extras", default="fwd_bwd,batched,layered,bsweep", help="comma-separated extra sections to run")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain device copy of known size (to scale HBM byte counters) and exit")
     return p.parse_args()
@@ -388,6 +388,61 @@ def batched(args, torch, np, S, synth):
     return out
 
 
+def bsweep(args, torch, np, S, synth):
+    """The headline product at several batch counts b (a one-GPU analog of
+    the paper's runtime-versus-batches study): for each b the smallest HBM
+    budget that gives b batches, then one warm-up and one timed product."""
+    dev = torch.device("cuda:0")
+    A = synth.rmat(args.scale, 16, synth.WORKLOADS["rmat20"].seed, dtype=torch.float32, device=dev)
+    eng = S.Engine(A, A, 1, budget_bytes=1 << 62)
+    plan = eng.plan()
+    flops = plan.total_flops
+    r = 8
+    total_out = int((r * plan.nnz_host[0] + 8).sum())
+    rows = []
+    # fewest batches last: the engine's output buffers only grow
+    for b in (64, 16, 8, 4, 2, 1):
+        lo, hi, avail = total_out // (b + 1) + 1, total_out // max(1, b - 1) + 1 if b > 1 else total_out, None
+        while lo <= hi:
+            mid = (lo + hi) // 2
+            try:
+                bb, _ = S.plan_batches(plan.nnz_host.reshape(-1), A.ncols, 1, 4, 0, mid, 0)
+            except S.SpgemmError:
+                lo = mid + 1
+                continue
+            if len(bb) - 1 > b:
+                lo = mid + 1
+            else:
+                avail, hi = mid, mid - 1
+        if avail is None:
+            rows.append({"b_target": b, "skipped": "no budget gives this many batches"})
+            continue
+        eng.release_buffers()  # the next plan's buffers replace them, not join them
+        torch.cuda.empty_cache()
+        free, _ = torch.cuda.mem_get_info()
+        if avail > 0.8 * free:
+            rows.append({"b_target": b, "skipped": f"output share {avail / 1e9:.1f} GB exceeds free HBM"})
+            continue
+        eng.budget_bytes = eng.input_bytes + eng.reserve_bytes + avail
+        times = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pl = eng.plan()
+            for i in range(pl.nbatches):
+                eng.run_batch(pl, i)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        eng.check()
+        t = times[-1]
+        rows.append({"b": pl.nbatches, "budget_bytes": eng.budget_bytes, "ms": round(t * 1e3, 2),
+                     "GFLOPs": round(2 * flops / t / 1e9, 2)})
+        log(f"bsweep: b={pl.nbatches} {t * 1e3:.1f} ms ({2 * flops / t / 1e9:.1f} GFLOP/s)")
+    del eng
+    return {"workload": "rmat20 headline product at several batch counts (one warm-up, one timed product each)",
+            "flops": flops, "runs": rows}
+
+
 def cpu_baseline(A, seconds: float):
     """The oracle (plain C, float64 dense accumulator, OpenMP over columns) on
     a seeded random sample of output columns of the headline product."""
@@ -502,7 +557,7 @@ def main():
     res, A = headline(args, torch, np, S, synth)
     torch.cuda.empty_cache()
     if not args.no_extras:
-        for name, fn in (("fwd_bwd", fwd_bwd), ("batched", batched), ("layered", layered)):
+        for name, fn in (("fwd_bwd", fwd_bwd), ("batched", batched), ("layered", layered), ("bsweep", bsweep)):
             if name in args.extras.split(","):
                 res[name] = fn(args, torch, np, S, synth)
                 torch.cuda.empty_cache()

@@ -308,6 +308,10 @@ class Engine:
             self._bufs = bufs
         return self._bufs
 
+    def release_buffers(self):
+        """Drops the output buffers (they are allocated again, at the size the next plan needs)."""
+        self._bufs = None
+
     def run_batch(self, plan: Plan, i: int, stream=None, marks=None) -> CSC:
         """Forms batch i; the returned CSC views buffers reused by the next call.
         With ``marks`` (a list), (phase, start_event, end_event) tuples are
