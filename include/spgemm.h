@@ -306,10 +306,14 @@ int spgemm_ws_status_code(void *ws, void *stream, int32_t *code_host);
  * grouped by row slab that the heavy-column path builds (the copy is
  * rebuilt unless a fingerprint of A's columns of the layer, formed on the
  * device at every call from the column pointers, rows and value bits, equals
- * the one it was built from; any other operation on the workspace clears
- * it).  spgemm_ws_invalidate clears it explicitly, so that the next numeric
- * call rebuilds it (for instance at the start of each product, to time a
- * product on its own).  Asynchronous: one small kernel on `stream`, no
+ * the one it was built from; every other operation of this library that
+ * initialises the workspace header clears it, and spgemm_batch_pack
+ * overwrites the header with its descriptor table, which leaves a stored
+ * fingerprint no more likely to match than a fingerprint collision).
+ * spgemm_ws_invalidate clears it explicitly, so that the next numeric call
+ * rebuilds it: call it at the start of each product to time a product on
+ * its own, and always after writing into a numeric workspace by any means
+ * other than this library's calls.  Asynchronous: one small kernel on `stream`, no
  * allocation and no memset, so it can be captured in a graph. */
 int spgemm_ws_invalidate(void *ws, void *stream);
 
