@@ -17,10 +17,14 @@ numpy arrays.  Every function cites the passage it implements:
                      pattern of C (product rule; not in the paper).
 * ``plan_batches``-- the batch-count bound of Eq. (2) and Alg. 3 with one
                      process, written out in Python integers.
+* ``prune_topk``  -- the per-column pruning an application applies to each
+                     output batch (threshold, then top-k per column; Sec. I,
+                     Sec. IV-B, Sec. V-C), in numpy.
 
 Parity status: every function here is pinned by tests in
 ``tests/test_oracle.py`` against numpy/scipy, closed forms, invariants or
-hand-derived fixtures. ``plan_batches`` is pinned by a brute-force search over
+hand-derived fixtures (``prune_topk`` by a hand-worked fixture with ties and
+signed zeros and by a sort-free characterisation on tie-heavy inputs). ``plan_batches`` is pinned by a brute-force search over
 all contiguous splits (fewest batches, then smallest largest batch); which of
 several equally balanced splits it returns is a convention the paper leaves
 open.
@@ -240,3 +244,33 @@ def plan_batches(col_bytes, avail_bytes: int) -> list[int]:
         else:
             lo = mid + 1
     return greedy(lo)
+
+
+def prune_topk(M, threshold: float, k: int) -> Mat:
+    """Column-wise pruning of one output batch, the consumer the paper puts
+    right after each batch (Sec. I and Sec. IV-B: the application prunes or
+    discards a batch before the next; Markov clustering keeps the top-k
+    entries of every column; Sec. V-C: HipMCL prunes column by column).
+
+    Per column: the candidates are the entries whose value is >= threshold
+    (compared in float64; NaN is never a candidate).  With k < 0 every
+    candidate is kept; otherwise the k largest candidates by value, ties
+    between equal values going to the smaller row index (-0.0 equals 0.0).
+    Kept entries stay in their input order.  Values come back as float64
+    (exact copies of the inputs)."""
+    M = as_mat(M)
+    colptr = np.zeros(M.ncols + 1, np.int64)
+    rows, vals = [], []
+    for j in range(M.ncols):
+        b, e = int(M.colptr[j]), int(M.colptr[j + 1])
+        r, v = M.rowidx[b:e], M.values[b:e]
+        cand = np.nonzero(v >= threshold)[0]
+        if k >= 0 and cand.size > k:
+            vc = np.where(v[cand] == 0.0, 0.0, v[cand])  # one zero
+            order = np.lexsort((r[cand], -vc))  # value descending, then row ascending
+            cand = np.sort(cand[order[:k]])
+        rows.append(r[cand])
+        vals.append(v[cand])
+        colptr[j + 1] = colptr[j] + cand.size
+    cat = (lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.zeros(0, dt))
+    return Mat(M.nrows, M.ncols, colptr, cat(rows, np.int32), cat(vals, np.float64))

@@ -364,3 +364,99 @@ def test_planner_errors_and_monotone():
         if prev is not None:
             assert b <= prev
         prev = b
+
+
+# ------------------------------------------------- per-column pruning of a batch
+def _prune_fixture():
+    with open(os.path.join(GOLDEN, "prune_topk_hand.json")) as f:
+        g = json.load(f)
+    cols = g["columns"]
+    colptr = np.cumsum([0] + [len(c) for c in cols]).astype(np.int64)
+    rows = np.array([e[0] for c in cols for e in c], np.int32)
+    vals = np.array([np.nan if e[1] is None else e[1] for c in cols for e in c], np.float64)
+    return g, Mat(g["nrows"], len(cols), colptr, rows, vals)
+
+
+def test_prune_hand_worked():
+    g, M = _prune_fixture()
+    for case in g["cases"]:
+        P = oracle.prune_topk(M, case["threshold"], case["k"])
+        for j, exp in enumerate(case["expect"]):
+            s, e = P.colptr[j], P.colptr[j + 1]
+            got = list(zip(P.rowidx[s:e].tolist(), P.values[s:e].tolist()))
+            assert [(r, v) for r, v in got] == [(r, v) for r, v in exp], (case, j)
+            # the sign of a kept zero is the input's
+            assert [np.signbit(v) for _, v in got] == [np.signbit(v) for _, v in exp], (case, j)
+
+
+def _tie_heavy(seed, m=9, n=12, dens=0.6):
+    """Random CSC with rows shuffled inside columns and values drawn from a
+    small set (many ties, both signed zeros, NaN)."""
+    rng = np.random.default_rng(seed)
+    pool = np.array([-2.0, -1.0, -0.0, 0.0, 0.5, 1.0, 1.0, 2.0, np.nan])
+    colptr, rows, vals = [0], [], []
+    for _ in range(n):
+        r = rng.permutation(m)[: rng.binomial(m, dens)]
+        rows += r.tolist()
+        vals += rng.choice(pool, r.size).tolist()
+        colptr.append(len(rows))
+    return Mat(m, n, np.array(colptr, np.int64), np.array(rows, np.int32), np.array(vals, np.float64))
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("threshold,k", [(-5.0, 1), (-5.0, 3), (0.0, 2), (0.5, 0), (-0.5, 4), (-5.0, -1), (1.0, -1)])
+def test_prune_brute_force(seed, threshold, k):
+    """Characterisation independent of any sort: the kept set of a column is
+    the unique subset of the candidates of size min(k, #candidates) in which
+    every kept entry outranks every dropped candidate (greater value, or an
+    equal value and a smaller row); kept entries keep their input order and
+    values bit for bit."""
+    M = _tie_heavy(seed)
+    P = oracle.prune_topk(M, threshold, k)
+
+    def outranks(a, b):  # (row, value) pairs
+        return a[1] > b[1] or (a[1] == b[1] and a[0] < b[0])
+
+    for j in range(M.ncols):
+        s, e = M.colptr[j], M.colptr[j + 1]
+        col = [(int(r), float(v), p) for p, (r, v) in enumerate(zip(M.rowidx[s:e], M.values[s:e]))]
+        cand = [c for c in col if c[1] >= threshold]
+        want = len(cand) if k < 0 else min(k, len(cand))
+        ps, pe = P.colptr[j], P.colptr[j + 1]
+        kept_rows = P.rowidx[ps:pe].tolist()
+        assert len(kept_rows) == want
+        kept = [c for c in cand if c[0] in kept_rows]
+        dropped = [c for c in cand if c[0] not in kept_rows]
+        assert len(kept) == want
+        assert all(outranks(a, b) for a in kept for b in dropped)
+        assert kept_rows == [c[0] for c in kept]  # input order
+        assert np.array_equal(P.values[ps:pe].view(np.uint64), np.array([c[1] for c in kept]).view(np.uint64))
+
+
+def test_prune_special_cases():
+    M = _tie_heavy(11, m=30, n=20)
+    finite = ~np.isnan(M.values)
+    # no threshold and no limit: the matrix minus its NaN entries
+    P = oracle.prune_topk(M, -np.inf, -1)
+    assert P.nnz == int(finite.sum()) and np.array_equal(P.rowidx, M.rowidx[finite])
+    # a limit no column reaches is the threshold alone, a plain mask
+    for t in (-1.0, 0.0, 1.0):
+        P = oracle.prune_topk(M, t, 10 ** 6)
+        keep = M.values >= t
+        assert np.array_equal(P.rowidx, M.rowidx[keep]) and np.array_equal(P.values, M.values[keep])
+        assert np.diff(P.colptr).tolist() == [int(keep[M.colptr[j]:M.colptr[j + 1]].sum()) for j in range(M.ncols)]
+    # nothing kept
+    assert oracle.prune_topk(M, -np.inf, 0).nnz == 0 and oracle.prune_topk(M, np.inf, -1).nnz == 0
+    # k = 1 on distinct values is the column maximum (np.argmax)
+    rng = np.random.default_rng(3)
+    R = random_sparse(40, 25, 0.3, rng)
+    P = oracle.prune_topk(R, -np.inf, 1)
+    for j in range(R.ncols):
+        s, e = R.colptr[j], R.colptr[j + 1]
+        if e > s:
+            assert P.colptr[j + 1] - P.colptr[j] == 1
+            assert P.values[P.colptr[j]] == R.values[s:e].max() and P.rowidx[P.colptr[j]] == R.rowidx[s + np.argmax(R.values[s:e])]
+    # an empty matrix and a matrix without columns
+    E = Mat(5, 3, np.zeros(4, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    assert oracle.prune_topk(E, 0.0, 2).colptr.tolist() == [0, 0, 0, 0]
+    assert oracle.prune_topk(Mat(5, 0, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0)), 0.0, 2).nnz == 0
