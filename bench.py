@@ -54,8 +54,8 @@ def _parse():
     p.add_argument("--protein-n", type=int, default=2_000_000)
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--no-extras", action="store_true", help="skip the fwd_bwd, batched, layered and bsweep sections")
-    p.add_argument("--extras", default="fwd_bwd,batched,layered,bsweep", help="comma-separated extra sections to run")
+    p.add_argument("--no-extras", action="store_true", help="skip the fwd_bwd, batched, layered, bsweep and prune sections")
+    p.add_argument("--extras", default="fwd_bwd,batched,layered,bsweep,prune", help="comma-separated extra sections to run")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain device copy of known size (to scale HBM byte counters) and exit")
     return p.parse_args()
@@ -538,6 +538,53 @@ def measured_traffic(kernel, workload):
     return int(t["hbm_bytes_per_launch"])
 
 
+def prune(args, torch, np, S, synth):
+    """The consumer the paper puts after each batch (an application prunes
+    every batch of C before the next; Markov clustering keeps the largest
+    entries of each column): the headline product at its default budget,
+    every batch pruned to its 100 largest entries per column.  Kernel times
+    come from the library's per-launch HIP events; bytes are the compulsory
+    ones (rows and values read once, column pointers, per-column selection
+    state written and read once, kept entries written)."""
+    dev = torch.device("cuda:0")
+    A = synth.rmat(args.scale, 16, synth.WORKLOADS["rmat20"].seed, dtype=torch.float32, device=dev)
+    eng = S.Engine(A, A, 1, budget_bytes=1 << 62)
+    plan = eng.plan()
+    total_out = int((8 * plan.nnz_host[0] + 8).sum())
+    eng.budget_bytes = eng.input_bytes + eng.reserve_bytes + total_out // args.batches + int(plan.nnz_host[0].max()) * 8 + 8
+    k = 100
+    stats = {"entries": 0, "kept": 0, "cols": 0}
+    ws = {}
+
+    def consume(c0, c1, Cb):
+        if "ws" not in ws or ws["ws"].numel() < S.workspace_size(S.OP_PRUNE, Cb):
+            ws["ws"] = S.alloc_workspace(S.workspace_size(S.OP_PRUNE, Cb), dev)
+        G = S.prune_topk(Cb, 0.0, k, ws=ws["ws"])
+        stats["entries"] += Cb.nnz
+        stats["kept"] += G.nnz
+        stats["cols"] += Cb.ncols
+
+    eng.run(consume=consume)  # warm-up
+    stats = {"entries": 0, "kept": 0, "cols": 0}
+    S.profile_enable(True)
+    pl = eng.run(consume=consume)
+    prof = S.profile_report()
+    S.profile_enable(False)
+    ms = sum(prof.get(n, (0.0, 0))[0] for n in ("prune_select", "prune_fill"))
+    nbytes = 8 * stats["entries"] + 2 * 8 * (stats["cols"] + pl.nbatches) + 2 * 20 * stats["cols"] + 8 * stats["kept"]
+    gbs = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None
+    log(f"prune: {pl.nbatches} batches, {stats['entries']:.4e} entries -> {stats['kept']:.4e} kept (k={k}), "
+        f"select {prof.get('prune_select', (0, 0))[0]:.1f} ms + fill {prof.get('prune_fill', (0, 0))[0]:.1f} ms, "
+        f"{gbs:.0f} GB/s compulsory")
+    del eng
+    return {"workload": f"rmat20 headline product, each of its batches pruned to the {k} largest entries per column",
+            "batches": pl.nbatches, "entries": stats["entries"], "kept": stats["kept"], "k": k,
+            "select_ms": round(prof.get("prune_select", (0.0, 0))[0], 3),
+            "fill_ms": round(prof.get("prune_fill", (0.0, 0))[0], 3),
+            "compulsory_bytes": nbytes, "achieved_GBps": None if gbs is None else round(gbs, 1),
+            "frac_of_hbm_peak": None if gbs is None else round(gbs / 8000.0, 4)}
+
+
 def main():
     args = _parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -557,7 +604,8 @@ def main():
     res, A = headline(args, torch, np, S, synth)
     torch.cuda.empty_cache()
     if not args.no_extras:
-        for name, fn in (("fwd_bwd", fwd_bwd), ("batched", batched), ("layered", layered), ("bsweep", bsweep)):
+        for name, fn in (("fwd_bwd", fwd_bwd), ("batched", batched), ("layered", layered), ("bsweep", bsweep),
+                         ("prune", prune)):
             if name in args.extras.split(","):
                 res[name] = fn(args, torch, np, S, synth)
                 torch.cuda.empty_cache()

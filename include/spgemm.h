@@ -83,7 +83,8 @@ typedef enum {
   SPGEMM_OP_MASKED_XTY = 4,
   SPGEMM_OP_TRANSPOSE = 5,
   SPGEMM_OP_BATCHED_FORWARD = 6,
-  SPGEMM_OP_BATCHED_BACKWARD = 7
+  SPGEMM_OP_BATCHED_BACKWARD = 7,
+  SPGEMM_OP_PRUNE = 8
 } spgemm_op;
 
 /* Workspace bytes needed by one call of `op`.  Host only; never syncs.
@@ -264,6 +265,30 @@ int spgemm_batched_masked_xty(const spgemm_csc *X, const spgemm_csc *Y, const sp
 int spgemm_batched_backward(const spgemm_csc *A, const spgemm_csc *B, const spgemm_csc *C, const void *dC_values,
                             void *dA_out, void *dB_out, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- Consumer of an output batch (Sec. I and Sec. IV-B: the application
+ * prunes each batch of C before the next one; Markov clustering keeps the
+ * k largest entries of every column, Sec. V-C).
+ *
+ * Per-column pruning of C (float32 or float64; rows unique inside each
+ * column, in any order).  Candidates are entries whose value, converted to
+ * float64, is >= threshold (NaN is never one; a NaN threshold keeps
+ * nothing).  k < 0 keeps every candidate; otherwise the k largest
+ * candidates of each column are kept, equal values going to the smaller row
+ * (-0.0 equals 0.0).  Kept entries keep their input order and are written
+ * to out_colptr[C.ncols + 1] (device, starts at 0), out_rowidx and
+ * out_values (device, C's dtype, exact copies).  out_cap, the capacity of
+ * the last two in entries, must be at least min(nnz(C), k * C.ncols)
+ * (nnz(C) for k < 0): the output never holds more, so no host
+ * synchronization is needed and the call can be captured in a graph.  The
+ * arrays of C are only read; the outputs must not overlap them.
+ * Workspace: spgemm_workspace_size(SPGEMM_OP_PRUNE, C, NULL, 0, 0, 1, ...).
+ * Device-side checks (spgemm_ws_status_code): 5 column pointers outside
+ * the arrays (that column is treated as empty), 10 a row twice in one
+ * column (that column is cut at k).  Errors: SPGEMM_E_INVAL for a NULL
+ * output or a capacity below the bound, SPGEMM_E_DTYPE, SPGEMM_E_WORKSPACE. */
+int spgemm_prune_topk(const spgemm_csc *C, double threshold, int64_t k, int64_t *out_colptr, int32_t *out_rowidx,
+                      void *out_values, int64_t out_cap, void *ws, size_t ws_bytes, void *stream);
+
 /* Bin thresholds (process-wide; used by calls launched afterwards): which = 0
  * for the symbolic pass, 1 for numeric, merge and masked products.
  * caps_host[5] are the largest bounds on distinct rows that go to bins 0..4
@@ -298,7 +323,8 @@ int spgemm_ws_status(void *ws, void *stream);
  * the symbolic pass, 5 column pointers inconsistent with the arrays they
  * index, 7 a column above the largest LDS table in a call without a host
  * synchronization, 8 an output larger than the capacity given, 9 a
- * malformed internal work item. */
+ * malformed internal work item, 10 a row twice in one column of a matrix
+ * being pruned. */
 int spgemm_ws_status_code(void *ws, void *stream, int32_t *code_host);
 
 /* What a workspace keeps between calls: consecutive spgemm_numeric calls on

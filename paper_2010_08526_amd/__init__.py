@@ -25,7 +25,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 # ---------------------------------------------------------------- constants
 OK, E_INVAL, E_SHAPE, E_DTYPE, E_BUDGET, E_WORKSPACE, E_HIP, E_OVERFLOW, E_DEVICE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 F32, F64 = 0, 1
-OP_SYMBOLIC, OP_NUMERIC, OP_MERGE, OP_COLPTR, OP_MASKED_XTY, OP_TRANSPOSE, OP_BATCHED_FORWARD, OP_BATCHED_BACKWARD = range(8)
+(OP_SYMBOLIC, OP_NUMERIC, OP_MERGE, OP_COLPTR, OP_MASKED_XTY, OP_TRANSPOSE, OP_BATCHED_FORWARD, OP_BATCHED_BACKWARD,
+ OP_PRUNE) = range(9)
 MAX_PARTS = 4096
 
 _DTYPE = {torch.float32: F32, torch.float64: F64}
@@ -397,6 +398,35 @@ def spgemm(A, B, *, layers: int = 1, budget_bytes: int | None = None, consume=No
     eng = Engine(A, B, layers, budget_bytes)
     res = eng.run(consume, stream)
     return res if consume is not None else res[0]
+
+
+# ------------------------------------------------------ consumer of a batch
+_lib.spgemm_prune_topk.argtypes = [_P, ctypes.c_double, _i64, _vp, _vp, _vp, _i64, _vp, _sz, _vp]
+
+
+def prune_bound(nnz: int, ncols: int, k: int) -> int:
+    """Most entries a pruned matrix can hold: min(nnz, k * ncols), nnz for k < 0."""
+    return nnz if k < 0 else min(nnz, k * ncols)
+
+
+def prune_topk(C, threshold: float, k: int, ws: torch.Tensor | None = None, stream=None) -> CSC:
+    """Per-column pruning of an output batch (the consumer an application
+    runs on each batch): entries >= threshold, then at most the k largest of
+    each column (k < 0: no limit), equal values going to the smaller row;
+    kept entries stay in input order.  Reads the entry count back to the
+    host and checks the workspace status."""
+    dev = C.rowidx.device
+    if ws is None:
+        ws = alloc_workspace(workspace_size(OP_PRUNE, C), dev)
+    cap = prune_bound(C.nnz, C.ncols, int(k))
+    cp = torch.empty(C.ncols + 1, dtype=torch.int64, device=dev)
+    ri = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
+    v = torch.empty(max(1, cap), dtype=C.values.dtype, device=dev)
+    _check(_lib.spgemm_prune_topk(ctypes.byref(desc(C)), float(threshold), int(k), _ptr(cp), _ptr(ri), _ptr(v), cap,
+                                  _ptr(ws), ws.numel(), _stream(stream)), "spgemm_prune_topk")
+    check_ws(ws, "device-side check (prune)", stream)
+    n = int(cp[-1])
+    return CSC(C.nrows, C.ncols, cp, ri[:n], v[:n])
 
 
 # ------------------------------------------------------------ gradient support

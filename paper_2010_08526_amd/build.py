@@ -42,7 +42,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     hipcc = _hipcc()
     objs = []
-    for src in ("host.cpp", "kernels.hip", "backward.hip", "profile.cpp"):
+    for src in ("host.cpp", "kernels.hip", "backward.hip", "prune.hip", "profile.cpp"):
         obj = os.path.join(LIBDIR, src.replace(".", "_") + ".o")
         cmd = [hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if src == "host.cpp":

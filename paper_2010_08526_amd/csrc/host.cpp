@@ -190,6 +190,21 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
       off = align_up(off + sizeof(double) * (size_t)A->nnz);
       break;
     }
+    case SPGEMM_OP_PRUNE: {  // A = the matrix pruned
+      if (!A) return SPGEMM_E_INVAL;
+      if (A->ncols < 0) return SPGEMM_E_INVAL;
+      const size_t n = (size_t)A->ncols;
+      L->ncol = A->ncols;
+      L->pr_cnt = off;
+      off = align_up(off + sizeof(int64_t) * n);
+      L->pr_cutv = off;
+      off = align_up(off + sizeof(uint64_t) * n);
+      L->pr_cutr = off;
+      off = align_up(off + sizeof(uint32_t) * n);
+      L->scan = off;
+      off = align_up(off + sizeof(int64_t) * (n / 8192 + 2));
+      break;
+    }
     case SPGEMM_OP_COLPTR: {
       if (c0 < 0 || c1 < c0) return SPGEMM_E_INVAL;
       int64_t n = c1 - c0;

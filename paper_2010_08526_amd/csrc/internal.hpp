@@ -124,6 +124,9 @@ struct WsLayout {
   size_t bl_ri = 0;       // layers: int32 [nnz(B)] rows of the layer's share of B
   size_t bl_v = 0;        // layers: 8-byte [nnz(B)] values (numeric only)
   int64_t bl_cap = 0;     // layers: entries the two arrays hold (0 = no split)
+  size_t pr_cnt = 0;      // prune: int64 [ncol] entries each column keeps
+  size_t pr_cutv = 0;     // prune: uint64 [ncol] value key of the smallest kept entry
+  size_t pr_cutr = 0;     // prune: uint32 [ncol] row key of the smallest kept entry
   int64_t P = 0;          // numeric: slabs (0 = heavy columns use global accumulators)
   size_t total = 0;
   int64_t slots = 0, nseg = 0, ncol = 0, m = 0;

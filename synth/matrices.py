@@ -23,6 +23,7 @@ from .rng import Stream
 
 # Stream tags: one per kind of draw so that no two quantities share counters.
 TAG_ROWS, TAG_VALS, TAG_RMAT, TAG_WEIGHT, TAG_EDGE, TAG_TARGET, TAG_SHUFFLE, TAG_BATCH = range(1, 9)
+TAG_PRUNE_ROWS, TAG_PRUNE_VALS = 9, 10
 
 
 @dataclass
@@ -304,3 +305,33 @@ def batch_packed(spec: BatchSpec, seed: int, dtype=torch.float32, device="cpu", 
         vals = (1.0 - Stream(seed * 2 + which, TAG_VALS + 16 * tag).uniform(gcol_e * 32 + t)).to(dtype)
         mats.append(CSC(total, total, cp, rows, vals))
     return mats[0], mats[1], off
+
+
+def tie_heavy(m: int, counts, seed: int, dtype=torch.float32, levels: int = 9, nan_frac: float = 0.02,
+              device="cpu", chunk: int = 1 << 24) -> CSC:
+    """A matrix to prune: column j holds counts[j] distinct rows of [0, m) in
+    random order (the first counts[j] of a random permutation), values drawn
+    from ``levels`` equally spaced points of [-2, 2] (many ties), every zero
+    with a random sign, NaN with probability ``nan_frac``."""
+    dev = torch.device(device)
+    counts = torch.as_tensor(counts, dtype=torch.int64)
+    n = counts.numel()
+    if n and int(counts.max()) > m:
+        raise ValueError("count exceeds rows")
+    sr, sv = Stream(seed, TAG_PRUNE_ROWS), Stream(seed, TAG_PRUNE_VALS)
+    per = max(1, chunk // max(1, m))
+    rows = []
+    for c0 in range(0, n, per):
+        c1 = min(n, c0 + per)
+        idx = torch.arange(c0 * m, c1 * m, dtype=torch.int64).reshape(c1 - c0, m)
+        perm = torch.argsort(sr.uniform(idx), dim=1)
+        keep = torch.arange(m)[None, :] < counts[c0:c1, None]
+        rows.append(perm[keep])
+    rowidx = (torch.cat(rows) if rows else torch.zeros(0, dtype=torch.int64)).to(torch.int32)
+    nnz = rowidx.numel()
+    e = torch.arange(nnz, dtype=torch.int64)
+    lvl = sv.randint(3 * e, levels).to(torch.float64)
+    v = -2.0 + 4.0 * lvl / (levels - 1)
+    v = torch.where((v == 0) & (sv.uniform(3 * e + 1) < 0.5), torch.full_like(v, -0.0), v)
+    v = torch.where(sv.uniform(3 * e + 2) < nan_frac, torch.full_like(v, float("nan")), v)
+    return CSC(m, n, _colptr_from_counts(counts), rowidx, v.to(dtype)).to(dev)

@@ -212,3 +212,42 @@ def test_bin_caps_validation():
     sym = _np.array([32, 128, 512, 2048, 16384], _np.int64)
     assert lib.spgemm_set_bin_caps(0, sym.ctypes.data) == S.OK
     assert lib.spgemm_set_bin_caps(0, None) == S.OK
+
+
+def _prune(C, k=3, cap=None, thr=0.0, cp=0x5000, ri=0x6000, v=0x7000, ws=None, ws_bytes=1 << 30):
+    if cap is None:
+        cap = S.prune_bound(C.d.nnz, C.d.ncols, k) if C else 0
+    return S._lib.spgemm_prune_topk(ctypes.byref(C.d) if C else None, thr, k, cp, ri, v, cap, ws, ws_bytes, None)
+
+
+def _prune_ws(C):
+    out = ctypes.c_size_t(0)
+    assert S._lib.spgemm_workspace_size(S.OP_PRUNE, ctypes.byref(C.d), None, 0, 0, 1, ctypes.byref(out)) == S.OK
+    return int(out.value)
+
+
+def test_prune_validation_before_launch():
+    C = FakeCSC(100, 8, 50)
+    assert _prune(None) == S.E_INVAL
+    assert _prune(C, cp=None) == S.E_INVAL
+    assert _prune(C, k=3, cap=23) == S.E_INVAL  # bound min(50, 3 * 8) = 24
+    assert _prune(C, k=-1, cap=49) == S.E_INVAL  # no limit: bound nnz
+    assert _prune(C, k=100, cap=49) == S.E_INVAL
+    assert _prune(C, ri=None) == S.E_INVAL
+    assert _prune(C, v=None) == S.E_INVAL
+    assert _prune(C, k=0, cap=0, ri=None, v=None) == S.E_WORKSPACE  # nothing to hold: outputs may be NULL
+    assert _prune(FakeCSC(100, 8, 50, values=False)) == S.E_INVAL
+    assert _prune(FakeCSC(100, 8, 50, dtype=7)) == S.E_DTYPE
+    assert _prune(C) == S.E_WORKSPACE
+    assert _prune(C, ws=0x10010) == S.E_WORKSPACE
+    need = _prune_ws(C)
+    assert _prune(C, ws=0x10000, ws_bytes=need - 1) == S.E_WORKSPACE
+    # the bound does not overflow for huge k
+    assert _prune(C, k=1 << 62, cap=50) == S.E_WORKSPACE
+    assert S.prune_bound(50, 8, 1 << 62) == 50 and S.prune_bound(50, 8, 2) == 16 and S.prune_bound(50, 8, -1) == 50
+
+
+def test_prune_workspace_grows_with_columns():
+    a, b = _prune_ws(FakeCSC(10, 1000, 5)), _prune_ws(FakeCSC(10, 2000, 5))
+    assert b - a >= 20 * 1000 - 3 * 256  # 8 + 8 + 4 bytes per column, three regions aligned to 256 bytes
+    assert _prune_ws(FakeCSC(10, 0, 0)) > 0

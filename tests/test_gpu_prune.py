@@ -1,0 +1,122 @@
+"""GPU parity of the per-column pruning of an output batch (threshold, then
+top-k per column) against the oracle: column pointers, rows and value bits
+identical, entry for entry, since selection does no arithmetic."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_util import host_sorted
+
+pytestmark = pytest.mark.gpu
+
+S = None
+
+
+def setup_module(module):
+    global S
+    import paper_2010_08526_amd as lib
+    S = lib
+
+
+def _assert_exact(G, P, what):
+    cp = G.colptr.cpu().numpy()
+    assert np.array_equal(cp, P.colptr), f"{what}: column pointers differ"
+    ri = G.rowidx.cpu().numpy()
+    assert np.array_equal(ri, P.rowidx), f"{what}: rows differ"
+    v = G.values.cpu().numpy().astype(np.float64)
+    assert np.array_equal(v.view(np.uint64), P.values.view(np.uint64)), f"{what}: value bits differ"
+
+
+CASES = [(-np.inf, 1), (-np.inf, 3), (0.0, 2), (0.25, 0), (-0.75, 17), (-np.inf, -1), (1.0, -1), (-1.0, 64),
+         (np.nan, 4)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("threshold,k", CASES)
+def test_prune_ragged_ties(dtype, threshold, k):
+    """104 columns of 0 ... 2100 entries (empty, shorter than k, one to
+    three compaction steps of 1024 and their edges), values from 9 levels
+    with signed zeros and NaN."""
+    print(f"case: prune ragged {dtype} thr={threshold} k={k}", flush=True)
+    counts = torch.tensor([0, 1, 2, 300, 255, 256, 257, 1023, 1024, 1025, 2047, 2048, 2049, 2100] +
+                          [(37 * i) % 301 for i in range(90)])
+    M = synth.tie_heavy(2100, counts, 7, dtype)
+    G = S.prune_topk(M.to("cuda"), threshold, k)
+    _assert_exact(G, oracle.prune_topk(M, threshold, k), f"{dtype} {threshold} {k}")
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("k", [1, 100, 69999, 249999, 250000])
+def test_prune_long_columns(dtype, k):
+    """Columns of 250,000 and 70,000 entries: the select walks every digit of
+    long runs of equal values and the compaction spans about 1000 chunks."""
+    print(f"case: prune long {dtype} k={k}", flush=True)
+    M = synth.tie_heavy(400_000, [0, 250_000, 3, 70_000, 1], 11, dtype, levels=5, nan_frac=0.001)
+    for thr in (-np.inf, 0.0):
+        G = S.prune_topk(M.to("cuda"), thr, k)
+        _assert_exact(G, oracle.prune_topk(M, thr, k), f"long {thr} {k}")
+
+
+def test_prune_more_columns_than_workgroups():
+    """70,000 columns: more than the grid, so workgroups take several columns."""
+    print("case: prune 70000 columns", flush=True)
+    M = synth.tie_heavy(64, torch.arange(70_000) % 65, 13, torch.float32)
+    for thr, k in ((-np.inf, 5), (0.5, 1), (-np.inf, -1)):
+        G = S.prune_topk(M.to("cuda"), thr, k)
+        _assert_exact(G, oracle.prune_topk(M, thr, k), f"wide {thr} {k}")
+
+
+def test_prune_empty_matrices():
+    print("case: prune empty", flush=True)
+    for counts in ([], [0, 0, 0]):
+        M = synth.tie_heavy(10, counts, 1, torch.float32)
+        G = S.prune_topk(M.to("cuda"), 0.0, 3)
+        assert G.colptr.cpu().tolist() == [0] * (len(counts) + 1) and G.nnz == 0
+
+
+def test_prune_workspace_reuse_across_shapes():
+    """One workspace, a large call then a smaller one: per-column state is
+    rewritten by each call."""
+    print("case: prune workspace reuse", flush=True)
+    big = synth.tie_heavy(500, torch.arange(3000) % 501, 17, torch.float64)
+    small = synth.tie_heavy(40, torch.arange(50) % 41, 19, torch.float64)
+    ws = S.alloc_workspace(S.workspace_size(S.OP_PRUNE, big), "cuda")
+    for M, k in ((big, 7), (small, 2), (big, -1)):
+        G = S.prune_topk(M.to("cuda"), -1.0, k, ws=ws)
+        _assert_exact(G, oracle.prune_topk(M, -1.0, k), f"reuse {M.ncols} {k}")
+
+
+def test_prune_as_batch_consumer():
+    """The consumer of each output batch of C = A*B (integer-valued float64
+    inputs, so every product value is exact and ties are common): pruning
+    batch by batch gives, column for column, the kept set the oracle finds
+    on its own product."""
+    print("case: prune consumer", flush=True)
+    A = synth.erdos_renyi(3000, 3000, 12, 23, torch.float64)
+    A = A.with_values(torch.ceil(A.values * 3))
+    Ad = A.to("cuda")
+    eng = S.Engine(Ad, Ad, 1, None)
+    plan = eng.plan()
+    total_out = int((12 * plan.nnz_host[0] + 8).sum())
+    eng.budget_bytes = eng.input_bytes + eng.reserve_bytes + total_out // 4 + int(plan.nnz_host[0].max()) * 12 + 8
+    thr, k = 2.0, 6
+    kept = []
+
+    def consume(c0, c1, Cb):
+        kept.append((c0, c1, S.prune_topk(Cb, thr, k)))
+
+    pl = eng.run(consume=consume)
+    assert pl.nbatches >= 3
+    P = oracle.prune_topk(oracle.spgemm(A, A), thr, k)
+    for c0, c1, G in kept:
+        cp, ri, v = host_sorted(G)
+        assert np.array_equal(cp, P.colptr[c0:c1 + 1] - P.colptr[c0]), f"batch {c0}:{c1} counts"
+        s, e = P.colptr[c0], P.colptr[c1]
+        col = np.repeat(np.arange(c1 - c0), np.diff(P.colptr[c0:c1 + 1]))
+        order = np.lexsort((P.rowidx[s:e], col))
+        assert np.array_equal(ri, P.rowidx[s:e][order]), f"batch {c0}:{c1} rows"
+        assert np.array_equal(v, P.values[s:e][order]), f"batch {c0}:{c1} values"
