@@ -54,8 +54,8 @@ def _parse():
     p.add_argument("--protein-n", type=int, default=2_000_000)
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--no-extras", action="store_true", help="skip the fwd_bwd, batched, layered, bsweep and prune sections")
-    p.add_argument("--extras", default="fwd_bwd,batched,layered,bsweep,prune", help="comma-separated extra sections to run")
+    p.add_argument("--no-extras", action="store_true", help="skip the fwd_bwd, batched, layered, bsweep, prune and aat sections")
+    p.add_argument("--extras", default="fwd_bwd,batched,layered,bsweep,prune,aat", help="comma-separated extra sections to run")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain device copy of known size (to scale HBM byte counters) and exit")
     return p.parse_args()
@@ -538,6 +538,39 @@ def measured_traffic(kernel, workload):
     return int(t["hbm_bytes_per_launch"])
 
 
+def aat(args, torch, np, S, synth):
+    """The paper's second workload shape, A*A^T (products of the Rice-kmers
+    matrix with its transpose): A with m = 1,000,000 rows, k = 50,000,000
+    columns and two entries per column at distinct uniform rows (k >> m, cf
+    about 2, light columns only).  The transpose runs on the GPU; one
+    warm-up, then one timed transpose and one timed product."""
+    dev = torch.device("cuda:0")
+    m, k = 1_000_000, 50_000_000
+    A = synth.erdos_renyi(m, k, 2, 201008526 + 7, torch.float32, device=dev)
+    times = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        At, _ = S.transpose(A, perm=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        eng = S.Engine(A, At, 1, None)
+        C, pl = eng.run()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times.append((t1 - t0, t2 - t1))
+        nnz_c, flops = C.nnz, pl.total_flops
+        del C, eng, At
+        torch.cuda.empty_cache()
+    tt, tp = times[-1]
+    log(f"aat: m={m} k={k} nnz(A)={A.nnz} flops={flops:.4e} nnz(C)={nnz_c:.4e} cf={flops / nnz_c:.2f}, "
+        f"transpose {tt * 1e3:.1f} ms, product {tp * 1e3:.1f} ms ({2 * flops / tp / 1e9:.1f} GFLOP/s, {pl.nbatches} batch)")
+    del A
+    return {"workload": f"A*A^T, A {m} x {k}, 2 entries per column at distinct uniform rows, float32",
+            "flops": flops, "nnz_c": nnz_c, "cf": round(flops / nnz_c, 3), "transpose_ms": round(tt * 1e3, 2),
+            "product_ms": round(tp * 1e3, 2), "GFLOPs": round(2 * flops / tp / 1e9, 2), "batches": pl.nbatches}
+
+
 def prune(args, torch, np, S, synth):
     """The consumer the paper puts after each batch (an application prunes
     every batch of C before the next; Markov clustering keeps the largest
@@ -605,7 +638,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_extras:
         for name, fn in (("fwd_bwd", fwd_bwd), ("batched", batched), ("layered", layered), ("bsweep", bsweep),
-                         ("prune", prune)):
+                         ("prune", prune), ("aat", aat)):
             if name in args.extras.split(","):
                 res[name] = fn(args, torch, np, S, synth)
                 torch.cuda.empty_cache()
