@@ -283,8 +283,9 @@ int spgemm_batched_backward(const spgemm_csc *A, const spgemm_csc *B, const spge
  * arrays of C are only read; the outputs must not overlap them.
  * Workspace: spgemm_workspace_size(SPGEMM_OP_PRUNE, C, NULL, 0, 0, 1, ...).
  * Device-side checks (spgemm_ws_status_code): 5 column pointers outside
- * the arrays (that column is treated as empty), 10 a row twice in one
- * column (that column is cut at k).  Errors: SPGEMM_E_INVAL for a NULL
+ * the arrays (that column is treated as empty), 10 a row twice in a column
+ * that had more than k candidates (that column keeps its first k kept
+ * entries; a column that keeps all its candidates is not checked).  Errors: SPGEMM_E_INVAL for a NULL
  * output or a capacity below the bound, SPGEMM_E_DTYPE, SPGEMM_E_WORKSPACE. */
 int spgemm_prune_topk(const spgemm_csc *C, double threshold, int64_t k, int64_t *out_colptr, int32_t *out_rowidx,
                       void *out_values, int64_t out_cap, void *ws, size_t ws_bytes, void *stream);
@@ -323,8 +324,8 @@ int spgemm_ws_status(void *ws, void *stream);
  * the symbolic pass, 5 column pointers inconsistent with the arrays they
  * index, 7 a column above the largest LDS table in a call without a host
  * synchronization, 8 an output larger than the capacity given, 9 a
- * malformed internal work item, 10 a row twice in one column of a matrix
- * being pruned. */
+ * malformed internal work item, 10 a row twice in a pruned column that had
+ * more than k candidates. */
 int spgemm_ws_status_code(void *ws, void *stream, int32_t *code_host);
 
 /* What a workspace keeps between calls: consecutive spgemm_numeric calls on
