@@ -460,3 +460,26 @@ def test_prune_special_cases():
     E = Mat(5, 3, np.zeros(4, np.int64), np.zeros(0, np.int32), np.zeros(0))
     assert oracle.prune_topk(E, 0.0, 2).colptr.tolist() == [0, 0, 0, 0]
     assert oracle.prune_topk(Mat(5, 0, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0)), 0.0, 2).nnz == 0
+
+
+def test_aat_closed_forms():
+    """A A^T (the paper's second workload shape): symmetric, its diagonal the
+    row sums of squares, equal to scipy's product; cf near 2 for two entries
+    per column with k >> m."""
+    rng = np.random.default_rng(8)
+    m, k = 300, 20000
+    rows = np.stack([rng.choice(m, 2, replace=False) for _ in range(k)]).reshape(-1).astype(np.int32)
+    vals = rng.random(2 * k) + 0.5
+    A = Mat(m, k, np.arange(0, 2 * k + 1, 2, dtype=np.int64), rows, vals)
+    S_ = sp.csc_matrix((vals, rows, A.colptr), shape=(m, k))
+    T = S_.T.tocsc()
+    At = Mat(k, m, T.indptr.astype(np.int64), T.indices.astype(np.int32), T.data.astype(np.float64))
+    P = oracle.spgemm(A, At)
+    D = np.zeros((m, m))
+    for j in range(m):
+        for p in range(P.colptr[j], P.colptr[j + 1]):
+            D[P.rowidx[p], j] = P.values[p]
+    assert np.allclose(D, D.T, rtol=1e-13, atol=0)
+    assert np.allclose(np.diag(D), np.asarray(S_.multiply(S_).sum(axis=1)).ravel(), rtol=1e-13)
+    assert np.allclose(D, (S_ @ S_.T).toarray(), rtol=1e-13, atol=0)
+    assert 1.5 < int(oracle.flops(A, At).sum()) / P.nnz <= 4.0

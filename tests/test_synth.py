@@ -106,3 +106,27 @@ def test_targets_depend_on_coordinates_only():
     c = torch.tensor([0, 2, 2, 2])
     t = synth.target_values(r, c, 10, 8)
     assert t[1] == t[3] and t[0] != t[1]
+
+
+def test_tie_heavy_columns_and_values():
+    counts = [0, 1, 7, 50, 50, 3]
+    M = synth.tie_heavy(50, counts, 4, torch.float64, levels=9, nan_frac=0.05)
+    assert M.colptr.tolist() == np.cumsum([0] + counts).tolist()
+    for j in range(M.ncols):
+        r = M.rowidx[M.colptr[j]:M.colptr[j + 1]].numpy()
+        assert r.size == np.unique(r).size and (r.size == 0 or (r.min() >= 0 and r.max() < 50))
+    v = M.values.numpy()
+    finite = v[~np.isnan(v)]
+    assert set(np.unique(finite).tolist()) <= {-2.0 + 0.5 * i for i in range(9)}
+    # deterministic, and a full column is a permutation of the rows
+    M2 = synth.tie_heavy(50, counts, 4, torch.float64, levels=9, nan_frac=0.05)
+    assert torch.equal(M.rowidx, M2.rowidx) and np.array_equal(v.view(np.uint64), M2.values.numpy().view(np.uint64))
+    assert sorted(M.rowidx[M.colptr[3]:M.colptr[4]].tolist()) == list(range(50))
+    # many entries: both zero signs and about the NaN fraction asked for
+    B = synth.tie_heavy(1000, [1000] * 40, 5, torch.float32, levels=9, nan_frac=0.02)
+    bv = B.values.numpy()
+    zeros = bv[bv == 0]
+    assert np.signbit(zeros).any() and (~np.signbit(zeros)).any()
+    assert 0.015 < np.isnan(bv).mean() < 0.025
+    # rows are not left sorted inside a column
+    assert not all(np.all(np.diff(B.rowidx[B.colptr[j]:B.colptr[j + 1]].numpy()) > 0) for j in range(3))
