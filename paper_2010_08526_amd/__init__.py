@@ -210,7 +210,7 @@ def check_ws(ws: torch.Tensor, where: str = "device check", stream=None):
     _check(rc, f"{where} (device code {code})" if code else where)
 
 
-# ------------------------------------------------------------ batch driver
+# -------------------------------------------------------------- batch loop
 def layer_bounds(kdim: int, n_layers: int) -> list[tuple[int, int]]:
     """The inner-dimension ranges the library uses for n_layers layers."""
     w = -(-kdim // n_layers) if n_layers > 0 else kdim
