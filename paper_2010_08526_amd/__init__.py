@@ -429,6 +429,30 @@ def prune_topk(C, threshold: float, k: int, ws: torch.Tensor | None = None, stre
     return CSC(C.nrows, C.ncols, cp, ri[:n], v[:n])
 
 
+def spgemm_topk(A, B, threshold: float, k: int, *, layers: int = 1, budget_bytes: int | None = None,
+                stream=None) -> CSC:
+    """C = A B formed batch by batch, every batch pruned as it is formed
+    (``prune_topk``: entries >= threshold, at most the k largest per column)
+    and only the pruned batches kept, concatenated: the whole product never
+    needs to fit in memory, only one batch of it."""
+    eng = Engine(A, B, layers, budget_bytes)
+    ws = {}
+    kept = []
+
+    def consume(c0, c1, Cb):
+        need = workspace_size(OP_PRUNE, Cb)
+        if "ws" not in ws or ws["ws"].numel() < need:
+            ws["ws"] = alloc_workspace(need, Cb.rowidx.device)
+        kept.append(prune_topk(Cb, threshold, k, ws=ws["ws"], stream=stream))
+
+    eng.run(consume, stream)
+    if not kept:  # no batches
+        dev = A.rowidx.device
+        return CSC(A.nrows, B.ncols, torch.zeros(B.ncols + 1, dtype=torch.int64, device=dev),
+                   torch.zeros(0, dtype=torch.int32, device=dev), torch.zeros(0, dtype=A.values.dtype, device=dev))
+    return _concat(kept, A.nrows)
+
+
 # ------------------------------------------------------------ gradient support
 _lib.spgemm_transpose.argtypes = [_P, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.spgemm_masked_xty.argtypes = [_P, _P, _P, _vp, _vp, _sz, _vp]

@@ -120,3 +120,28 @@ def test_prune_as_batch_consumer():
         order = np.lexsort((P.rowidx[s:e], col))
         assert np.array_equal(ri, P.rowidx[s:e][order]), f"batch {c0}:{c1} rows"
         assert np.array_equal(v, P.values[s:e][order]), f"batch {c0}:{c1} values"
+
+
+def test_spgemm_topk_keeps_only_pruned_batches():
+    """The one-call form: C = A*A formed in at least three batches, each
+    pruned as it is formed; the concatenation equals, column for column,
+    the oracle's product pruned as a whole (integer-valued float64 inputs,
+    so products are exact and ties common)."""
+    print("case: spgemm_topk", flush=True)
+    A = synth.erdos_renyi(2500, 2500, 10, 29, torch.float64)
+    A = A.with_values(torch.ceil(A.values * 3))
+    Ad = A.to("cuda")
+    eng = S.Engine(Ad, Ad, 1, None)
+    plan = eng.plan()
+    total_out = int((12 * plan.nnz_host[0] + 8).sum())
+    budget = eng.input_bytes + eng.reserve_bytes + total_out // 3 + int(plan.nnz_host[0].max()) * 12 + 8
+    del eng
+    thr, k = 3.0, 4
+    G = S.spgemm_topk(Ad, Ad, thr, k, budget_bytes=budget)
+    P = oracle.prune_topk(oracle.spgemm(A, A), thr, k)
+    cp, ri, v = host_sorted(G)
+    assert np.array_equal(cp, P.colptr)
+    col = np.repeat(np.arange(P.ncols), np.diff(P.colptr))
+    order = np.lexsort((P.rowidx, col))
+    assert np.array_equal(ri, P.rowidx[order]) and np.array_equal(v, P.values[order])
+    assert G.nnz <= k * A.ncols
