@@ -127,6 +127,43 @@ class BatchedEngine:
         self.graph.replay()
 
 
+def spgemm_batched(pairs, graph: bool = True, device="cuda"):
+    """C_i = A_i B_i for a list of (A_i, B_i) pairs of device CSCs, as one
+    packed product: one symbolic pass, one scan and one numeric pass over all
+    instances.  With graph=True the forward is captured in a HIP graph and
+    run by a replay.  Returns (list of C_i, rows local to each instance, the
+    engine); the engine replays the product for new values of the same
+    patterns (its packed A and B hold the values)."""
+    if not pairs:
+        raise ValueError("no instances")
+    As = [a for a, _ in pairs]
+    Bs = [b for _, b in pairs]
+    for i, (a, b) in enumerate(pairs):
+        if int(a.ncols) != int(b.nrows):
+            raise ValueError(f"instance {i}: A has {a.ncols} columns, B has {b.nrows} rows")
+        if a.values is None or b.values is None or a.values.dtype != As[0].values.dtype or \
+                b.values.dtype != As[0].values.dtype:
+            raise ValueError(f"instance {i}: every operand needs values of one dtype")
+    A, offA = batch_pack(As, device)
+    B, offB = batch_pack(Bs, device)
+    eng = BatchedEngine(A, B, device=device)
+    if graph:
+        eng.capture(eng.forward)
+        eng.replay()
+    else:
+        eng.forward()
+    eng.check()
+    C = eng.C
+    cp = C.colptr.cpu().numpy()
+    out = []
+    for i in range(len(pairs)):
+        c0, c1 = int(offB[i, 1]), int(offB[i + 1, 1])
+        e0, e1 = int(cp[c0]), int(cp[c1])
+        out.append(CSC(int(As[i].nrows), int(Bs[i].ncols), C.colptr[c0:c1 + 1] - e0,
+                       C.rowidx[e0:e1] - int(offA[i, 0]), C.values[e0:e1]))
+    return out, eng
+
+
 # ------------------------------------------------------------------ autotuner
 def _cache_path() -> str:
     base = os.environ.get("XDG_CACHE_HOME", os.path.join(os.path.expanduser("~"), ".cache"))
