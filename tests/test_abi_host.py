@@ -251,3 +251,34 @@ def test_prune_workspace_grows_with_columns():
     a, b = _prune_ws(FakeCSC(10, 1000, 5)), _prune_ws(FakeCSC(10, 2000, 5))
     assert b - a >= 20 * 1000 - 3 * 256  # 8 + 8 + 4 bytes per column, three regions aligned to 256 bytes
     assert _prune_ws(FakeCSC(10, 0, 0)) > 0
+
+
+# ------------------------------------------------- planner properties (hypothesis)
+from hypothesis import given, settings  # noqa: E402
+from hypothesis import strategies as st  # noqa: E402
+
+
+@settings(max_examples=150, deadline=None)
+@given(st.lists(st.integers(0, 400), min_size=1, max_size=60), st.integers(0, 3000), st.integers(0, 3000),
+       st.sampled_from([4, 8]))
+def test_planner_properties(counts, extra, extra2, vb):
+    """Every batch fits, the batches tile the columns in order, a larger
+    budget never needs more batches, one batch exactly when everything
+    fits, and the count is at least the Eq. (2) bound ceil(total / avail)."""
+    nnz = np.array(counts, np.int64)
+    n = nnz.size
+    mem = (4 + vb) * nnz + 8
+    avail = int(mem.max()) + extra
+    b, tot = S.plan_batches(nnz, n, 1, vb, 0, avail, 0)
+    assert b[0] == 0 and b[-1] == n and all(x < y for x, y in zip(b, b[1:]))
+    for i in range(len(b) - 1):
+        assert int(mem[b[i]:b[i + 1]].sum()) <= avail
+        assert int(tot[i][0]) == int(nnz[b[i]:b[i + 1]].sum())
+    nb = len(b) - 1
+    assert nb >= -(-int(mem.sum()) // avail)
+    assert (nb == 1) == (int(mem.sum()) <= avail)
+    b2, _ = S.plan_batches(nnz, n, 1, vb, 0, avail + extra2, 0)
+    assert len(b2) - 1 <= nb
+    # an input and reserve share moves the budget, not the split
+    b3, _ = S.plan_batches(nnz, n, 1, vb, 1000, avail + 1500, 500)
+    assert b3 == b

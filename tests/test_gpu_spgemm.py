@@ -291,3 +291,23 @@ def test_b_rows_outside_inner_dimension_flagged(layers):
     S.numeric(Ad, Bbad, 0, n, 0, layers, fl, cp, c_ri, c_v, wsn)
     assert S.ws_status_code(wsn) == (S.E_DEVICE, 1)
     assert torch.all(c_ri[total:] == -5)  # nothing written past the output
+
+
+def test_one_column_per_batch():
+    """b = ncols: A = 2 I and three entries per column of B, so every column
+    of C holds exactly three entries and a budget of one column's bytes
+    gives one batch per column; the concatenation equals C."""
+    print("case: one column per batch", flush=True)
+    n = 150
+    B = synth.erdos_renyi(n, n, 3, 37, torch.float32)
+    A = synth.CSC(n, n, torch.arange(n + 1, dtype=torch.int64), torch.arange(n, dtype=torch.int32),
+                  torch.full((n,), 2.0, dtype=torch.float32))
+    eng = S.Engine(A.to("cuda"), B.to("cuda"), 1, None)
+    eng.plan()
+    eng.budget_bytes = eng.input_bytes + eng.reserve_bytes + 3 * 8 + 8
+    C, plan = eng.run()
+    assert plan.nbatches == n
+    P = oracle.spgemm(A, B)
+    assert_matches(C, P, torch.float32, "b = ncols")
+    cp, ri, v = host_sorted(C)
+    assert np.array_equal(v, P.values)  # single-term products are exact
