@@ -415,6 +415,8 @@ def prune_topk(C, threshold: float, k: int, ws: torch.Tensor | None = None, stre
     each column (k < 0: no limit), equal values going to the smaller row;
     kept entries stay in input order.  Reads the entry count back to the
     host and checks the workspace status."""
+    if C.values is None:
+        raise ValueError("prune_topk needs values")
     dev = C.rowidx.device
     if ws is None:
         ws = alloc_workspace(workspace_size(OP_PRUNE, C), dev)

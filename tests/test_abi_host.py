@@ -10,6 +10,7 @@ import os
 import re
 
 import numpy as np
+import torch
 import pytest
 
 import oracle
@@ -282,3 +283,9 @@ def test_planner_properties(counts, extra, extra2, vb):
     # an input and reserve share moves the budget, not the split
     b3, _ = S.plan_batches(nnz, n, 1, vb, 1000, avail + 1500, 500)
     assert b3 == b
+
+
+def test_prune_binding_rejects_pattern_only():
+    M = S.CSC(4, 2, torch.zeros(3, dtype=torch.int64), torch.zeros(0, dtype=torch.int32), None)
+    with pytest.raises(ValueError):
+        S.prune_topk(M, 0.0, 1)

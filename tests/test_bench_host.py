@@ -47,3 +47,17 @@ def test_source_digest_covers_every_device_source():
     names = sorted(n for n in os.listdir(csrc) if n.endswith((".hip", ".hpp")))
     assert "kernels.hip" in names and "backward.hip" in names
 
+
+
+def test_default_run_covers_every_section():
+    b = _bench()
+    argv = sys.argv
+    try:
+        sys.argv = ["bench.py"]
+        args = b._parse()
+    finally:
+        sys.argv = argv
+    assert args.gpus == 1 and not args.no_extras
+    assert set(args.extras.split(",")) == {"fwd_bwd", "batched", "layered", "bsweep", "prune", "aat"}
+    for name in args.extras.split(","):
+        assert callable(getattr(b, name))
