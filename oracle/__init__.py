@@ -20,6 +20,8 @@ numpy arrays.  Every function cites the passage it implements:
 * ``prune_topk``  -- the per-column pruning an application applies to each
                      output batch (threshold, then top-k per column; Sec. I,
                      Sec. IV-B, Sec. V-C), in numpy.
+* ``spgemm_semiring`` -- the product over another semiring (min-plus,
+                     or-and; Sec. II-A), pure Python for small inputs.
 
 Parity status: every function here is pinned by tests in
 ``tests/test_oracle.py`` against numpy/scipy, closed forms, invariants or
@@ -274,3 +276,39 @@ def prune_topk(M, threshold: float, k: int) -> Mat:
         colptr[j + 1] = colptr[j] + cand.size
     cat = (lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.zeros(0, dt))
     return Mat(M.nrows, M.ncols, colptr, cat(rows, np.int32), cat(vals, np.float64))
+
+
+_SEMIRINGS = {
+    # name: (add, multiply)
+    "plus_times": (lambda x, y: x + y, lambda a, b: a * b),
+    "min_plus": (min, lambda a, b: a + b),
+    "or_and": (lambda x, y: 1.0, lambda a, b: 1.0),
+}
+
+
+def spgemm_semiring(A, B, semiring: str) -> Mat:
+    """C = A B over a semiring (Sec. II-A: the algorithms apply to any
+    semiring since nothing Strassen-like is used): for every (i, j) with at
+    least one product term, C(i, j) is the semiring sum over k of
+    A(i, k) (x) B(k, j), terms taken in B's order, then A's.  plus_times is
+    the ordinary product; min_plus the tropical one (shortest paths);
+    or_and the boolean one (every structural entry is 1).  Pure Python,
+    for small inputs.  Rows come out sorted per column."""
+    add, mul = _SEMIRINGS[semiring]
+    A, B = as_mat(A), as_mat(B)
+    if A.ncols != B.nrows:
+        raise ValueError("inner dimensions differ")
+    colptr = np.zeros(B.ncols + 1, np.int64)
+    rows, vals = [], []
+    for j in range(B.ncols):
+        acc = {}
+        for q in range(B.colptr[j], B.colptr[j + 1]):
+            kk, bv = int(B.rowidx[q]), float(B.values[q])
+            for p in range(A.colptr[kk], A.colptr[kk + 1]):
+                i, t = int(A.rowidx[p]), mul(float(A.values[p]), bv)
+                acc[i] = add(acc[i], t) if i in acc else t
+        for i in sorted(acc):
+            rows.append(i)
+            vals.append(acc[i])
+        colptr[j + 1] = colptr[j] + len(acc)
+    return Mat(A.nrows, B.ncols, colptr, np.array(rows, np.int32), np.array(vals, np.float64))

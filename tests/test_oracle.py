@@ -483,3 +483,58 @@ def test_aat_closed_forms():
     assert np.allclose(np.diag(D), np.asarray(S_.multiply(S_).sum(axis=1)).ravel(), rtol=1e-13)
     assert np.allclose(D, (S_ @ S_.T).toarray(), rtol=1e-13, atol=0)
     assert 1.5 < int(oracle.flops(A, At).sum()) / P.nnz <= 4.0
+
+
+# ------------------------------------------------------------------ semirings
+def test_semiring_plus_times_is_the_product():
+    rng = np.random.default_rng(21)
+    A, B = random_sparse(30, 25, 0.2, rng), random_sparse(25, 28, 0.2, rng)
+    P, Q = oracle.spgemm(A, B), oracle.spgemm_semiring(A, B, "plus_times")
+    assert np.array_equal(P.colptr, Q.colptr) and np.array_equal(P.rowidx, Q.rowidx)
+    assert np.allclose(P.values, Q.values, rtol=1e-13, atol=0)
+
+
+def test_semiring_or_and_is_the_pattern_product():
+    rng = np.random.default_rng(22)
+    A, B = random_sparse(40, 30, 0.1, rng), random_sparse(30, 35, 0.1, rng)
+    Q = oracle.spgemm_semiring(A, B, "or_and")
+    want = (pattern_dense(A).astype(np.int64) @ pattern_dense(B).astype(np.int64)) > 0
+    got = np.zeros_like(want)
+    for j in range(Q.ncols):
+        got[Q.rowidx[Q.colptr[j]:Q.colptr[j + 1]], j] = True
+    assert np.array_equal(got, want) and np.all(Q.values == 1.0)
+
+
+def test_semiring_min_plus_squaring_reaches_shortest_paths():
+    """Repeated min-plus squaring of a weight matrix with a zero diagonal
+    gives distances over at most 2^t edges; after ceil(log2 n) squarings they
+    are the all-pairs shortest paths (scipy's Dijkstra)."""
+    from scipy.sparse.csgraph import shortest_path
+    rng = np.random.default_rng(23)
+    n = 24
+    mask = rng.random((n, n)) < 0.12
+    np.fill_diagonal(mask, False)
+    Wd = np.where(mask, rng.integers(1, 10, (n, n)).astype(np.float64), 0.0)
+    D = Wd.copy()
+    np.fill_diagonal(D, 0.0)
+    # the zero diagonal must be stored: the pattern is mask | I
+    pat = mask | np.eye(n, dtype=bool)
+    colptr = np.concatenate([[0], np.cumsum(pat.sum(0))]).astype(np.int64)
+    rows = np.concatenate([np.nonzero(pat[:, j])[0] for j in range(n)]).astype(np.int32)
+    vals = np.concatenate([D[pat[:, j], j] for j in range(n)])
+    M = Mat(n, n, colptr, rows, vals)
+    for _ in range(int(np.ceil(np.log2(n)))):
+        M = oracle.spgemm_semiring(M, M, "min_plus")
+    got = np.full((n, n), np.inf)
+    for j in range(n):
+        got[M.rowidx[M.colptr[j]:M.colptr[j + 1]], j] = M.values[M.colptr[j]:M.colptr[j + 1]]
+    # entry (i, j) of the column-oriented product is the path i <- j, i.e. from j to i along W(i, k) W(k, j)
+    want = shortest_path(sp.csr_matrix(Wd.T), method="D", directed=True).T
+    assert np.array_equal(got, want)
+
+
+def test_semiring_min_plus_two_hops_by_hand():
+    # edges 0->1 (2), 1->2 (3), 0->2 (7): stored as W(dst, src); two hops from 0 to 2 cost 5
+    W = Mat(3, 3, np.array([0, 2, 3, 3]), np.array([1, 2, 2], np.int32), np.array([2.0, 7.0, 3.0]))
+    Q = oracle.spgemm_semiring(W, W, "min_plus")  # exactly two edges
+    assert Q.colptr.tolist() == [0, 1, 1, 1] and Q.rowidx.tolist() == [2] and Q.values.tolist() == [5.0]
