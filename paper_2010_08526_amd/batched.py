@@ -133,7 +133,8 @@ def spgemm_batched(pairs, graph: bool = True, device="cuda"):
     instances.  With graph=True the forward is captured in a HIP graph and
     run by a replay.  Returns (list of C_i, rows local to each instance, the
     engine); the engine replays the product for new values of the same
-    patterns (its packed A and B hold the values)."""
+    patterns (its packed A and B hold the values).  The C_i are views of the
+    engine's output buffers: a replay rewrites them in place."""
     if not pairs:
         raise ValueError("no instances")
     As = [a for a, _ in pairs]
