@@ -538,3 +538,32 @@ def test_semiring_min_plus_two_hops_by_hand():
     W = Mat(3, 3, np.array([0, 2, 3, 3]), np.array([1, 2, 2], np.int32), np.array([2.0, 7.0, 3.0]))
     Q = oracle.spgemm_semiring(W, W, "min_plus")  # exactly two edges
     assert Q.colptr.tolist() == [0, 1, 1, 1] and Q.rowidx.tolist() == [2] and Q.values.tolist() == [5.0]
+
+
+from hypothesis import given, settings  # noqa: E402
+from hypothesis import strategies as st  # noqa: E402
+
+
+@settings(max_examples=120, deadline=None)
+@given(st.integers(0, 10 ** 6), st.integers(0, 12), st.integers(0, 12), st.floats(-2.5, 2.5), st.floats(0, 2))
+def test_prune_monotone(seed, k1, k2, t1, dt):
+    """A larger k keeps a superset (the smaller kept set is a prefix of the
+    larger in rank order); a higher threshold keeps a subset; counts are
+    min(k, candidates) per column."""
+    M = _tie_heavy(seed % 1000, m=10, n=8, dens=0.7)
+    ka, kb = min(k1, k2), max(k1, k2)
+    t2 = t1 + dt
+
+    def kept(P):
+        return [set(P.rowidx[P.colptr[j]:P.colptr[j + 1]].tolist()) for j in range(P.ncols)]
+
+    Pa, Pb = oracle.prune_topk(M, t1, ka), oracle.prune_topk(M, t1, kb)
+    assert all(x <= y for x, y in zip(kept(Pa), kept(Pb)))
+    Ph = oracle.prune_topk(M, t2, kb)
+    Pl = oracle.prune_topk(M, t1, -1)
+    Phl = oracle.prune_topk(M, t2, -1)
+    assert all(x <= y for x, y in zip(kept(Phl), kept(Pl)))
+    for j in range(M.ncols):
+        v = M.values[M.colptr[j]:M.colptr[j + 1]]
+        ncand = int((v >= t2).sum())
+        assert Ph.colptr[j + 1] - Ph.colptr[j] == min(kb, ncand)
