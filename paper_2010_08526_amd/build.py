@@ -10,6 +10,7 @@ instructions are switched off for all device code.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -41,17 +42,21 @@ def build(verbose: bool = False) -> str:
     """Compile every source and link libspgemm.so; always recompiles."""
     os.makedirs(LIBDIR, exist_ok=True)
     hipcc = _hipcc()
-    objs = []
+    objs, cmds = [], []
     for src in ("host.cpp", "kernels.hip", "backward.hip", "prune.hip", "profile.cpp"):
-        obj = os.path.join(LIBDIR, src.replace(".", "_") + ".o")
+        obj = os.path.join(LIBDIR, src.replace(".", "_") + f".{os.getpid()}.o")
         cmd = [hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if src == "host.cpp":
             cmd = [hipcc, "-O2", "-std=c++17", "-fPIC", "-Wall", f"-I{os.path.join(ROOT, 'include')}", "-c",
                    os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        cmds.append(cmd)
         objs.append(obj)
+    # the translation units are independent: compile them side by side
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
+        for f in [ex.submit(subprocess.check_call, c) for c in cmds]:
+            f.result()
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

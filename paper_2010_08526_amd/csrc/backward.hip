@@ -371,7 +371,7 @@ static int mxty_typed(const spgemm_csc *X, const spgemm_csc *Y, const spgemm_csc
   WsHeader *hdr = (WsHeader *)ws;
   int32_t *bins = (int32_t *)(ws + L.bins);
   const int64_t n = Y->ncols;
-  int rc = launch_init_header(hdr, 1, st);
+  int rc = launch_init_header(hdr, zero_region_tag(kTagMasked, L), st);
   if (rc) return rc;
   hipLaunchKernelGGL(k_mxty_bin, dim3(grid_of(n, 256)), dim3(256), 0, st, Y->colptr, M->colptr, n, g_min_bin_value(),
                      bin_caps(1), bins, hdr);
@@ -412,7 +412,7 @@ static int mxty_typed(const spgemm_csc *X, const spgemm_csc *Y, const spgemm_csc
   if (heavy > 0) {
     if (L.slots <= 0) return SPGEMM_E_INVAL;
     double *dense = (double *)(ws + L.heavy_vals);
-    const uint64_t tag = 0x6d78747900000000ull ^ ((uint64_t)L.slots << 32) ^ (uint64_t)L.m;
+    const uint64_t tag = zero_region_tag(kTagMasked, L);
     if (h.clean_tag != tag) {
       hipLaunchKernelGGL(k_tr_zero, dim3(4 * device_cus()), dim3(256), 0, st, (unsigned long long *)dense,
                          L.slots * L.m);
@@ -655,7 +655,7 @@ static int fbwd_typed(const spgemm_csc *A, const spgemm_csc *B, const spgemm_csc
   int32_t *bins = (int32_t *)(ws + L.bins);
   double *acc = (double *)(ws + L.heavy_vals);
   const int64_t n = C->ncols;
-  int rc = launch_init_header(hdr, 0, st);
+  int rc = launch_init_header(hdr, (uint64_t)0, st);
   if (rc) return rc;
   const unsigned gz = (unsigned)std::max<int64_t>(1, std::min<int64_t>(grid_of(A->nnz, 256), 8 * device_cus()));
   hipLaunchKernelGGL(k_zero_f64, dim3(gz), dim3(256), 0, st, acc, A->nnz);
@@ -690,7 +690,7 @@ template <class VT>
 static int transpose_typed(const spgemm_csc *X, int64_t *t_colptr, int32_t *t_rowidx, void *t_values, int64_t *perm,
                            const WsLayout &L, char *ws, hipStream_t st) {
   WsHeader *hdr = (WsHeader *)ws;
-  int rc = launch_init_header(hdr, 0, st);
+  int rc = launch_init_header(hdr, (uint64_t)0, st);
   if (rc) return rc;
   ProfScope prof("transpose", st);
   const int64_t m = X->nrows;
@@ -754,7 +754,7 @@ int spgemm_masked_xty(const spgemm_csc *X, const spgemm_csc *Y, const spgemm_csc
   st = check_ws(ws, ws_bytes, L.total);
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
-  if (Y->ncols == 0 || M->nnz == 0) return launch_init_header((WsHeader *)ws, 1, s);
+  if (Y->ncols == 0 || M->nnz == 0) return launch_init_header((WsHeader *)ws, kKeepAnyTag, s);
   if (X->dtype == SPGEMM_F64) return mxty_typed<double>(X, Y, M, out_values, L, (char *)ws, s, true);
   return mxty_typed<float>(X, Y, M, out_values, L, (char *)ws, s, true);
 }
@@ -774,7 +774,7 @@ int spgemm_batched_masked_xty(const spgemm_csc *X, const spgemm_csc *Y, const sp
   st = check_ws(ws, ws_bytes, L.total);
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
-  if (Y->ncols == 0 || M->nnz == 0) return launch_init_header((WsHeader *)ws, 1, s);
+  if (Y->ncols == 0 || M->nnz == 0) return launch_init_header((WsHeader *)ws, kKeepAnyTag, s);
   if (X->dtype == SPGEMM_F64) return mxty_typed<double>(X, Y, M, out_values, L, (char *)ws, s, false);
   return mxty_typed<float>(X, Y, M, out_values, L, (char *)ws, s, false);
 }

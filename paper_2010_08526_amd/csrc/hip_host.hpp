@@ -10,7 +10,9 @@ namespace spg {
 int hip_fail(hipError_t e);
 int read_header(WsHeader *dev, hipStream_t st, WsHeader *out);  // synchronizes st
 int device_cus();
-int launch_init_header(WsHeader *h, int keep_clean, hipStream_t st);
+// keep_tag: the zero_region_tag of the caller's accumulator region (the
+// header's clean_tag survives only if it equals it), 0, or kKeepAnyTag
+int launch_init_header(WsHeader *h, uint64_t keep_tag, hipStream_t st);
 int launch_set_tag(WsHeader *h, uint64_t tag, hipStream_t st);
 int g_min_bin_value();  // the spgemm_debug_min_bin setting
 BinCaps bin_caps(int which);  // 0: symbolic, 1: numeric / merge / masked product

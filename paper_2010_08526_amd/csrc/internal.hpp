@@ -77,7 +77,7 @@ inline int64_t hv_item_cap(int64_t ncol, int64_t P) {
 struct WsHeader {
   int32_t status;  // 0 = ok; nonzero = a device-side check failed
   int32_t pad0;
-  uint64_t clean_tag;  // nonzero iff the heavy accumulator region is known to be all zero
+  uint64_t clean_tag;  // zero_region_tag of the accumulator region known to be all zero; 0 = none
   int32_t bin_count[kNumBins];
   int32_t items;        // heavy items listed for the current chunk
   int32_t item_cursor;  // work-queue position over those items
@@ -131,6 +131,30 @@ struct WsLayout {
   size_t total = 0;
   int64_t slots = 0, nseg = 0, ncol = 0, m = 0;
 };
+
+// Zero-filled accumulator regions.  The global heavy path (product and
+// merge) and the masked product keep their dense accumulators all zero
+// between calls (each call clears what it used), so a call may skip the fill
+// when the header's clean_tag says the region it is about to use was left
+// zero by a call with the same region.  The tag names the region: its kind,
+// offsets, slot count and rows.  Every call that initialises the header
+// passes the tag of its own region (or 0 if it has none, which clears the
+// tag: its layout may put other data there); kKeepAnyTag is for calls that
+// write nothing but the header.
+constexpr uint64_t kKeepAnyTag = ~0ull;
+enum : uint64_t { kTagProduct = 0x70726f64ull, kTagMasked = 0x6d787479ull };
+inline uint64_t zero_region_tag(uint64_t kind, const WsLayout &L) {
+  if (L.slots <= 0 || L.heavy_vals == 0) return 0;
+  uint64_t t = kind;
+  const uint64_t parts[6] = {(uint64_t)L.heavy_vals, (uint64_t)L.heavy_flags, (uint64_t)L.heavy_segcnt,
+                             (uint64_t)L.slots,      (uint64_t)L.m,           (uint64_t)L.nseg};
+  for (uint64_t x : parts) {
+    t = (t ^ x) * 0x9e3779b97f4a7c15ull;
+    t ^= t >> 29;
+  }
+  t |= 1;  // never 0 (no region)
+  return t == kKeepAnyTag ? t - 2 : t;
+}
 
 // Computes the layout; returns SPGEMM_OK or an error status.
 int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t c1, int32_t n_layers,

@@ -403,7 +403,7 @@ __device__ __forceinline__ void traverse_merge(const PartDesc *P, int nparts, in
 // ============================================================================
 // Small kernels: header init, fills.
 // ============================================================================
-__global__ void k_init_header(WsHeader *h, int keep_clean, int keep_status = 0, int keep_left = 0) {
+__global__ void k_init_header(WsHeader *h, uint64_t keep_tag, int keep_status = 0, int keep_left = 0) {
   if (threadIdx.x == 0) {
     if (!keep_status) h->status = 0;
     if (!keep_left) h->left_tag = 0;  // every other operation may overwrite the slabbed copy
@@ -414,7 +414,7 @@ __global__ void k_init_header(WsHeader *h, int keep_clean, int keep_status = 0, 
     h->item_cursor = 0;
     h->nwide = 0;
     h->wide_cursor = 0;
-    if (!keep_clean) h->clean_tag = 0;
+    if (keep_tag != kKeepAnyTag && h->clean_tag != keep_tag) h->clean_tag = 0;
   }
 }
 
@@ -2204,8 +2204,8 @@ int launch_set_tag(WsHeader *h, uint64_t tag, hipStream_t st) {
   return SPGEMM_OK;
 }
 
-int launch_init_header(WsHeader *h, int keep_clean, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, h, keep_clean, 0);
+int launch_init_header(WsHeader *h, uint64_t keep_tag, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, h, keep_tag, 0);
   LAUNCHCHK();
   return SPGEMM_OK;
 }
@@ -2405,7 +2405,7 @@ static int symbolic_pass(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
                          hipStream_t st, bool sync, bool keep_status = false) {
   WsHeader *hdr = (WsHeader *)ws;
   int32_t *bins = (int32_t *)(ws + L.bins);
-  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, 0, keep_status ? 1 : 0);
+  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, (uint64_t)0, keep_status ? 1 : 0);
   LAUNCHCHK();
   const int64_t per_block = 4 * kBinColsPerWave;
   {
@@ -2441,9 +2441,6 @@ static int symbolic_pass(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
   return SPGEMM_OK;
 }
 
-static uint64_t clean_tag_of(const WsLayout &L) {
-  return 0x5eed0000f00dull ^ ((uint64_t)L.slots << 40) ^ (uint64_t)L.m ^ ((uint64_t)L.heavy_vals << 20);
-}
 
 // Numeric-style pass (product or merge) once the bins are filled.  cnt[b]
 // < 0 means the count is only on the device (no host synchronization);
@@ -2487,7 +2484,7 @@ static int accumulate_pass(const Src &src, const int *cnt, const WsHeader &h, co
     double *vals = (double *)(ws + L.heavy_vals);
     uint8_t *flags = (uint8_t *)(ws + L.heavy_flags);
     int64_t *segcnt = (int64_t *)(ws + L.heavy_segcnt);
-    const uint64_t tag = clean_tag_of(L);
+    const uint64_t tag = zero_region_tag(kTagProduct, L);
     if (h.clean_tag != tag) {
       const int64_t bytes = (int64_t)(L.heavy_segcnt - L.heavy_vals);
       hipLaunchKernelGGL(k_fill_zero, dim3(4 * device_cus()), dim3(256), 0, st, (uint4 *)(ws + L.heavy_vals), bytes / 16);
@@ -2519,7 +2516,8 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
                          char *ws, hipStream_t st, bool sync, bool keep_status = false) {
   WsHeader *hdr = (WsHeader *)ws;
   int32_t *bins = (int32_t *)(ws + L.bins);
-  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, 1, keep_status ? 1 : 0, 1);
+  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, zero_region_tag(kTagProduct, L),
+                     keep_status ? 1 : 0, 1);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_bin<false>, dim3(grid_of(ncol, 4 * kBinColsPerWave)), dim3(256), 0, st, A->colptr, B->colptr,
                      B->rowidx, c0, ncol, klo, khi, (int64_t)A->ncols, A->nrows, c_colptr, (int64_t *)nullptr,
@@ -2621,7 +2619,7 @@ static int merge_typed(const spgemm_csc *parts, int32_t n_parts, const int64_t *
   WsHeader *hdr = (WsHeader *)ws;
   int32_t *bins = (int32_t *)(ws + L.bins);
   PartDesc *pd = (PartDesc *)(ws + L.parts);
-  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, 1, 0);
+  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, zero_region_tag(kTagProduct, L), 0);
   LAUNCHCHK();
   for (int c = 0; c < n_parts; c += kWave) {
     PartsChunk hc;
@@ -2728,7 +2726,7 @@ int spgemm_symbolic(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_
   hipStream_t s = (hipStream_t)stream;
   char *w = (char *)ws;
   if (ncol == 0) {
-    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)w, 0, 0);
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)w, (uint64_t)0, 0);
     LAUNCHCHK();
     return SPGEMM_OK;
   }
@@ -2737,7 +2735,7 @@ int spgemm_symbolic(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_
   const int64_t width = (kdim + n_layers - 1) / n_layers;
   for (int32_t l = 0; l < n_layers; l++) {
     const int64_t klo = std::min<int64_t>(kdim, (int64_t)l * width), khi = std::min<int64_t>(kdim, klo + width);
-    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)w, 0, 0);
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)w, (uint64_t)0, 0);
     LAUNCHCHK();
     spgemm_csc Bl;
     int rc = build_layer<float>(B, c0, ncol, klo, khi, kdim, false, L, w, s, &Bl);
@@ -2766,7 +2764,7 @@ int spgemm_numeric(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t
   const int64_t ncol = c1 - c0;
   if (ncol > 0 && !c_colptr) return SPGEMM_E_INVAL;
   if (ncol == 0) {
-    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, (hipStream_t)stream, (WsHeader *)ws, 1, 0);
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, (hipStream_t)stream, (WsHeader *)ws, kKeepAnyTag, 0);
     LAUNCHCHK();
     return SPGEMM_OK;
   }
@@ -2775,7 +2773,8 @@ int spgemm_numeric(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t
   const int64_t klo = std::min<int64_t>(kdim, (int64_t)layer * width), khi = std::min<int64_t>(kdim, klo + width);
   hipStream_t s = (hipStream_t)stream;
   if (n_layers > 1) {  // the layer's share of B first, then the passes over it
-    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)ws, 1, 0, 1);
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)ws, zero_region_tag(kTagProduct, L), 0,
+                       1);
     LAUNCHCHK();
     spgemm_csc Bl;
     if (A->dtype == SPGEMM_F32) {
@@ -2810,7 +2809,7 @@ int spgemm_merge(const spgemm_csc *parts, int32_t n_parts, const int64_t *c_colp
   if (st) return st;
   if (L.ncol > 0 && !c_colptr) return SPGEMM_E_INVAL;
   if (L.ncol == 0) {
-    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, (hipStream_t)stream, (WsHeader *)ws, 1, 0);
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, (hipStream_t)stream, (WsHeader *)ws, kKeepAnyTag, 0);
     LAUNCHCHK();
     return SPGEMM_OK;
   }
@@ -2948,7 +2947,7 @@ int spgemm_ws_status_code(void *ws, void *stream, int32_t *code_host) {
   if (rc) return rc;
   if (h.status != 0) {
     if (code_host) *code_host = h.status;
-    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)ws, 1, 0);
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)ws, kKeepAnyTag, 0);
     return SPGEMM_E_DEVICE;
   }
   return SPGEMM_OK;

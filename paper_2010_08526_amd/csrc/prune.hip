@@ -297,7 +297,7 @@ template <typename VT>
 int prune_typed(const spgemm_csc *C, double thr, int64_t k, int64_t *out_colptr, int32_t *out_rowidx,
                 void *out_values, const WsLayout &L, char *ws, hipStream_t st) {
   WsHeader *hdr = (WsHeader *)ws;
-  int rc = launch_init_header(hdr, 0, st);
+  int rc = launch_init_header(hdr, (uint64_t)0, st);
   if (rc) return rc;
   const int64_t n = C->ncols;
   int64_t *cnt = (int64_t *)(ws + L.pr_cnt);

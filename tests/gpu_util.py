@@ -36,6 +36,46 @@ def assert_matches(C, P, dtype, what=""):
     assert np.all((np.diff(ri) > 0) | (np.diff(np.repeat(np.arange(cp.size - 1), np.diff(cp))) != 0))
 
 
+def sorted_values(C, values):
+    """Values aligned with C's stored entries (device or host), put in the
+    per-column row order of host_sorted(C)."""
+    cp = C.colptr.cpu().numpy().astype(np.int64)
+    cp = cp - cp[0]
+    ri = C.rowidx.cpu().numpy()
+    col = np.repeat(np.arange(cp.size - 1), np.diff(cp))
+    order = np.lexsort((ri, col))
+    v = values.cpu().numpy() if isinstance(values, torch.Tensor) else np.asarray(values)
+    return v.astype(np.float64)[order]
+
+
+def grads_and_bounds(A, B, P, dc):
+    """Oracle gradients for dC = dc on P(C) (values in the oracle's row
+    order), and per gradient entry the sum of |terms| (the scale of the
+    float64 and float32 bounds)."""
+    dCh = oracle.Mat(P.nrows, P.ncols, P.colptr, P.rowidx, dc)
+    gA, gB = oracle.grad_a(A, B, dCh), oracle.grad_b(A, B, dCh)
+    adC = oracle.Mat(P.nrows, P.ncols, P.colptr, P.rowidx, np.abs(dc))
+    Aa, Ba = oracle.as_mat(A), oracle.as_mat(B)
+    sA = oracle.grad_a(Aa, oracle.Mat(Ba.nrows, Ba.ncols, Ba.colptr, Ba.rowidx, np.abs(Ba.values)), adC)
+    sB = oracle.grad_b(oracle.Mat(Aa.nrows, Aa.ncols, Aa.colptr, Aa.rowidx, np.abs(Aa.values)), Ba, adC)
+    return gA, gB, sA, sB
+
+
+def assert_grads(A, B, C, dC, dA, dB, dtype, what=""):
+    """Device gradients dA, dB of the loss whose dC (device values aligned
+    with C's entries) the device used, against the oracle's direct formulas
+    on the same dC: every entry within TOL[dtype] * sum |terms|.  C's
+    structure must already match the oracle's product."""
+    P = oracle.spgemm(A, B)
+    gA, gB, sA, sB = grads_and_bounds(A, B, P, sorted_values(C, dC))
+    tol = TOL[dtype]
+    dA = dA.double().cpu().numpy()
+    dB = dB.double().cpu().numpy()
+    ea, eb = np.abs(dA - gA), np.abs(dB - gB)
+    assert np.all(ea <= tol * sA + 1e-300), f"{what} dA: worst {float((ea / np.maximum(sA, 1e-300)).max()):.3e}"
+    assert np.all(eb <= tol * sB + 1e-300), f"{what} dB: worst {float((eb / np.maximum(sB, 1e-300)).max()):.3e}"
+
+
 def to_dev(M, device="cuda"):
     return M.to(device)
 
