@@ -244,6 +244,25 @@ int spgemm_batched_forward(const spgemm_csc *A, const spgemm_csc *B, int64_t nnz
                            int64_t *nnz_out, int64_t *c_colptr, int32_t *c_rowidx, void *c_values, void *ws,
                            size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as spgemm_batched_forward, with no workspace argument.  Its
+ * scratch is a fixed device array of SPGEMM_NOALLOC_SCRATCH_BYTES inside the
+ * library (one per GPU, held until the process ends); the call allocates
+ * nothing and calls no allocating routine.  Inputs whose
+ * SPGEMM_OP_BATCHED_FORWARD workspace exceeds that size are refused with
+ * SPGEMM_E_WORKSPACE before anything is launched.  Every call on one GPU
+ * shares that GPU's array and initialises what it reads, so calls that
+ * overlap on one GPU (different streams, or host threads) race and must not
+ * be issued; calls in sequence on one stream are safe.  `stream` must
+ * belong to the current device.  Device-side failures are recorded in the
+ * array's status word, which this entry point cannot return later: check
+ * outputs (e.g. the last column pointer against nnz_cap) instead. */
+#define SPGEMM_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int spgemm_batched_forward_noalloc(const spgemm_csc *A, const spgemm_csc *B, int64_t nnz_cap, int64_t *flops_out,
+                                   int64_t *nnz_out, int64_t *c_colptr, int32_t *c_rowidx, void *c_values,
+                                   void *stream);
+
 /* spgemm_masked_xty with no host synchronization (graph-capturable, same
  * workspace).  Columns of Y above the largest LDS table are not supported
  * here and are reported through the workspace status. */

@@ -55,6 +55,22 @@ def batch_pack(instances, device="cuda", stream=None):
     return CSC(rows, cols, cp, ri[:nnz], None if v is None else v[:nnz]), offs.reshape(count + 1, 3)
 
 
+# Scratch of the allocation-free forward (SPGEMM_NOALLOC_SCRATCH_BYTES in spgemm.h).
+NOALLOC_SCRATCH_BYTES = 64 << 20
+_lib.spgemm_batched_forward_noalloc.argtypes = [ctypes.POINTER(spgemm_csc), ctypes.POINTER(spgemm_csc),
+                                                ctypes.c_int64] + [ctypes.c_void_p] * 6
+
+
+def batched_forward_noalloc(A, B, nnz_cap: int, flops, nnz, colptr, rowidx, values, stream=None):
+    """spgemm_batched_forward without a workspace argument: the library's
+    fixed per-device scratch serves it (inputs whose workspace would exceed
+    NOALLOC_SCRATCH_BYTES are refused).  Outputs are the caller's; the call
+    allocates nothing."""
+    _check(_lib.spgemm_batched_forward_noalloc(ctypes.byref(desc(A)), ctypes.byref(desc(B)), int(nnz_cap),
+                                               _ptr(flops), _ptr(nnz), _ptr(colptr), _ptr(rowidx), _ptr(values),
+                                               _stream(stream)), "spgemm_batched_forward_noalloc")
+
+
 class BatchedEngine:
     """Forward (and the fused backward) of a packed product, host-sync free.
 

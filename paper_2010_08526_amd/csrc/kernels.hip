@@ -2700,6 +2700,35 @@ static int merge_typed(const spgemm_csc *parts, int32_t n_parts, const int64_t *
   return SPGEMM_OK;
 }
 
+// Scratch of the allocation-free entry point: one fixed array per device
+// (every module load gives each GPU its own copy), shared by every call on
+// that device, so calls that overlap on one GPU race.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in):
+// the device address comes from hipGetSymbolAddress, taken once per device
+// with that device current and kept per device.
+static __device__ __align__(256) unsigned char scratch[SPGEMM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+}  // namespace
+
+static int noalloc_scratch(void **out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return SPGEMM_E_INVAL;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || reinterpret_cast<uintptr_t>(p) % 256) return SPGEMM_E_WORKSPACE;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SPGEMM_OK;
+}
+
 static_assert(sizeof(PartDesc) == kPartDescBytes, "part descriptor size");
 static_assert(sizeof(WsHeader) <= 2048, "header too large");
 
@@ -2865,6 +2894,25 @@ int spgemm_batched_forward(const spgemm_csc *A, const spgemm_csc *B, int64_t nnz
   if (A->dtype == SPGEMM_F32)
     return numeric_typed<float>(A, B, 0, n, 0, A->ncols, c_colptr, c_rowidx, c_values, L, w, s, false, true);
   return numeric_typed<double>(A, B, 0, n, 0, A->ncols, c_colptr, c_rowidx, c_values, L, w, s, false, true);
+}
+
+int spgemm_batched_forward_noalloc(const spgemm_csc *A, const spgemm_csc *B, int64_t nnz_cap, int64_t *flops_out,
+                                   int64_t *nnz_out, int64_t *c_colptr, int32_t *c_rowidx, void *c_values,
+                                   void *stream) {
+  int st = check_csc(A, true);
+  if (!st) st = check_csc(B, true);
+  if (st) return st;
+  if (A->dtype != B->dtype) return SPGEMM_E_DTYPE;
+  if (A->ncols != B->nrows) return SPGEMM_E_SHAPE;
+  WsLayout L;
+  st = ws_layout(SPGEMM_OP_BATCHED_FORWARD, A, B, 0, B->ncols, 1, &L);
+  if (st) return st;
+  if (L.total > (size_t)SPGEMM_NOALLOC_SCRATCH_BYTES) return SPGEMM_E_WORKSPACE;  // before any HIP call
+  void *ws = nullptr;
+  st = noalloc_scratch(&ws);
+  if (st) return st;
+  return spgemm_batched_forward(A, B, nnz_cap, flops_out, nnz_out, c_colptr, c_rowidx, c_values, ws,
+                                (size_t)SPGEMM_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 int spgemm_set_bin_caps(int32_t which, const int64_t *caps_host) {

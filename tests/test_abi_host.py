@@ -289,3 +289,23 @@ def test_prune_binding_rejects_pattern_only():
     M = S.CSC(4, 2, torch.zeros(3, dtype=torch.int64), torch.zeros(0, dtype=torch.int32), None)
     with pytest.raises(ValueError):
         S.prune_topk(M, 0.0, 1)
+
+
+def test_noalloc_forward_refuses_inputs_beyond_its_scratch():
+    """The allocation-free forward checks its fixed scratch size on the host,
+    before any HIP call: a product whose workspace would exceed it is
+    refused; shape and dtype errors come first."""
+    import paper_2010_08526_amd.batched as Bt
+    lib = S._lib
+    n = 4_000_000  # 24 bytes of bin lists per column alone exceed the scratch
+    A, B = FakeCSC(n, n, 5), FakeCSC(n, n, 5)
+    need = ctypes.c_size_t()
+    assert lib.spgemm_workspace_size(S.OP_BATCHED_FORWARD, ctypes.byref(A.d), ctypes.byref(B.d), 0, n, 1,
+                                     ctypes.byref(need)) == S.OK
+    assert need.value > Bt.NOALLOC_SCRATCH_BYTES
+    r = lib.spgemm_batched_forward_noalloc(ctypes.byref(A.d), ctypes.byref(B.d), 10, 0x1, 0x1, 0x1, 0x1, 0x1, None)
+    assert r == S.E_WORKSPACE
+    assert lib.spgemm_batched_forward_noalloc(ctypes.byref(A.d), ctypes.byref(FakeCSC(n + 1, n, 5).d), 10, 0x1, 0x1,
+                                              0x1, 0x1, 0x1, None) == S.E_SHAPE
+    assert lib.spgemm_batched_forward_noalloc(ctypes.byref(A.d), ctypes.byref(FakeCSC(n, n, 5, dtype=S.F64).d), 10,
+                                              0x1, 0x1, 0x1, 0x1, 0x1, None) == S.E_DTYPE
