@@ -68,7 +68,8 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
       const int64_t P = num_slabs(A->nrows);
       // columns of A one call reads: one layer of ceil(k / n_layers) columns
       const int64_t kcols = (A->ncols + n_layers - 1) / n_layers;
-      const bool slabs = numeric && A->nrows > kNumCap[kNumBins - 2] && P <= kMaxSlabs &&
+      // (entries of the slabbed copy are addressed with 32-bit indices)
+      const bool slabs = numeric && A->nrows > kNumCap[kNumBins - 2] && P <= kMaxSlabs && A->nnz <= INT32_MAX &&
                          sizeof(int32_t) * (uint64_t)(P + 1) * (uint64_t)kcols <= kMaxSlabOffBytes;
       if (slabs) {
         // the slabbed copy of A depends only on A and the layer: it comes
@@ -79,10 +80,8 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
         off = align_up(off + sizeof(int32_t) * (size_t)(L->P + 1) * (size_t)kcols);
         L->slab_pack = off;
         off = align_up(off + sizeof(uint64_t) * (size_t)L->P * (size_t)kcols);
-        L->slab_ri = off;
-        off = align_up(off + sizeof(int32_t) * (size_t)A->nnz);
-        L->slab_v = off;
-        off = align_up(off + sizeof(double) * (size_t)A->nnz);
+        L->slab_ent = off;
+        off = align_up(off + kSlabEntBytes[A->dtype == SPGEMM_F64 ? 1 : 0] * (size_t)A->nnz);
       }
       L->bins = off;
       off = align_up(off + sizeof(int32_t) * kNumBins * (size_t)ncol);

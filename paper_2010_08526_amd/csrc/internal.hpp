@@ -59,6 +59,7 @@ constexpr int kHvSlots = 2560;
 constexpr int kHvCap = kHvSlots / 2;
 constexpr int64_t kHvWideT = 1024;
 constexpr uint64_t kHvItemBytes = uint64_t(64) << 20;  // item list of one chunk of heavy columns
+constexpr size_t kSlabEntBytes[2] = {8, 16};  // one slabbed entry of A (row and value): float32, float64
 constexpr int64_t kMbBucket = int64_t(1) << 28;  // merge: entries bucketed at once (heavy columns)
 
 inline int64_t num_slabs(int64_t m) { return (m + kSlabRows - 1) / kSlabRows; }
@@ -109,8 +110,9 @@ struct WsLayout {
   size_t scan = 0;        // int64 block sums
   size_t parts = 0;       // merge: part descriptors
   size_t slab_off = 0;    // numeric: int32 [kcols][P+1] slab offsets of the left operand
-  size_t slab_ri = 0;     // numeric: int32 [nnzA] slabbed rows
-  size_t slab_v = 0;      // numeric: 8-byte [nnzA] slabbed values
+  size_t slab_ent = 0;    // numeric: [nnzA] slabbed entries of A (row and value side by side)
+  size_t slab_ri = 0;     // merge: int32 [mb_cap] bucketed rows
+  size_t slab_v = 0;      // merge: 8-byte [mb_cap] bucketed values
   size_t slab_pack = 0;   // numeric: uint64 [P][kcols] slab segments, slab-major (start << kSegLenBits | len)
   size_t hv_cur = 0;      // numeric: int32 [ncol] output cursor per heavy column
   size_t hv_items = 0;    // numeric: uint32 [hv_item_cap] heavy item slots of one chunk

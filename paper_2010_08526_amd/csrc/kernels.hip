@@ -940,10 +940,26 @@ __global__ void k_left_set(WsHeader *h, const int32_t *heavy_count) {
   if (threadIdx.x == 0 && *heavy_count != 0) h->left_tag = h->status == 0 ? (h->left_new | 1ull) : 0ull;
 }
 
+// One entry of the slabbed copy of the left operand: row and value side by
+// side, so that one load fetches both.
+template <class VT>
+struct SlabEnt;
+template <>
+struct __align__(8) SlabEnt<float> {
+  int32_t row;
+  float v;
+};
+template <>
+struct __align__(16) SlabEnt<double> {
+  int32_t row;
+  int32_t pad;
+  double v;
+};
+
 template <class VT>
 __global__ __launch_bounds__(256) void k_slab_split(const int64_t *Acp, const int32_t *Ari, const VT *Av,
                                                     int64_t klo, int64_t khi, int64_t m, int P, int32_t *soff,
-                                                    int32_t *s_ri, VT *s_v, const int32_t *heavy_count,
+                                                    SlabEnt<VT> *s_ent, const int32_t *heavy_count,
                                                     int32_t *status, const WsHeader *hdr) {
   __shared__ int s_hist[4][kMaxSlabs + 1];
   const int w = threadIdx.x / kWave, l = lane();
@@ -980,8 +996,10 @@ __global__ __launch_bounds__(256) void k_slab_split(const int64_t *Acp, const in
     const int32_t row = Ari[p];
     const uint32_t sl = min((uint32_t)row >> kSlabShift, (uint32_t)(P - 1));
     const int pos = atomicAdd(&h[sl], 1);
-    s_ri[a0 + pos] = row;
-    s_v[a0 + pos] = Av[p];
+    SlabEnt<VT> e;
+    e.row = row;
+    e.v = Av[p];
+    s_ent[a0 + pos] = e;
   }
 }
 
@@ -1121,8 +1139,7 @@ __global__ __launch_bounds__(kHvPlanThreads) void k_hv_plan(const int64_t *Bcp, 
 template <class VT>
 struct HvArgs {
   const int64_t *Acp;
-  const int32_t *Ari;  // slabbed rows
-  const VT *Av;        // slabbed values
+  const SlabEnt<VT> *ent;  // slabbed entries (fewer than 2^31)
   const int64_t *Bcp;
   const int32_t *Bri;
   const VT *Bv;
@@ -1132,15 +1149,18 @@ struct HvArgs {
 };
 
 // Visits the terms A(i,k) B(k,col) of k in B(:,col) = entries [pbeg, pend)
-// of B with i in slabs [sa, sb): ins(i, value).  Segment bounds are checked once per segment (the
-// element reads need no check); returns nonzero if an index was out of
-// range (that segment is skipped).  The nw waves of the workgroup split the
-// chunks of 64 entries of B(:,col) when there are at least cs_min*nw of them,
-// else they split the rounds of every chunk.  Short segments are flattened
-// into rounds of 64 elements (owner of each element from a ballot, or an LDS
-// marker and a max-scan when a segment starts inside the round), kPipe
-// rounds' gathers in flight; segments of kLongSeg or more elements are
-// streamed by the whole wave.
+// of B with i in slabs [sa, sb): ins(i, value).  Segment bounds are checked
+// once per segment (the element reads need no check); returns nonzero if an
+// index was out of range (that segment is skipped).  The nw waves of the
+// workgroup split the chunks of 64 entries of B(:,col) when there are at
+// least cs_min*nw of them, else they split the rounds of every chunk.
+// Short segments are flattened into rounds of 64 elements: the nonempty
+// ones are listed in order (entry base minus exclusive prefix, B value), and
+// one 64-bit word per round marks the positions where a segment starts, so
+// the owner of element e is (segments starting before the round) + (starts
+// in the round at or below e) - 1: a ballot, a population count and a mask
+// count, with no scan.  kHvPipe rounds' gathers are kept in flight;
+// segments of kLongSeg or more elements are streamed by the whole wave.
 constexpr int kHvPipe = 4;
 constexpr int kHvVec = 4;
 constexpr int kHvBlk = kWave * kHvVec;
@@ -1182,11 +1202,32 @@ __device__ __forceinline__ void hv_pre_seg(const HvArgs<VT> &a, int sa, int sb, 
   }
 }
 
+// Per-wave scratch of the traversal: the start mask of 64 consecutive
+// rounds and the chunk's nonempty short segments.
+template <class VT>
+struct SegInfo;
+template <>
+struct __align__(8) SegInfo<float> {
+  uint32_t offm;  // entry index of the segment's first element minus its exclusive prefix (mod 2^32)
+  float b;        // B(k,j)
+};
+template <>
+struct __align__(16) SegInfo<double> {
+  uint32_t offm;
+  uint32_t pad;
+  double b;
+};
+template <class VT>
+struct HvScratch {
+  uint64_t rmask[kWave];
+  SegInfo<VT> info[kWave];
+};
+
 // pre: the wave's first chunk loaded ahead (same pbeg, pend, sa, sb, w, nw,
 // cs_min), or nullptr.
 template <class VT, class Ins>
 __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t pbeg, int64_t pend, int sa, int sb, int w,
-                                           int nw, int cs_min, SegScratch &sc, const HvPre<VT> *pre,
+                                           int nw, int cs_min, HvScratch<VT> &sc, const HvPre<VT> *pre,
                                            Ins &&ins) {
   const int l = lane();
   const int nchunk = (int)((pend - pbeg + kWave - 1) / kWave);
@@ -1242,56 +1283,58 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t pbeg, in
     const int excl = incl - ls;
     const int total = readlane(incl, 63);
     if (total > 0) {
-      sc.off[l] = off - excl;
-      sc.scale[l] = b;
-      wave_sync();
+      const uint64_t nz = __ballot(ls > 0);
+      if (ls > 0) {
+        SegInfo<VT> si;
+        si.offm = (uint32_t)(uint64_t)(off - excl);
+        si.b = bv;
+        sc.info[mbcnt(nz)] = si;
+      }
+      const int nround = (total + kWave - 1) / kWave;
       int r0 = (r_rank - units) % r_stride;
       if (r0 < 0) r0 += r_stride;
-      for (int r = r0; r * kWave < total; r += kHvPipe * r_stride) {
-        int own_[kHvPipe];
+      for (int g = 0; g < nround; g += kWave) {  // 64 rounds per start-mask refill
+        sc.rmask[l] = 0ull;
+        wave_sync();
+        const int rr = (excl >> 6) - g;
+        if (ls > 0 && rr >= 0 && rr < kWave) atomicOr((unsigned long long *)&sc.rmask[rr], 1ull << (excl & 63));
+        wave_sync();
+        const int gend = min(nround, g + kWave);
+        int rf = (r0 - g) % r_stride;
+        if (rf < 0) rf += r_stride;
+        for (int r = g + rf; r < gend; r += kHvPipe * r_stride) {
+          int own_[kHvPipe];
 #pragma unroll
-        for (int u = 0; u < kHvPipe; u++) {
-          const int fb = (r + u * r_stride) * kWave;
-          own_[u] = -1;
-          if (fb < total) {
-            const int last = min(fb + kWave - 1, total - 1);
-            const uint64_t started = __ballot(ls > 0 && excl <= fb);
-            const int carry = started ? 64 - __clzll((long long)started) : 0;
-            int own;
-            if (__ballot(ls > 0 && excl <= last) == started) {
-              own = carry;
-            } else {
-              if (ls > 0 && excl > fb && excl < fb + kWave) sc.mark[excl - fb] = l + 1;
-              wave_sync();
-              const int mk = sc.mark[l];
-              sc.mark[l] = 0;
-              own = max(wave_incl_max(mk), carry);
-              wave_sync();
+          for (int u = 0; u < kHvPipe; u++) {
+            const int ru = r + u * r_stride;
+            own_[u] = -1;
+            if (ru < gend) {
+              const int fb = ru * kWave;
+              const uint64_t m = sc.rmask[ru - g];
+              const int carry = __popcll(__ballot(ls > 0 && excl < fb));
+              const int o = carry + mbcnt(m) + (int)((m >> l) & 1ull) - 1;
+              if (fb + l < total) own_[u] = o;
             }
-            if (fb + l < total) own_[u] = own - 1;
           }
-        }
-        // gathers only; the loaded values are used after every load is issued
-        int64_t q_[kHvPipe];
+          SegInfo<VT> inf_[kHvPipe];
 #pragma unroll
-        for (int u = 0; u < kHvPipe; u++) q_[u] = sc.off[max(own_[u], 0)] + (r + u * r_stride) * kWave + l;
-        int32_t row_[kHvPipe];
-        VT raw_[kHvPipe];
+          for (int u = 0; u < kHvPipe; u++)
+            if (own_[u] >= 0) inf_[u] = sc.info[own_[u]];
+          // gathers only; the loaded values are used after every load is issued
+          SlabEnt<VT> e_[kHvPipe];
 #pragma unroll
-        for (int u = 0; u < kHvPipe; u++) {
-          row_[u] = 0;
-          raw_[u] = VT(0);
-          if (own_[u] >= 0) {
-            row_[u] = a.Ari[q_[u]];
-            raw_[u] = a.Av[q_[u]];
+          for (int u = 0; u < kHvPipe; u++) {
+            e_[u].row = 0;
+            e_[u].v = VT(0);
+            if (own_[u] >= 0) e_[u] = a.ent[inf_[u].offm + (uint32_t)((r + u * r_stride) * kWave + l)];
           }
-        }
 #pragma unroll
-        for (int u = 0; u < kHvPipe; u++)
-          if (own_[u] >= 0) ins(opaque(row_[u]), (double)opaque(raw_[u]) * sc.scale[own_[u]]);
+          for (int u = 0; u < kHvPipe; u++)
+            if (own_[u] >= 0) ins(opaque(e_[u].row), (double)opaque(e_[u].v) * (double)inf_[u].b);
+        }
+        wave_sync();
       }
-      units += (total + kWave - 1) / kWave;
-      wave_sync();
+      units += nround;
     }
     uint64_t lm = __ballot(lg);
     while (lm) {
@@ -1305,21 +1348,17 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t pbeg, in
       if (b0 < 0) b0 += r_stride;
       for (int blk = b0; blk < nblk; blk += r_stride) {
         const int e0 = blk * kHvBlk + l;
-        int32_t row[kHvVec];
-        VT raw[kHvVec];
+        SlabEnt<VT> ev[kHvVec];
 #pragma unroll
         for (int t = 0; t < kHvVec; t++) {
           const int e = e0 + t * kWave;
-          row[t] = 0;
-          raw[t] = VT(0);
-          if (e < sn) {
-            row[t] = a.Ari[so + e];
-            raw[t] = a.Av[so + e];
-          }
+          ev[t].row = 0;
+          ev[t].v = VT(0);
+          if (e < sn) ev[t] = a.ent[so + e];
         }
 #pragma unroll
         for (int t = 0; t < kHvVec; t++)
-          if (e0 + t * kWave < sn) ins(opaque(row[t]), (double)opaque(raw[t]) * sbv);
+          if (e0 + t * kWave < sn) ins(opaque(ev[t].row), (double)opaque(ev[t].v) * sbv);
       }
       units += nblk;
     }
@@ -1356,8 +1395,9 @@ struct HvProductSrc {
     hv_pre_b<VT>(a, lo, hi, w, nw, kCsMin, pre);
   }
   __device__ __forceinline__ void pre_seg(int sa, int sb, Pre &pre) const { hv_pre_seg<VT>(a, sa, sb, pre); }
+  using Scratch = HvScratch<VT>;
   template <class Ins>
-  __device__ __forceinline__ int visit(int64_t lo, int64_t hi, int sa, int sb, int w, int nw, SegScratch &sc,
+  __device__ __forceinline__ int visit(int64_t lo, int64_t hi, int sa, int sb, int w, int nw, Scratch &sc,
                                        const Pre &pre, Ins &&ins) const {
     return hv_traverse<VT>(a, lo, hi, sa, sb, w, nw, kCsMin, sc, &pre, ins);
   }
@@ -1378,7 +1418,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
   static_assert(kWords <= kHvThreads, "one bitmap word per thread");
   static_assert(kHvSlots * 12 <= kSlabRows * 8, "hash table fits the dense array");
   __shared__ __align__(16) unsigned char s_tab[kSlabRows * 8 + kSlabRows / 8];
-  __shared__ SegScratch s_sc[NW];
+  __shared__ typename Src::Scratch s_sc[NW];
   __shared__ int s_batch;
   __shared__ uint32_t s_e[kWave];
   __shared__ int32_t s_jj[kWave];
@@ -1392,11 +1432,15 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
   hc = min(hc, max(nheavy - h0, (int64_t)0));  // the device count bounds a chunk sized on the host
   const int64_t nb = (hc + kWave - 1) / kWave;
   const int64_t nbatch = nb * P;
-  s_sc[w].mark[l] = 0;
   double *acc = (double *)s_tab;
   uint32_t *bits = (uint32_t *)(s_tab + kSlabRows * 8);
-  int32_t *keys = (int32_t *)s_tab;
+  int32_t *keys = (int32_t *)s_tab;  // hash items: key = row + 1, 0 = free
   double *vals = (double *)(s_tab + kHvSlots * 4);
+  // The table is all zero between items: cleared once here, and every
+  // compaction clears what the item wrote (dense rows with their bitmap
+  // bits, occupied hash slots), so no item starts with a clearing pass.
+  for (int q = threadIdx.x; q < (int)(sizeof(s_tab) / 16); q += kHvThreads)
+    reinterpret_cast<uint4 *>(s_tab)[q] = make_uint4(0u, 0u, 0u, 0u);
   for (;;) {
     __syncthreads();  // the previous batch's s_batch, s_e, s_jj, s_mask are no longer read
     if (threadIdx.x == 0) s_batch = atomicAdd(&hdr->item_cursor, 1);
@@ -1466,12 +1510,9 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
       const int64_t lo = s_lo[j], hi = s_hi[j];
       int bad;
       int c = 0;
+      uint32_t word = 0u;  // dense: this lane's bitmap word of the wave's rows
       const uint32_t rb = (uint32_t)t << kSlabShift;
       if (dense) {
-        for (int q = threadIdx.x; q < (int)kSlabRows / 2; q += kHvThreads)  // 16-byte stores
-          reinterpret_cast<double2 *>(acc)[q] = make_double2(0.0, 0.0);
-        if (threadIdx.x < kWords) bits[threadIdx.x] = 0u;
-        __syncthreads();
         int outside = 0;
         bad = src.visit(lo, hi, t, sb0, w, NW, s_sc[w], pre, [&](int32_t row, double v) {
           const uint32_t r = (uint32_t)row - rb;
@@ -1486,61 +1527,66 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
         __syncthreads();
         // wave w owns rows [w * kRowsPerWave, +kRowsPerWave): bitmap words
         // w * kWordsPerWave + lane
-        c = l < kWordsPerWave ? __popc(bits[w * kWordsPerWave + l]) : 0;
+        if (l < kWordsPerWave) word = bits[w * kWordsPerWave + l];
+        c = __popc(word);
       } else {
-        for (int q = threadIdx.x; q < kHvSlots / 4; q += kHvThreads)  // 16-byte stores
-          reinterpret_cast<int4 *>(keys)[q] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
-        for (int q = threadIdx.x; q < kHvSlots / 2; q += kHvThreads)
-          reinterpret_cast<double2 *>(vals)[q] = make_double2(0.0, 0.0);
-        __syncthreads();
         bad = src.visit(lo, hi, t, sb0, w, NW, s_sc[w], pre, [&](int32_t row, double v) {
-          ht_accumulate(keys, vals, kHvSlots, row, v);
+          ht_accumulate_z(keys, vals, kHvSlots, row, v);
         });
         __syncthreads();
         // wave w owns slots [w * kSlotsPerWave, +kSlotsPerWave)
 #pragma unroll
-        for (int g = 0; g < kSlotsPerWave / kWave; g++) c += keys[w * kSlotsPerWave + g * kWave + l] != kEmpty ? 1 : 0;
+        for (int g = 0; g < kSlotsPerWave / kWave; g++) c += keys[w * kSlotsPerWave + g * kWave + l] != 0 ? 1 : 0;
       }
       if (jn >= 0) pre_load(jn, false);  // the next item's B entries
       if (__ballot(bad) && l == 0) flag_error(status, 5);
       // each wave reserves room for its own entries on the column's cursor
       // (no workgroup scan or barrier) and writes its rows or slots 64 at a
-      // time to consecutive positions
+      // time to consecutive positions, clearing them in the table
       const int cw = readlane(wave_incl_add(c), kWave - 1);
       int pw = 0;
       if (l == 0 && cw) pw = atomicAdd(&hv_cur[jj], cw);
       pw = readlane(pw, 0);
-      if ((int64_t)pw + cw > cap) {
-        if (l == 0) flag_error(status, 4);
-      } else {
-        int64_t o = base + pw;
-        if (dense) {
+      const bool fits = (int64_t)pw + cw <= cap;
+      if (!fits && l == 0) flag_error(status, 4);
+      int64_t o = base + pw;
+      if (dense) {
 #pragma unroll 4
-          for (int g = 0; g < kRowsPerWave / kWave; g++) {
-            const int r = w * kRowsPerWave + g * kWave + l;
-            const bool occ = (bits[r >> 5] >> (r & 31)) & 1u;
-            const uint64_t mask = __ballot(occ);
-            if (occ) {
+        for (int g = 0; g < kRowsPerWave / kWave; g++) {
+          const uint64_t mask = (uint64_t)(uint32_t)readlane((int)word, 2 * g) |
+                                ((uint64_t)(uint32_t)readlane((int)word, 2 * g + 1) << 32);
+          if (mask == 0ull) continue;
+          const int r = w * kRowsPerWave + g * kWave + l;
+          if ((mask >> l) & 1ull) {
+            const double x = acc[r];
+            acc[r] = 0.0;
+            if (fits) {
               const int64_t q = o + mbcnt(mask);
               out_ri[q] = (int32_t)(rb + r);
-              out_v[q] = (VT)acc[r];
+              out_v[q] = (VT)x;
             }
-            o += __popcll(mask);
           }
-        } else {
+          o += __popcll(mask);
+        }
+        if (l < kWordsPerWave) bits[w * kWordsPerWave + l] = 0u;
+      } else {
 #pragma unroll 2
-          for (int g = 0; g < kSlotsPerWave / kWave; g++) {
-            const int q = w * kSlotsPerWave + g * kWave + l;
-            const int32_t key = keys[q];
-            const bool occ = key != kEmpty;
-            const uint64_t mask = __ballot(occ);
-            if (occ) {
+        for (int g = 0; g < kSlotsPerWave / kWave; g++) {
+          const int q = w * kSlotsPerWave + g * kWave + l;
+          const int32_t key = keys[q];
+          const bool occ = key != 0;
+          const uint64_t mask = __ballot(occ);
+          if (occ) {
+            const double x = vals[q];
+            keys[q] = 0;
+            vals[q] = 0.0;
+            if (fits) {
               const int64_t d = o + mbcnt(mask);
-              out_ri[d] = key;
-              out_v[d] = (VT)vals[q];
+              out_ri[d] = key - 1;
+              out_v[d] = (VT)x;
             }
-            o += __popcll(mask);
           }
+          o += __popcll(mask);
         }
       }
       if (jn >= 0) pre_load(jn, true);  // and their segment words
@@ -1845,8 +1891,9 @@ struct MbSrc {
   struct Pre {};  // nothing to load ahead: the range is the item's input
   __device__ __forceinline__ void pre_b(int64_t, int64_t, int, int, Pre &) const {}
   __device__ __forceinline__ void pre_seg(int, int, Pre &) const {}
+  using Scratch = HvScratch<VT>;  // unused: the entries of an item are contiguous
   template <class Ins>
-  __device__ __forceinline__ int visit(int64_t e0, int64_t e1, int, int, int w, int nw, SegScratch &, const Pre &,
+  __device__ __forceinline__ int visit(int64_t e0, int64_t e1, int, int, int w, int nw, Scratch &, const Pre &,
                                        Ins &&ins) const {
     constexpr int kV = 4;
     const int l = lane();
@@ -1893,7 +1940,7 @@ __global__ __launch_bounds__(kHvWideThreads) void k_hv_wide(HvArgs<VT> a, int64_
   static_assert(kRowsPerWave % kWave == 0 && kWordsPerWave <= kWave, "rows split evenly over waves");
   __shared__ double s_acc[kHvWideRows];
   __shared__ uint32_t s_bits[kWords];
-  __shared__ SegScratch s_sc[NW];
+  __shared__ HvScratch<VT> s_sc[NW];
   __shared__ int s_item;
   const int w = threadIdx.x / kWave, l = lane();
   int32_t *status = &hdr->status;
@@ -1902,7 +1949,6 @@ __global__ __launch_bounds__(kHvWideThreads) void k_hv_wide(HvArgs<VT> a, int64_
   const int64_t nwide = min((int64_t)hdr->nwide, wcap);
   const int64_t nq = (P + kHvWideSlabs - 1) / kHvWideSlabs;
   const int64_t nitems = nwide * nq;
-  s_sc[w].mark[l] = 0;
   for (;;) {
     __syncthreads();  // s_item of the previous item is no longer read
     if (threadIdx.x == 0) s_item = atomicAdd(&hdr->wide_cursor, 1);
@@ -2536,8 +2582,7 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
   const int heavy = cnt[kNumBins - 1];
   if (slabs && heavy != 0) {
     int32_t *soff = (int32_t *)(ws + L.slab_off);
-    int32_t *s_ri = (int32_t *)(ws + L.slab_ri);
-    VT *s_v = (VT *)(ws + L.slab_v);
+    SlabEnt<VT> *s_ent = (SlabEnt<VT> *)(ws + L.slab_ent);
     const int32_t *hc = &hdr->bin_count[kNumBins - 1];
     if (khi > klo) {
       ProfScope prof("slab_split", st);
@@ -2550,7 +2595,7 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
                          (const VT *)A->values, klo, khi, seed, hdr, hc);
       LAUNCHCHK();
       hipLaunchKernelGGL(k_slab_split<VT>, dim3(grid_of(khi - klo, 4)), dim3(256), 0, st, A->colptr, A->rowidx,
-                         (const VT *)A->values, klo, khi, A->nrows, (int)L.P, soff, s_ri, s_v, hc, &hdr->status,
+                         (const VT *)A->values, klo, khi, A->nrows, (int)L.P, soff, s_ent, hc, &hdr->status,
                          (const WsHeader *)hdr);
       LAUNCHCHK();
       hipLaunchKernelGGL(k_seg_pack, dim3(grid_of(khi - klo, 64), (unsigned)((L.P + 63) / 64)), dim3(256), 0, st,
@@ -2562,8 +2607,7 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
     }
     HvArgs<VT> ha;
     ha.Acp = A->colptr;
-    ha.Ari = s_ri;
-    ha.Av = s_v;
+    ha.ent = s_ent;
     ha.Bcp = B->colptr;
     ha.Bri = B->rowidx;
     ha.Bv = (const VT *)B->values;
@@ -2730,6 +2774,8 @@ static int noalloc_scratch(void **out) {
 }
 
 static_assert(sizeof(PartDesc) == kPartDescBytes, "part descriptor size");
+static_assert(sizeof(SlabEnt<float>) == kSlabEntBytes[0] && sizeof(SlabEnt<double>) == kSlabEntBytes[1],
+              "slabbed entry sizes");
 static_assert(sizeof(WsHeader) <= 2048, "header too large");
 
 }  // namespace spg
