@@ -62,6 +62,20 @@ typedef enum {
 
 typedef enum { SPGEMM_F32 = 0, SPGEMM_F64 = 1 } spgemm_dtype;
 
+/* Semiring of spgemm_numeric and spgemm_merge (Sec. II-A: the algorithms
+ * use only a semiring's addition and multiplication, so they apply to any
+ * semiring).  For every output entry (i,j) with at least one product term:
+ *   PLUS_TIMES: C(i,j) = sum over k of A(i,k)*B(k,j)   (the ordinary product)
+ *   MIN_PLUS  : C(i,j) = min over k of A(i,k)+B(k,j)   (tropical: shortest paths)
+ *   OR_AND    : C(i,j) = 1                              (boolean: every stored
+ *               entry is true, so the result is the pattern product)
+ * Terms are formed and combined in float64 and rounded once to the output
+ * dtype; min and the or-and result are exact, a min-plus term is one
+ * float64 addition.  Structure is structural in every semiring (the same
+ * pattern as the plus-times product).  A merge combines the parts' entries
+ * with the semiring's addition. */
+typedef enum { SPGEMM_SR_PLUS_TIMES = 0, SPGEMM_SR_MIN_PLUS = 1, SPGEMM_SR_OR_AND = 2 } spgemm_semiring;
+
 /* A CSC matrix.  colptr[ncols+1] (int64, colptr[0] = 0, nondecreasing,
  * colptr[ncols] = nnz), rowidx[nnz] (int32, 0 <= row < nrows, unique within
  * a column, any order), values[nnz] of `dtype` (may be NULL where only the
@@ -84,7 +98,8 @@ typedef enum {
   SPGEMM_OP_TRANSPOSE = 5,
   SPGEMM_OP_BATCHED_FORWARD = 6,
   SPGEMM_OP_BATCHED_BACKWARD = 7,
-  SPGEMM_OP_PRUNE = 8
+  SPGEMM_OP_PRUNE = 8,
+  SPGEMM_OP_SORT = 9
 } spgemm_op;
 
 /* Workspace bytes needed by one call of `op`.  Host only; never syncs.
@@ -97,6 +112,7 @@ typedef enum {
  *   TRANSPOSE:         A = the matrix to transpose.
  *   BATCHED_FORWARD:   A, B = the packed operands; c0 = 0, c1 = B.ncols.
  *   BATCHED_BACKWARD:  A, B = the operands of the product.
+ *   PRUNE, SORT:       A = the matrix pruned or sorted; B unused.
  * The result depends only on shapes, never on device data. */
 int spgemm_workspace_size(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t c1,
                           int32_t n_layers, size_t *bytes_host);
@@ -158,22 +174,24 @@ int spgemm_colptr(const int64_t *counts, int64_t n, int64_t *colptr_out, void *w
  * `stream` to read the per-bin column counts (and, for heavy columns, their
  * count) that size the launches.  With n_layers > 1 the layer's share of
  * B(:, c0:c1) is first compacted into the workspace.  A mismatch between
- * counts and the product sets the workspace status (spgemm_ws_status). */
+ * counts and the product sets the workspace status (spgemm_ws_status).
+ * `semiring` is a spgemm_semiring (SPGEMM_E_INVAL otherwise). */
 int spgemm_numeric(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t c1, int32_t layer,
                    int32_t n_layers, const int64_t *flops, const int64_t *c_colptr, int32_t *c_rowidx,
-                   void *c_values, void *ws, size_t ws_bytes, void *stream);
+                   void *c_values, int32_t semiring, void *ws, size_t ws_bytes, void *stream);
 
 /* Sort-free hash merge (Sec. IV-D, sort-free hash merging; Merge in Alg. 1
  * and Alg. 2): C(:,j) = sum over parts of parts[p](:,j), entries with equal
- * row added.  parts is a HOST array of n_parts descriptors (device arrays
+ * row combined (added, for plus-times).  parts is a HOST array of n_parts descriptors (device arrays
  * inside), all with the same nrows, ncols and dtype, 1 <= n_parts <= 4096.
  * c_colptr (ncols+1) comes from the union counts (row L of the symbolic
  * output for the batch).  Output rows in hash-table order.  Synchronizes
  * `stream` to read the per-bin column counts and, for columns of more than
  * 5120 rows, their total entry counts (to cut them into chunks that fit the
- * workspace's bucket region). */
+ * workspace's bucket region).  Entries with equal row are combined with the
+ * addition of `semiring` (a spgemm_semiring; SPGEMM_E_INVAL otherwise). */
 int spgemm_merge(const spgemm_csc *parts, int32_t n_parts, const int64_t *c_colptr, int32_t *c_rowidx,
-                 void *c_values, void *ws, size_t ws_bytes, void *stream);
+                 void *c_values, int32_t semiring, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- Gradient support.  For a loss defined on the pattern of C = A*B
  * (not part of the paper), with dC = dLoss/dC on P(C):
@@ -308,6 +326,24 @@ int spgemm_batched_backward(const spgemm_csc *A, const spgemm_csc *B, const spge
  * output or a capacity below the bound, SPGEMM_E_DTYPE, SPGEMM_E_WORKSPACE. */
 int spgemm_prune_topk(const spgemm_csc *C, double threshold, int64_t k, int64_t *out_colptr, int32_t *out_rowidx,
                       void *out_values, int64_t out_cap, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- Row-sorted output (Sec. IV-D: the final output of the column-wise
+ * merge, Merge-Fiber, is kept sorted within each column; the sort-free hash
+ * kernels of this library write rows in table order instead).
+ *
+ * Sorts every column of C by row, values moving with their rows, into
+ * rowidx_out / values_out (device arrays of C.nnz entries, distinct from C's
+ * arrays: out of place; C's column pointers describe the result too).  Rows
+ * must be unique within each column, as in every output of this library; a
+ * repeated row or a row outside [0, C.nrows) sets the workspace status
+ * (code 11), and in columns of more than 4096 entries leaves some positions
+ * of that column unwritten (nothing outside the column is written).  Columns of
+ * up to 64 entries are sorted by one wavefront, up to 4096 by one workgroup
+ * in LDS, longer ones by row windows of 2^19 rows ranked through an LDS
+ * bitmap.  Asynchronous, no host synchronization (graph-capturable).
+ * Workspace: SPGEMM_OP_SORT with A = C. */
+int spgemm_sort_columns(const spgemm_csc *C, int32_t *rowidx_out, void *values_out, void *ws, size_t ws_bytes,
+                        void *stream);
 
 /* Bin thresholds (process-wide; used by calls launched afterwards): which = 0
  * for the symbolic pass, 1 for numeric, merge and masked products.

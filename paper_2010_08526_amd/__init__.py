@@ -25,8 +25,11 @@ _lib = ctypes.CDLL(LIB_PATH)
 # ---------------------------------------------------------------- constants
 OK, E_INVAL, E_SHAPE, E_DTYPE, E_BUDGET, E_WORKSPACE, E_HIP, E_OVERFLOW, E_DEVICE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 F32, F64 = 0, 1
+# semirings of the numeric pass and the merge (spgemm_semiring)
+PLUS_TIMES, MIN_PLUS, OR_AND = 0, 1, 2
+SEMIRINGS = {"plus_times": PLUS_TIMES, "min_plus": MIN_PLUS, "or_and": OR_AND}
 (OP_SYMBOLIC, OP_NUMERIC, OP_MERGE, OP_COLPTR, OP_MASKED_XTY, OP_TRANSPOSE, OP_BATCHED_FORWARD, OP_BATCHED_BACKWARD,
- OP_PRUNE) = range(9)
+ OP_PRUNE, OP_SORT) = range(10)
 MAX_PARTS = 4096
 
 _DTYPE = {torch.float32: F32, torch.float64: F64}
@@ -46,8 +49,8 @@ _lib.spgemm_symbolic.argtypes = [_P, _P, _i64, _i64, _i32, _vp, _vp, _vp, _sz, _
 _lib.spgemm_plan_batches.argtypes = [_vp, _i64, _i32, _i32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, _i32,
                                      _vp, ctypes.POINTER(_i32), _vp]
 _lib.spgemm_colptr.argtypes = [_vp, _i64, _vp, _vp, _sz, _vp]
-_lib.spgemm_numeric.argtypes = [_P, _P, _i64, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
-_lib.spgemm_merge.argtypes = [_P, _i32, _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.spgemm_numeric.argtypes = [_P, _P, _i64, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _sz, _vp]
+_lib.spgemm_merge.argtypes = [_P, _i32, _vp, _vp, _vp, _i32, _vp, _sz, _vp]
 _lib.spgemm_ws_status.argtypes = [_vp, _vp]
 _lib.spgemm_ws_status_code.argtypes = [_vp, _vp, _vp]
 _lib.spgemm_ws_invalidate.argtypes = [_vp, _vp]
@@ -175,17 +178,46 @@ def colptr(counts: torch.Tensor, out: torch.Tensor, ws: torch.Tensor, stream=Non
     _check(_lib.spgemm_colptr(_ptr(counts), n, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)), "spgemm_colptr")
 
 
+def semiring_id(semiring) -> int:
+    """spgemm_semiring value of a name ('plus_times', 'min_plus', 'or_and') or id."""
+    if isinstance(semiring, str):
+        if semiring not in SEMIRINGS:
+            raise ValueError(f"unknown semiring {semiring!r}")
+        return SEMIRINGS[semiring]
+    return int(semiring)
+
+
 def numeric(A, B, c0: int, c1: int, layer: int, n_layers: int, flops, c_colptr, c_rowidx, c_values,
-            ws: torch.Tensor, stream=None):
+            ws: torch.Tensor, stream=None, semiring=PLUS_TIMES):
     _check(_lib.spgemm_numeric(ctypes.byref(desc(A)), ctypes.byref(desc(B)), c0, c1, layer, n_layers, _ptr(flops),
-                               _ptr(c_colptr), _ptr(c_rowidx), _ptr(c_values), _ptr(ws), ws.numel(), _stream(stream)),
-           "spgemm_numeric")
+                               _ptr(c_colptr), _ptr(c_rowidx), _ptr(c_values), semiring_id(semiring), _ptr(ws),
+                               ws.numel(), _stream(stream)), "spgemm_numeric")
 
 
-def merge(parts, c_colptr, c_rowidx, c_values, ws: torch.Tensor, stream=None):
+def merge(parts, c_colptr, c_rowidx, c_values, ws: torch.Tensor, stream=None, semiring=PLUS_TIMES):
     arr = (spgemm_csc * len(parts))(*[desc(p) for p in parts])
-    _check(_lib.spgemm_merge(arr, len(parts), _ptr(c_colptr), _ptr(c_rowidx), _ptr(c_values), _ptr(ws), ws.numel(),
-                             _stream(stream)), "spgemm_merge")
+    _check(_lib.spgemm_merge(arr, len(parts), _ptr(c_colptr), _ptr(c_rowidx), _ptr(c_values), semiring_id(semiring),
+                             _ptr(ws), ws.numel(), _stream(stream)), "spgemm_merge")
+
+
+_lib.spgemm_sort_columns.argtypes = [_P, _vp, _vp, _vp, _sz, _vp]
+
+
+def sort_columns(C, rowidx_out: torch.Tensor | None = None, values_out: torch.Tensor | None = None,
+                 ws: torch.Tensor | None = None, stream=None) -> CSC:
+    """C with every column's entries in row order (values moved with their
+    rows), written to separate arrays; C's column pointers are shared."""
+    dev = C.rowidx.device
+    n = C.nnz
+    if ws is None:
+        ws = alloc_workspace(workspace_size(OP_SORT, C), dev)
+    if rowidx_out is None:
+        rowidx_out = torch.empty(max(1, n), dtype=torch.int32, device=dev)
+    if values_out is None:
+        values_out = torch.empty(max(1, n), dtype=C.values.dtype, device=dev)
+    _check(_lib.spgemm_sort_columns(ctypes.byref(desc(C)), _ptr(rowidx_out), _ptr(values_out), _ptr(ws), ws.numel(),
+                                    _stream(stream)), "spgemm_sort_columns")
+    return CSC(C.nrows, C.ncols, C.colptr, rowidx_out[:n], values_out[:n])
 
 
 def ws_status(ws: torch.Tensor, stream=None) -> int:
@@ -248,10 +280,14 @@ class Engine:
     """
 
     def __init__(self, A, B, n_layers: int = 1, budget_bytes: int | None = None, max_batches: int = 1 << 16,
-                 device="cuda"):
+                 device="cuda", semiring=PLUS_TIMES, sorted_output: bool = False):
         if A.ncols != B.nrows:
             raise SpgemmError(E_SHAPE, "Engine")
         self.A, self.B, self.L = A, B, int(n_layers)
+        self.semiring = semiring_id(semiring)
+        # row-sorted output columns: each batch is formed, then sorted into a
+        # second buffer of the same size (counted by the planner)
+        self.sorted_output = bool(sorted_output)
         self.device = device
         self.max_batches = max_batches
         self.vbytes = 4 if A.values is None or A.values.dtype == torch.float32 else 8
@@ -263,13 +299,15 @@ class Engine:
         self.ws_mrg = alloc_workspace(workspace_size(OP_MERGE, mparts, None, 0, 0, max(1, self.L)), device) \
             if self.L > 1 else None
         self.ws_scan = alloc_workspace(workspace_size(OP_COLPTR, None, None, 0, n + 1), device)
+        self.ws_sort = alloc_workspace(workspace_size(OP_SORT, CSC(A.nrows, n, B.colptr, B.rowidx, B.values)), device) \
+            if self.sorted_output else None
         rows = self.L + 1 if self.L > 1 else 1
         self.flops = torch.empty(n, dtype=torch.int64, device=device)
         self.nnz = torch.empty((rows, n), dtype=torch.int64, device=device)
         r = 4 + self.vbytes
         self.input_bytes = r * (A.nnz + B.nnz) + 8 * (A.ncols + B.ncols + 2)
-        self.reserve_bytes = sum(int(w.numel()) for w in (self.ws_sym, self.ws_num, self.ws_mrg, self.ws_scan)
-                                 if w is not None) + 8 * 4 * (n + 1) * rows
+        self.reserve_bytes = sum(int(w.numel()) for w in (self.ws_sym, self.ws_num, self.ws_mrg, self.ws_scan,
+                                                          self.ws_sort) if w is not None) + 8 * 4 * (n + 1) * rows
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info()
             budget_bytes = int(free * 0.9) + self.input_bytes + self.reserve_bytes
@@ -283,8 +321,15 @@ class Engine:
         ws_invalidate(self.ws_num, stream)
         symbolic(A, B, 0, n, self.L, self.flops, self.nnz, self.ws_sym, stream)
         nnz_host = self.nnz.cpu().numpy()
-        bounds, tot = plan_batches(nnz_host.reshape(-1), n, self.L, self.vbytes, self.input_bytes, self.budget_bytes,
+        counts = nnz_host
+        if self.sorted_output:  # the merged batch is held twice: as formed and sorted
+            counts = nnz_host.copy()
+            counts[-1] *= 2
+        bounds, tot = plan_batches(counts.reshape(-1), n, self.L, self.vbytes, self.input_bytes, self.budget_bytes,
                                    self.reserve_bytes, self.max_batches)
+        if self.sorted_output:
+            tot = np.stack([nnz_host[:, a:b].sum(1) for a, b in zip(bounds[:-1], bounds[1:])]) if len(bounds) > 1 \
+                else tot
         return Plan(self.flops, self.nnz, nnz_host, bounds, tot, self.L, self.budget_bytes, self.input_bytes,
                     self.reserve_bytes)
 
@@ -302,6 +347,9 @@ class Engine:
                     "ccp": torch.empty(need[0] + 1, dtype=torch.int64, device=dev),
                     "cri": torch.empty(max(1, need[1]), dtype=torch.int32, device=dev),
                     "cv": torch.empty(max(1, need[1]), dtype=self.vdtype, device=dev)}
+            if self.sorted_output:
+                bufs["sri"] = torch.empty(max(1, need[1]), dtype=torch.int32, device=dev)
+                bufs["sv"] = torch.empty(max(1, need[1]), dtype=self.vdtype, device=dev)
             if L > 1:
                 bufs["dcp"] = torch.empty((L, need[0] + 1), dtype=torch.int64, device=dev)
                 bufs["dri"] = torch.empty(max(1, need[2]), dtype=torch.int32, device=dev)
@@ -332,7 +380,7 @@ class Engine:
         if L == 1:
             e0 = mark()
             colptr(self.nnz[0, c0:c1], ccp, self.ws_scan, stream)
-            numeric(A, B, c0, c1, 0, 1, self.flops[c0:c1], ccp, cri, cv, self.ws_num, stream)
+            numeric(A, B, c0, c1, 0, 1, self.flops[c0:c1], ccp, cri, cv, self.ws_num, stream, self.semiring)
             if marks is not None:
                 marks.append(("numeric", e0, mark()))
             nnzc = int(plan.batch_nnz[i, 0])
@@ -346,20 +394,26 @@ class Engine:
                 cnt = int(plan.batch_nnz[i, l])
                 dri = bufs["dri"][off:off + cnt]
                 dv = bufs["dv"][off:off + cnt]
-                numeric(A, B, c0, c1, l, L, self.flops[c0:c1], dcp, dri, dv, self.ws_num, stream)
+                numeric(A, B, c0, c1, l, L, self.flops[c0:c1], dcp, dri, dv, self.ws_num, stream, self.semiring)
                 parts.append(CSC(A.nrows, w, dcp, dri, dv))
                 off += cnt
             e1 = mark()
             colptr(self.nnz[L, c0:c1], ccp, self.ws_scan, stream)
-            merge(parts, ccp, cri, cv, self.ws_mrg, stream)
+            merge(parts, ccp, cri, cv, self.ws_mrg, stream, self.semiring)
             if marks is not None:
                 marks.append(("numeric", e0, e1))
                 marks.append(("merge", e1, mark()))
             nnzc = int(plan.batch_nnz[i, L])
+        if self.sorted_output:
+            e0 = mark()
+            Cs = sort_columns(CSC(A.nrows, w, ccp, cri[:nnzc], cv[:nnzc]), bufs["sri"], bufs["sv"], self.ws_sort, stream)
+            if marks is not None:
+                marks.append(("sort", e0, mark()))
+            return Cs
         return CSC(A.nrows, w, ccp, cri[:nnzc], cv[:nnzc])
 
     def check(self, stream=None):
-        for w in (self.ws_sym, self.ws_num, self.ws_mrg):
+        for w in (self.ws_sym, self.ws_num, self.ws_mrg, self.ws_sort):
             if w is not None:
                 check_ws(w, "device-side check", stream)
 
@@ -392,10 +446,13 @@ def _concat(batches, nrows):
                torch.cat([b.values for b in batches]))
 
 
-def spgemm(A, B, *, layers: int = 1, budget_bytes: int | None = None, consume=None, stream=None):
-    """C = A B (plus-times).  With ``consume`` the batches are handed to it and
-    discarded; otherwise C is returned (all batches concatenated)."""
-    eng = Engine(A, B, layers, budget_bytes)
+def spgemm(A, B, *, layers: int = 1, budget_bytes: int | None = None, consume=None, stream=None,
+           semiring=PLUS_TIMES, sorted_output: bool = False):
+    """C = A B over ``semiring`` ('plus_times', 'min_plus', 'or_and'), rows of
+    each column in hash-table order or, with ``sorted_output``, ascending.
+    With ``consume`` the batches are handed to it and discarded; otherwise C
+    is returned (all batches concatenated)."""
+    eng = Engine(A, B, layers, budget_bytes, semiring=semiring, sorted_output=sorted_output)
     res = eng.run(consume, stream)
     return res if consume is not None else res[0]
 

@@ -43,7 +43,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     hipcc = _hipcc()
     objs, cmds = [], []
-    for src in ("host.cpp", "kernels.hip", "backward.hip", "prune.hip", "profile.cpp"):
+    for src in ("host.cpp", "kernels.hip", "backward.hip", "prune.hip", "sort.hip", "profile.cpp"):
         obj = os.path.join(LIBDIR, src.replace(".", "_") + f".{os.getpid()}.o")
         cmd = [hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if src == "host.cpp":

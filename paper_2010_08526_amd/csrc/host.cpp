@@ -204,6 +204,15 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
       off = align_up(off + sizeof(int64_t) * (n / 8192 + 2));
       break;
     }
+    case SPGEMM_OP_SORT: {  // A = the matrix sorted: column lists of three length classes
+      if (!A) return SPGEMM_E_INVAL;
+      if (A->ncols < 0) return SPGEMM_E_INVAL;
+      L->ncol = A->ncols;
+      L->m = A->nrows;
+      L->bins = off;
+      off = align_up(off + sizeof(int32_t) * 3 * (size_t)A->ncols);
+      break;
+    }
     case SPGEMM_OP_COLPTR: {
       if (c0 < 0 || c1 < c0) return SPGEMM_E_INVAL;
       int64_t n = c1 - c0;

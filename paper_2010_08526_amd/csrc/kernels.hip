@@ -22,6 +22,7 @@
 #include "lds_hash.hpp"
 #include "hip_host.hpp"
 #include "profile.hpp"
+#include "semiring.hpp"
 
 namespace spg {
 
@@ -136,7 +137,7 @@ constexpr int kLongSeg = 256;
 constexpr int kVec = 8;
 constexpr int kBlk = kWave * kVec;
 
-template <bool VALUES, class VT, class Ins>
+template <bool VALUES, class VT, class Mul = SrPlusTimes, class Ins>
 __device__ __forceinline__ void stream_segment(const int32_t *__restrict__ ri, const VT *__restrict__ v,
                                                double scale, int len, int64_t unit_base, int64_t r_rank,
                                                int64_t r_stride, uint32_t m, int32_t *status, Ins &&ins) {
@@ -163,7 +164,7 @@ __device__ __forceinline__ void stream_segment(const int32_t *__restrict__ ri, c
       if (e0 + t * kWave < len) {
         const int32_t r = opaque(row[t]);
         if ((uint32_t)r < m)
-          ins(r, VALUES ? (double)opaque(raw[t]) * scale : 0.0);
+          ins(r, VALUES ? Mul::mul((double)opaque(raw[t]), scale) : 0.0);
         else
           flag_error(status, 3);
       }
@@ -240,7 +241,7 @@ __device__ __forceinline__ void lp_a(const ProductArgs<VT> &a, LightPre<VT> &pre
   }
 }
 
-template <bool VALUES, class VT, bool SLAB = false, class Ins>
+template <bool VALUES, class VT, bool SLAB = false, class Mul = SrPlusTimes, class Ins>
 __device__ __forceinline__ void traverse_product(const ProductArgs<VT> &a, int64_t col, int64_t c_rank,
                                                  int64_t c_stride, int64_t r_rank, int64_t r_stride,
                                                  SegScratch &sc, int32_t *status, Ins &&ins,
@@ -302,7 +303,7 @@ __device__ __forceinline__ void traverse_product(const ProductArgs<VT> &a, int64
             row = a.Ari[q];
             if (VALUES) raw = a.Av[q];
           },
-          [&](int o, VT raw) { return VALUES ? (double)raw * sc.scale[o] : 0.0; }, ins);
+          [&](int o, VT raw) { return VALUES ? Mul::mul((double)raw, sc.scale[o]) : 0.0; }, ins);
       if (__ballot(oob) && l == 0) flag_error(status, 5);
       rounds_before += (total + kWave - 1) / kWave;
       wave_sync();
@@ -319,7 +320,7 @@ __device__ __forceinline__ void traverse_product(const ProductArgs<VT> &a, int64
         flag_error(status, 5);
         continue;
       }
-      stream_segment<VALUES, VT>(a.Ari + so, VALUES ? a.Av + so : nullptr, sb, sn, rounds_before, r_rank, r_stride,
+      stream_segment<VALUES, VT, Mul>(a.Ari + so, VALUES ? a.Av + so : nullptr, sb, sn, rounds_before, r_rank, r_stride,
                                  (uint32_t)a.m, status, ins);
       rounds_before += (sn + kBlk - 1) / kBlk;
     }
@@ -331,16 +332,16 @@ __device__ __forceinline__ void traverse_product(const ProductArgs<VT> &a, int64
 // handful of long segments is typical of heavy columns) split the rounds of
 // every chunk instead, so that no wave idles.  (Splitting fewer chunks among
 // groups of waves loses more to uneven chunks than it saves in re-reads.)
-template <bool VALUES, class VT, bool SLAB = false, class Ins>
+template <bool VALUES, class VT, bool SLAB = false, class Mul = SrPlusTimes, class Ins>
 __device__ __forceinline__ void traverse_product_block(const ProductArgs<VT> &a, int64_t col, int w, int nw,
                                                        SegScratch &sc, int32_t *status, Ins &&ins,
                                                        SlabSel sl = SlabSel{nullptr, 0, 0, 0},
                                                        const LightPre<VT> *pre = nullptr) {
   const int64_t nchunks = ((pre ? pre->pend - pre->pbeg : a.Bcp[col + 1] - a.Bcp[col]) + kWave - 1) / kWave;
   if (nchunks >= 2 * nw)
-    traverse_product<VALUES, VT, SLAB>(a, col, w, nw, 0, 1, sc, status, ins, sl, pre);
+    traverse_product<VALUES, VT, SLAB, Mul>(a, col, w, nw, 0, 1, sc, status, ins, sl, pre);
   else
-    traverse_product<VALUES, VT, SLAB>(a, col, 0, 1, w, nw, sc, status, ins, sl, pre);
+    traverse_product<VALUES, VT, SLAB, Mul>(a, col, 0, 1, w, nw, sc, status, ins, sl, pre);
 }
 
 // Visits every stored entry of column `col` of the parts: ins(i, value).
@@ -394,7 +395,7 @@ __device__ __forceinline__ void traverse_merge(const PartDesc *P, int nparts, in
       const int32_t *sri = (const int32_t *)readlane64((int64_t)ri, L);
       const VT *sv = (const VT *)readlane64((int64_t)v, L);
       const int sn = readlane(len, L);
-      stream_segment<true, VT>(sri, sv, 1.0, sn, rounds_before, r_rank, r_stride, (uint32_t)m, status, ins);
+      stream_segment<true, VT, MulFirst>(sri, sv, 1.0, sn, rounds_before, r_rank, r_stride, (uint32_t)m, status, ins);
       rounds_before += (sn + kBlk - 1) / kBlk;
     }
   }
@@ -665,8 +666,10 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(ProductArgs<float> a, int64
 // Numeric and merge kernels (float64 accumulation, output in VT).
 // ============================================================================
 // Source selector: the product terms of A*B, or the entries of the parts.
-template <class VT>
+template <class VT, class SR = SrPlusTimes>
 struct ProductSrc {
+  using Sr = SR;
+  static constexpr bool kMerge = false;
   ProductArgs<VT> a;
   int64_t c0;
   using Pre = LightPre<VT>;
@@ -677,29 +680,33 @@ struct ProductSrc {
   template <class Ins>
   __device__ __forceinline__ void visit_pre(int64_t jj, const Pre &pre, void *scratch, int32_t *status,
                                             Ins &&ins) const {
-    traverse_product<true, VT>(a, c0 + jj, 0, 1, 0, 1, *(SegScratch *)scratch, status, ins,
-                               SlabSel{nullptr, 0, 0, 0}, &pre);
+    traverse_product<true, VT, false, SR>(a, c0 + jj, 0, 1, 0, 1, *(SegScratch *)scratch, status, ins,
+                                          SlabSel{nullptr, 0, 0, 0}, &pre);
   }
   // the waves of a workgroup on one column (chunks or rounds split)
   template <class Ins>
   __device__ __forceinline__ void visit_pre_block(int64_t jj, const Pre &pre, int w, int nw, void *scratch,
                                                   int32_t *status, Ins &&ins) const {
-    traverse_product_block<true, VT>(a, c0 + jj, w, nw, *(SegScratch *)scratch, status, ins,
-                                     SlabSel{nullptr, 0, 0, 0}, &pre);
+    traverse_product_block<true, VT, false, SR>(a, c0 + jj, w, nw, *(SegScratch *)scratch, status, ins,
+                                                SlabSel{nullptr, 0, 0, 0}, &pre);
   }
   template <class Ins>
   __device__ __forceinline__ void visit(int64_t jj, int64_t c_rank, int64_t c_stride, int64_t r_rank,
                                         int64_t r_stride, void *scratch, int32_t *status, Ins &&ins) const {
     if (c_stride > 1 && r_stride == 1)
-      traverse_product_block<true, VT>(a, c0 + jj, (int)c_rank, (int)c_stride, *(SegScratch *)scratch, status, ins);
+      traverse_product_block<true, VT, false, SR>(a, c0 + jj, (int)c_rank, (int)c_stride, *(SegScratch *)scratch,
+                                                  status, ins);
     else
-      traverse_product<true, VT>(a, c0 + jj, c_rank, c_stride, r_rank, r_stride, *(SegScratch *)scratch, status, ins);
+      traverse_product<true, VT, false, SR>(a, c0 + jj, c_rank, c_stride, r_rank, r_stride, *(SegScratch *)scratch,
+                                            status, ins);
   }
   static constexpr size_t kScratch = sizeof(SegScratch);
 };
 
-template <class VT>
+template <class VT, class SR = SrPlusTimes>
 struct MergeSrc {
+  using Sr = SR;
+  static constexpr bool kMerge = true;
   const PartDesc *P;
   int nparts;
   int64_t m;
@@ -737,7 +744,7 @@ __device__ __forceinline__ void init_mark(void *scratch) {
 // Writes the occupied slots [s_lo, s_hi) of a table, in slot order, to
 // consecutive output positions from o on (one wave; positions at or beyond
 // `end` are not written).  Returns the position after the last entry.
-template <class VT>
+template <class VT, class SR>
 __device__ __forceinline__ int64_t compact_run(const int32_t *keys, const double *vals, int s_lo, int s_hi,
                                                int64_t o, int64_t end, int32_t *out_ri, VT *out_v) {
   const int l = lane();
@@ -749,7 +756,7 @@ __device__ __forceinline__ int64_t compact_run(const int32_t *keys, const double
     const int64_t q = o + mbcnt(mask);
     if (occ && q < end) {
       out_ri[q] = key;
-      out_v[q] = (VT)vals[s];
+      out_v[q] = (VT)SR::out(vals[s]);
     }
     o += __popcll(mask);
   }
@@ -813,11 +820,12 @@ __global__ __launch_bounds__(256) void k_num_wave(Src src, const int32_t *list, 
     for (int s = l; s < TBL / 4; s += kWave) reinterpret_cast<int4 *>(keys)[s] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
     for (int s = l; s < TBL / 2; s += kWave) reinterpret_cast<double2 *>(vals)[s] = make_double2(0.0, 0.0);
     wave_sync();
-    src.visit_pre(jj, cur, s_sc[w], status, [&](int32_t row, double v) { ht_accumulate(keys, vals, TBL, row, v); });
+    src.visit_pre(jj, cur, s_sc[w], status,
+                  [&](int32_t row, double v) { ht_accumulate_sr<typename Src::Sr>(keys, vals, TBL, row, v); });
     if (more) src.pre_b(pre, 0, 1);
     wave_sync();
     // one wave owns the column: output positions follow a running count
-    const int64_t o = compact_run<VT>(keys, vals, 0, TBL, base, base + cap, out_ri, out_v);
+    const int64_t o = compact_run<VT, typename Src::Sr>(keys, vals, 0, TBL, base, base + cap, out_ri, out_v);
     if (more) src.pre_a(pre);
     if (l == 0 && o - base != cap) flag_error(status, 4);
     wave_sync();
@@ -870,7 +878,7 @@ __global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *l
     for (int s = threadIdx.x; s < TBL / 2; s += THREADS) reinterpret_cast<double2 *>(s_vals)[s] = make_double2(0.0, 0.0);
     __syncthreads();
     src.visit_pre_block(jj, cur, w, NW, s_sc[w], status,
-                        [&](int32_t row, double v) { ht_accumulate(s_keys, s_vals, TBL, row, v); });
+                        [&](int32_t row, double v) { ht_accumulate_sr<typename Src::Sr>(s_keys, s_vals, TBL, row, v); });
     if (more) src.pre_b(pre, w, NW);
     __syncthreads();
     // wave w owns slots [w * PER, (w + 1) * PER): count them, scan the waves'
@@ -880,7 +888,7 @@ __global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *l
     const int cw = count_run(s_keys, lo, hi);  // every lane of the wave takes part
     int total;
     const int ex = block_excl<NW>(l == 0 ? cw : 0, s_w, total);
-    compact_run<VT>(s_keys, s_vals, lo, hi, base + readlane(ex, 0), base + cap, out_ri, out_v);
+    compact_run<VT, typename Src::Sr>(s_keys, s_vals, lo, hi, base + readlane(ex, 0), base + cap, out_ri, out_v);
     if (more) src.pre_a(pre);
     if (threadIdx.x == 0 && total != cap) flag_error(status, 4);
     __syncthreads();
@@ -1225,7 +1233,7 @@ struct HvScratch {
 
 // pre: the wave's first chunk loaded ahead (same pbeg, pend, sa, sb, w, nw,
 // cs_min), or nullptr.
-template <class VT, class Ins>
+template <class VT, class Mul = SrPlusTimes, class Ins>
 __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t pbeg, int64_t pend, int sa, int sb, int w,
                                            int nw, int cs_min, HvScratch<VT> &sc, const HvPre<VT> *pre,
                                            Ins &&ins) {
@@ -1330,7 +1338,7 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t pbeg, in
           }
 #pragma unroll
           for (int u = 0; u < kHvPipe; u++)
-            if (own_[u] >= 0) ins(opaque(e_[u].row), (double)opaque(e_[u].v) * (double)inf_[u].b);
+            if (own_[u] >= 0) ins(opaque(e_[u].row), Mul::mul((double)opaque(e_[u].v), (double)inf_[u].b));
         }
         wave_sync();
       }
@@ -1358,7 +1366,7 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t pbeg, in
         }
 #pragma unroll
         for (int t = 0; t < kHvVec; t++)
-          if (e0 + t * kWave < sn) ins(opaque(ev[t].row), (double)opaque(ev[t].v) * sbv);
+          if (e0 + t * kWave < sn) ins(opaque(ev[t].row), Mul::mul((double)opaque(ev[t].v), sbv));
       }
       units += nblk;
     }
@@ -1379,8 +1387,9 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t pbeg, in
 constexpr int kHvThreads = 256;
 
 // Item source of the numeric pass: the product terms of column c0 + jj.
-template <class VT>
+template <class VT, class SR = SrPlusTimes>
 struct HvProductSrc {
+  using Sr = SR;
   HvArgs<VT> a;
   int64_t c0;
   int P;
@@ -1399,7 +1408,7 @@ struct HvProductSrc {
   template <class Ins>
   __device__ __forceinline__ int visit(int64_t lo, int64_t hi, int sa, int sb, int w, int nw, Scratch &sc,
                                        const Pre &pre, Ins &&ins) const {
-    return hv_traverse<VT>(a, lo, hi, sa, sb, w, nw, kCsMin, sc, &pre, ins);
+    return hv_traverse<VT, SR>(a, lo, hi, sa, sb, w, nw, kCsMin, sc, &pre, ins);
   }
 };
 
@@ -1517,7 +1526,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
         bad = src.visit(lo, hi, t, sb0, w, NW, s_sc[w], pre, [&](int32_t row, double v) {
           const uint32_t r = (uint32_t)row - rb;
           if (r < (uint32_t)kSlabRows) {
-            atomicAdd(&acc[r], v);
+            Src::Sr::acc(&acc[r], v);
             atomicOr(&bits[r >> 5], 1u << (r & 31));
           } else {
             outside = 1;
@@ -1531,7 +1540,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
         c = __popc(word);
       } else {
         bad = src.visit(lo, hi, t, sb0, w, NW, s_sc[w], pre, [&](int32_t row, double v) {
-          ht_accumulate_z(keys, vals, kHvSlots, row, v);
+          ht_accumulate_z<typename Src::Sr>(keys, vals, kHvSlots, row, v);
         });
         __syncthreads();
         // wave w owns slots [w * kSlotsPerWave, +kSlotsPerWave)
@@ -1563,7 +1572,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
             if (fits) {
               const int64_t q = o + mbcnt(mask);
               out_ri[q] = (int32_t)(rb + r);
-              out_v[q] = (VT)x;
+              out_v[q] = (VT)Src::Sr::out(x);
             }
           }
           o += __popcll(mask);
@@ -1583,7 +1592,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
             if (fits) {
               const int64_t d = o + mbcnt(mask);
               out_ri[d] = key - 1;
-              out_v[d] = (VT)x;
+              out_v[d] = (VT)Src::Sr::out(x);
             }
           }
           o += __popcll(mask);
@@ -1873,8 +1882,9 @@ __global__ __launch_bounds__(kMbThreads) __attribute__((amdgpu_waves_per_eu(8)))
 }
 
 // Item source of the merge: the bucket range of the item's slabs.
-template <class VT>
+template <class VT, class SR = SrPlusTimes>
 struct MbSrc {
+  using Sr = SR;
   const int32_t *brow;
   const VT *bval;
   const int32_t *soff;
@@ -1927,7 +1937,7 @@ constexpr int kHvWideSlabs = 4;
 constexpr int64_t kHvWideRows = kSlabRows * kHvWideSlabs;
 constexpr int kHvWideThreads = 1024;
 
-template <class VT>
+template <class VT, class SR>
 __global__ __launch_bounds__(kHvWideThreads) void k_hv_wide(HvArgs<VT> a, int64_t c0, const int32_t *list,
                                                             const int32_t *wlist, int64_t wcap, WsHeader *hdr,
                                                             const int64_t *c_colptr, int32_t *hv_cur,
@@ -1970,10 +1980,10 @@ __global__ __launch_bounds__(kHvWideThreads) void k_hv_wide(HvArgs<VT> a, int64_
     if (threadIdx.x < kWords) s_bits[threadIdx.x] = 0u;
     __syncthreads();
     int outside = 0;
-    int bad = hv_traverse<VT>(a, a.Bcp[col], a.Bcp[col + 1], sa, sb, w, NW, 1, s_sc[w], (const HvPre<VT> *)nullptr, [&](int32_t row, double v) {
+    int bad = hv_traverse<VT, SR>(a, a.Bcp[col], a.Bcp[col + 1], sa, sb, w, NW, 1, s_sc[w], (const HvPre<VT> *)nullptr, [&](int32_t row, double v) {
       const uint32_t r = (uint32_t)row - rb;
       if (r < (uint32_t)kHvWideRows) {
-        atomicAdd(&s_acc[r], v);
+        SR::acc(&s_acc[r], v);
         atomicOr(&s_bits[r >> 5], 1u << (r & 31));
       } else {
         outside = 1;
@@ -2001,7 +2011,7 @@ __global__ __launch_bounds__(kHvWideThreads) void k_hv_wide(HvArgs<VT> a, int64_
         if (occ) {
           const int64_t d = o + mbcnt(mask);
           out_ri[d] = (int32_t)(rb + r);
-          out_v[d] = (VT)s_acc[r];
+          out_v[d] = (VT)SR::out(s_acc[r]);
         }
         o += __popcll(mask);
       }
@@ -2037,7 +2047,7 @@ __global__ __launch_bounds__(256) void k_heavy_acc(Src src, const int32_t *list,
   uint8_t *df = flags + (int64_t)slot * m;
   // chunks of B(:,j) are shared by all waves of the group; rounds are split
   src.visit(jj, 0, 1, (int64_t)part * NW + w, (int64_t)parts * NW, s_sc[w], status, [&](int32_t row, double v) {
-    atomicAdd(&dv[row], v);
+    Src::Sr::acc(&dv[row], v);
     df[row] = 1;
   });
 }
@@ -2061,7 +2071,7 @@ __global__ __launch_bounds__(256) void k_heavy_count(int nslots, int64_t m, int6
 }
 
 // Ordered compaction of one segment of a heavy column; resets its slots.
-template <class VT>
+template <class VT, class SR>
 __global__ __launch_bounds__(256) void k_heavy_write(const int32_t *list, int first, int nslots, int64_t m,
                                                      int64_t nseg, double *vals, uint8_t *flags,
                                                      const int64_t *segcnt, const int64_t *c_colptr,
@@ -2111,7 +2121,7 @@ __global__ __launch_bounds__(256) void k_heavy_write(const int32_t *list, int fi
         const int64_t r = my0 + i;
         if (o < cap) {
           out_ri[cbase + o] = (int32_t)r;
-          out_v[cbase + o] = (VT)dv[r];
+          out_v[cbase + o] = (VT)SR::out(dv[r]);
         }
         o++;
         dv[r] = 0.0;
@@ -2504,7 +2514,7 @@ static int accumulate_pass(const Src &src, const int *cnt, const WsHeader &h, co
                                                 "num_block10240"};
   static const char *kMrgNames[kNumBins - 1] = {"mrg_wave64", "mrg_wave256", "mrg_wave1024", "mrg_block4096",
                                                 "mrg_block10240"};
-  const char *const *names = std::is_same<Src, MergeSrc<VT>>::value ? kMrgNames : kNumNames;
+  const char *const *names = Src::kMerge ? kMrgNames : kNumNames;
   for (int b = 0; b < kNumBins - 1; b++) {
     if (cnt[b] == 0) continue;
     ProfScope prof(names[b], st);
@@ -2548,7 +2558,7 @@ static int accumulate_pass(const Src &src, const int *cnt, const WsHeader &h, co
       LAUNCHCHK();
       hipLaunchKernelGGL(k_heavy_count, dim3((unsigned)(ns * L.nseg)), dim3(256), 0, st, ns, L.m, L.nseg, flags, segcnt);
       LAUNCHCHK();
-      hipLaunchKernelGGL((k_heavy_write<VT>), dim3((unsigned)(ns * L.nseg)), dim3(256), 0, st, list, first, ns, L.m,
+      hipLaunchKernelGGL((k_heavy_write<VT, typename Src::Sr>), dim3((unsigned)(ns * L.nseg)), dim3(256), 0, st, list, first, ns, L.m,
                          L.nseg, vals, flags, segcnt, c_colptr, out_ri, out_v, status);
       LAUNCHCHK();
     }
@@ -2556,7 +2566,7 @@ static int accumulate_pass(const Src &src, const int *cnt, const WsHeader &h, co
   return SPGEMM_OK;
 }
 
-template <class VT>
+template <class VT, class SR>
 static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t ncol, int64_t klo,
                          int64_t khi, const int64_t *c_colptr, int32_t *c_rowidx, void *c_values, const WsLayout &L,
                          char *ws, hipStream_t st, bool sync, bool keep_status = false) {
@@ -2573,7 +2583,7 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
   WsHeader h;
   int rc = bin_counts(hdr, st, sync, cnt, &h);
   if (rc) return rc;
-  ProductSrc<VT> src;
+  ProductSrc<VT, SR> src;
   src.a = product_args<VT>(A, B, klo, khi);
   src.c0 = c0;
   const bool slabs = L.P > 0;
@@ -2640,13 +2650,13 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
       }
       {
         ProfScope prof("heavy_wide", st);
-        hipLaunchKernelGGL(k_hv_wide<VT>, dim3(device_cus()), dim3(kHvWideThreads), 0, st, ha, c0, list,
+        hipLaunchKernelGGL((k_hv_wide<VT, SR>), dim3(device_cus()), dim3(kHvWideThreads), 0, st, ha, c0, list,
                            (const int32_t *)wlist, ncol, hdr, c_colptr, hv_cur, c_rowidx, (VT *)c_values);
         LAUNCHCHK();
       }
       ProfScope prof("heavy_items", st);
-      HvProductSrc<VT> hsrc{ha, c0, (int)L.P};
-      hipLaunchKernelGGL((k_hv_items<VT, HvProductSrc<VT>>), dim3(4 * device_cus()), dim3(kHvThreads), 0, st, hsrc, list,
+      HvProductSrc<VT, SR> hsrc{ha, c0, (int)L.P};
+      hipLaunchKernelGGL((k_hv_items<VT, HvProductSrc<VT, SR>>), dim3(4 * device_cus()), dim3(kHvThreads), 0, st, hsrc, list,
                          (const uint32_t *)slots, h0, h1 - h0, hdr, c_colptr, hv_cur, c_rowidx, (VT *)c_values);
       LAUNCHCHK();
     }
@@ -2657,7 +2667,7 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
   return SPGEMM_OK;
 }
 
-template <class VT>
+template <class VT, class SR>
 static int merge_typed(const spgemm_csc *parts, int32_t n_parts, const int64_t *c_colptr, int32_t *c_rowidx,
                        void *c_values, const WsLayout &L, char *ws, hipStream_t st) {
   WsHeader *hdr = (WsHeader *)ws;
@@ -2682,7 +2692,7 @@ static int merge_typed(const spgemm_csc *parts, int32_t n_parts, const int64_t *
   WsHeader h;
   int rc = bin_counts(hdr, st, true, cnt, &h);
   if (rc) return rc;
-  MergeSrc<VT> src;
+  MergeSrc<VT, SR> src;
   src.P = pd;
   src.nparts = n_parts;
   src.m = L.m;
@@ -2732,8 +2742,8 @@ static int merge_typed(const spgemm_csc *parts, int32_t n_parts, const int64_t *
       LAUNCHCHK();
     }
     ProfScope prof("merge_items", st);
-    MbSrc<VT> msrc{brow, bval, soff, base, h0, (int)L.P};
-    hipLaunchKernelGGL((k_hv_items<VT, MbSrc<VT>>), dim3(4 * device_cus()), dim3(kHvThreads), 0, st, msrc, list,
+    MbSrc<VT, SR> msrc{brow, bval, soff, base, h0, (int)L.P};
+    hipLaunchKernelGGL((k_hv_items<VT, MbSrc<VT, SR>>), dim3(4 * device_cus()), dim3(kHvThreads), 0, st, msrc, list,
                        (const uint32_t *)slots, h0, h1 - h0, hdr, c_colptr, hv_cur, c_rowidx, (VT *)c_values);
     LAUNCHCHK();
     h0 = h1;
@@ -2780,6 +2790,33 @@ static_assert(sizeof(WsHeader) <= 2048, "header too large");
 
 }  // namespace spg
 
+namespace spg {
+// The numeric pass for the dtype of A and a semiring (keep_status: a
+// layer's call keeps the status its share of B may have set).
+static int numeric_dispatch(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t ncol, int64_t klo,
+                            int64_t khi, const int64_t *c_colptr, int32_t *c_rowidx, void *c_values, int32_t semiring,
+                            const WsLayout &L, char *ws, hipStream_t s, bool keep_status) {
+  const bool f32 = A->dtype == SPGEMM_F32;
+  switch (semiring) {
+    case SPGEMM_SR_MIN_PLUS:
+      return f32 ? numeric_typed<float, SrMinPlus>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, ws, s,
+                                                   true, keep_status)
+                 : numeric_typed<double, SrMinPlus>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, ws, s,
+                                                    true, keep_status);
+    case SPGEMM_SR_OR_AND:
+      return f32 ? numeric_typed<float, SrOrAnd>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, ws, s,
+                                                 true, keep_status)
+                 : numeric_typed<double, SrOrAnd>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, ws, s,
+                                                  true, keep_status);
+    default:
+      return f32 ? numeric_typed<float, SrPlusTimes>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, ws,
+                                                     s, true, keep_status)
+                 : numeric_typed<double, SrPlusTimes>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, ws,
+                                                      s, true, keep_status);
+  }
+}
+}  // namespace spg
+
 using namespace spg;
 
 extern "C" {
@@ -2823,7 +2860,8 @@ int spgemm_symbolic(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_
 
 int spgemm_numeric(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t c1, int32_t layer,
                    int32_t n_layers, const int64_t *flops, const int64_t *c_colptr, int32_t *c_rowidx,
-                   void *c_values, void *ws, size_t ws_bytes, void *stream) {
+                   void *c_values, int32_t semiring, void *ws, size_t ws_bytes, void *stream) {
+  if (semiring < SPGEMM_SR_PLUS_TIMES || semiring > SPGEMM_SR_OR_AND) return SPGEMM_E_INVAL;
   (void)flops;
   int st = check_csc(A, true);
   if (!st) st = check_csc(B, true);
@@ -2852,25 +2890,19 @@ int spgemm_numeric(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t
                        1);
     LAUNCHCHK();
     spgemm_csc Bl;
-    if (A->dtype == SPGEMM_F32) {
-      st = build_layer<float>(B, c0, ncol, klo, khi, kdim, true, L, (char *)ws, s, &Bl);
-      if (st) return st;
-      return numeric_typed<float>(A, &Bl, 0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, (char *)ws, s, true,
-                                  true);
-    }
-    st = build_layer<double>(B, c0, ncol, klo, khi, kdim, true, L, (char *)ws, s, &Bl);
+    st = A->dtype == SPGEMM_F32 ? build_layer<float>(B, c0, ncol, klo, khi, kdim, true, L, (char *)ws, s, &Bl)
+                                : build_layer<double>(B, c0, ncol, klo, khi, kdim, true, L, (char *)ws, s, &Bl);
     if (st) return st;
-    return numeric_typed<double>(A, &Bl, 0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, (char *)ws, s, true,
-                                 true);
+    return numeric_dispatch(A, &Bl, 0, ncol, klo, khi, c_colptr, c_rowidx, c_values, semiring, L, (char *)ws, s,
+                            true);
   }
-  if (A->dtype == SPGEMM_F32)
-    return numeric_typed<float>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, (char *)ws, s, true);
-  return numeric_typed<double>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, (char *)ws, s, true);
+  return numeric_dispatch(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, semiring, L, (char *)ws, s, false);
 }
 
 int spgemm_merge(const spgemm_csc *parts, int32_t n_parts, const int64_t *c_colptr, int32_t *c_rowidx,
-                 void *c_values, void *ws, size_t ws_bytes, void *stream) {
+                 void *c_values, int32_t semiring, void *ws, size_t ws_bytes, void *stream) {
   if (!parts || n_parts < 1 || n_parts > kMaxParts) return SPGEMM_E_INVAL;
+  if (semiring < SPGEMM_SR_PLUS_TIMES || semiring > SPGEMM_SR_OR_AND) return SPGEMM_E_INVAL;
   for (int p = 0; p < n_parts; p++) {
     int st = check_csc(&parts[p], true);
     if (st) return st;
@@ -2889,8 +2921,19 @@ int spgemm_merge(const spgemm_csc *parts, int32_t n_parts, const int64_t *c_colp
     return SPGEMM_OK;
   }
   hipStream_t s = (hipStream_t)stream;
-  if (parts[0].dtype == SPGEMM_F32) return merge_typed<float>(parts, n_parts, c_colptr, c_rowidx, c_values, L, (char *)ws, s);
-  return merge_typed<double>(parts, n_parts, c_colptr, c_rowidx, c_values, L, (char *)ws, s);
+  const bool f32 = parts[0].dtype == SPGEMM_F32;
+  char *w = (char *)ws;
+  switch (semiring) {
+    case SPGEMM_SR_MIN_PLUS:
+      return f32 ? merge_typed<float, SrMinPlus>(parts, n_parts, c_colptr, c_rowidx, c_values, L, w, s)
+                 : merge_typed<double, SrMinPlus>(parts, n_parts, c_colptr, c_rowidx, c_values, L, w, s);
+    case SPGEMM_SR_OR_AND:
+      return f32 ? merge_typed<float, SrOrAnd>(parts, n_parts, c_colptr, c_rowidx, c_values, L, w, s)
+                 : merge_typed<double, SrOrAnd>(parts, n_parts, c_colptr, c_rowidx, c_values, L, w, s);
+    default:
+      return f32 ? merge_typed<float, SrPlusTimes>(parts, n_parts, c_colptr, c_rowidx, c_values, L, w, s)
+                 : merge_typed<double, SrPlusTimes>(parts, n_parts, c_colptr, c_rowidx, c_values, L, w, s);
+  }
 }
 
 int spgemm_colptr(const int64_t *counts, int64_t n, int64_t *colptr_out, void *ws, size_t ws_bytes, void *stream) {
@@ -2938,8 +2981,10 @@ int spgemm_batched_forward(const spgemm_csc *A, const spgemm_csc *B, int64_t nnz
   LAUNCHCHK();
   // the numeric pass keeps the status word, so an overflow found above is reported
   if (A->dtype == SPGEMM_F32)
-    return numeric_typed<float>(A, B, 0, n, 0, A->ncols, c_colptr, c_rowidx, c_values, L, w, s, false, true);
-  return numeric_typed<double>(A, B, 0, n, 0, A->ncols, c_colptr, c_rowidx, c_values, L, w, s, false, true);
+    return numeric_typed<float, SrPlusTimes>(A, B, 0, n, 0, A->ncols, c_colptr, c_rowidx, c_values, L, w, s, false,
+                                             true);
+  return numeric_typed<double, SrPlusTimes>(A, B, 0, n, 0, A->ncols, c_colptr, c_rowidx, c_values, L, w, s, false,
+                                            true);
 }
 
 int spgemm_batched_forward_noalloc(const spgemm_csc *A, const spgemm_csc *B, int64_t nnz_cap, int64_t *flops_out,

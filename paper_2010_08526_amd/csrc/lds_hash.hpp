@@ -32,16 +32,32 @@ __device__ __forceinline__ void ht_accumulate(int32_t *keys, double *vals, uint3
   }
 }
 
-// As ht_accumulate on a table whose free slots hold 0: keys are stored as
-// key + 1 (key < INT32_MAX), so an all-zero table is empty and a pass that
-// reads the table out can leave it empty by writing zeros.
+// As ht_accumulate, combining values with the addition of semiring SR
+// (SR::acc on the slot; slots start all zero).
+template <class SR>
+__device__ __forceinline__ void ht_accumulate_sr(int32_t *keys, double *vals, uint32_t T, int32_t key, double v) {
+  uint32_t h = hash_slot(key, T);
+  for (uint32_t probe = 0; probe < T; probe++) {
+    const int32_t old = atomicCAS(&keys[h], kEmpty, key);
+    if (old == kEmpty || old == key) {
+      SR::acc(&vals[h], v);
+      return;
+    }
+    h = (h + 1 == T) ? 0 : h + 1;
+  }
+}
+
+// As ht_accumulate_sr on a table whose free slots hold 0: keys are stored
+// as key + 1 (key < INT32_MAX), so an all-zero table is empty and a pass
+// that reads the table out can leave it empty by writing zeros.
+template <class SR>
 __device__ __forceinline__ void ht_accumulate_z(int32_t *keys, double *vals, uint32_t T, int32_t key, double v) {
   const int32_t kk = key + 1;
   uint32_t h = hash_slot(key, T);
   for (uint32_t probe = 0; probe < T; probe++) {
     const int32_t old = atomicCAS(&keys[h], 0, kk);
     if (old == 0 || old == kk) {
-      atomicAdd(&vals[h], v);
+      SR::acc(&vals[h], v);
       return;
     }
     h = (h + 1 == T) ? 0 : h + 1;

@@ -128,26 +128,34 @@ def test_symbolic_validation_before_launch():
 def test_numeric_and_merge_validation_before_launch():
     A, B = FakeCSC(10, 8, 5), FakeCSC(8, 7, 5, dtype=S.F64)
     lib = S._lib
-    r = lib.spgemm_numeric(ctypes.byref(A.d), ctypes.byref(B.d), 0, 7, 0, 1, None, 0x1, 0x1, 0x1, 0x10000, 1 << 30,
+    r = lib.spgemm_numeric(ctypes.byref(A.d), ctypes.byref(B.d), 0, 7, 0, 1, None, 0x1, 0x1, 0x1, 0, 0x10000, 1 << 30,
                            None)
     assert r == S.E_DTYPE  # mixed dtypes
     B2 = FakeCSC(8, 7, 5)
-    r = lib.spgemm_numeric(ctypes.byref(A.d), ctypes.byref(B2.d), 0, 7, 2, 2, None, 0x1, 0x1, 0x1, 0x10000, 1 << 30,
+    r = lib.spgemm_numeric(ctypes.byref(A.d), ctypes.byref(B2.d), 0, 7, 2, 2, None, 0x1, 0x1, 0x1, 0, 0x10000, 1 << 30,
                            None)
     assert r == S.E_INVAL  # layer >= n_layers
     noval = FakeCSC(10, 8, 5, values=False)
-    r = lib.spgemm_numeric(ctypes.byref(noval.d), ctypes.byref(B2.d), 0, 7, 0, 1, None, 0x1, 0x1, 0x1, 0x10000,
+    r = lib.spgemm_numeric(ctypes.byref(noval.d), ctypes.byref(B2.d), 0, 7, 0, 1, None, 0x1, 0x1, 0x1, 0, 0x10000,
                            1 << 30, None)
     assert r == S.E_INVAL  # numeric needs values
     r = lib.spgemm_numeric(ctypes.byref(A.d), ctypes.byref(FakeCSC(8, 7, 5, dtype=7).d), 0, 7, 0, 1, None, 0x1, 0x1,
-                           0x1, 0x10000, 1 << 30, None)
+                           0x1, 0, 0x10000, 1 << 30, None)
     assert r == S.E_DTYPE
+    for sr in (-1, 3):  # not a semiring
+        assert lib.spgemm_numeric(ctypes.byref(A.d), ctypes.byref(B2.d), 0, 7, 0, 1, None, 0x1, 0x1, 0x1, sr,
+                                  0x10000, 1 << 30, None) == S.E_INVAL
+        ok = (S.spgemm_csc * 2)(FakeCSC(10, 4, 3).d, FakeCSC(10, 4, 3).d)
+        assert lib.spgemm_merge(ok, 2, 0x1, 0x1, 0x1, sr, 0x10000, 1 << 30, None) == S.E_INVAL
+    with pytest.raises(ValueError):
+        S.semiring_id("max_times")
+    assert [S.semiring_id(x) for x in ("plus_times", "min_plus", "or_and", 2)] == [0, 1, 2, 2]
     parts = (S.spgemm_csc * 2)(FakeCSC(10, 4, 3).d, FakeCSC(10, 5, 3).d)
-    assert lib.spgemm_merge(parts, 2, 0x1, 0x1, 0x1, 0x10000, 1 << 30, None) == S.E_SHAPE
-    assert lib.spgemm_merge(parts, 0, 0x1, 0x1, 0x1, 0x10000, 1 << 30, None) == S.E_INVAL
-    assert lib.spgemm_merge(parts, 4097, 0x1, 0x1, 0x1, 0x10000, 1 << 30, None) == S.E_INVAL
+    assert lib.spgemm_merge(parts, 2, 0x1, 0x1, 0x1, 0, 0x10000, 1 << 30, None) == S.E_SHAPE
+    assert lib.spgemm_merge(parts, 0, 0x1, 0x1, 0x1, 0, 0x10000, 1 << 30, None) == S.E_INVAL
+    assert lib.spgemm_merge(parts, 4097, 0x1, 0x1, 0x1, 0, 0x10000, 1 << 30, None) == S.E_INVAL
     parts = (S.spgemm_csc * 2)(FakeCSC(10, 4, 3).d, FakeCSC(10, 4, 3, dtype=S.F64).d)
-    assert lib.spgemm_merge(parts, 2, 0x1, 0x1, 0x1, 0x10000, 1 << 30, None) == S.E_DTYPE
+    assert lib.spgemm_merge(parts, 2, 0x1, 0x1, 0x1, 0, 0x10000, 1 << 30, None) == S.E_DTYPE
     assert lib.spgemm_colptr(0x1, -1, 0x1, 0x10000, 1 << 20, None) == S.E_INVAL
     assert lib.spgemm_colptr(0x1, 10, None, 0x10000, 1 << 20, None) == S.E_INVAL
     assert lib.spgemm_colptr(0x1, 10, 0x1, 0x10000, 8, None) == S.E_WORKSPACE
@@ -309,3 +317,17 @@ def test_noalloc_forward_refuses_inputs_beyond_its_scratch():
                                               0x1, 0x1, 0x1, None) == S.E_SHAPE
     assert lib.spgemm_batched_forward_noalloc(ctypes.byref(A.d), ctypes.byref(FakeCSC(n, n, 5, dtype=S.F64).d), 10,
                                               0x1, 0x1, 0x1, 0x1, 0x1, None) == S.E_DTYPE
+
+
+def test_sort_validation_before_launch():
+    lib = S._lib
+    C = FakeCSC(100, 10, 5)
+    need = ctypes.c_size_t()
+    assert lib.spgemm_workspace_size(S.OP_SORT, ctypes.byref(C.d), None, 0, 0, 1, ctypes.byref(need)) == S.OK
+    assert need.value >= 4096 + 3 * 4 * 10
+    assert lib.spgemm_sort_columns(ctypes.byref(C.d), 0x2000, 0x9000, 0x10000, 1 << 20, None) == S.E_INVAL  # in place
+    assert lib.spgemm_sort_columns(ctypes.byref(C.d), 0x8000, 0x3000, 0x10000, 1 << 20, None) == S.E_INVAL
+    assert lib.spgemm_sort_columns(ctypes.byref(C.d), None, 0x9000, 0x10000, 1 << 20, None) == S.E_INVAL
+    assert lib.spgemm_sort_columns(ctypes.byref(C.d), 0x8000, 0x9000, 0x10000, 16, None) == S.E_WORKSPACE
+    assert lib.spgemm_sort_columns(ctypes.byref(FakeCSC(100, 10, 5, values=False).d), 0x8000, 0x9000, 0x10000,
+                                   1 << 20, None) == S.E_INVAL
