@@ -1311,6 +1311,27 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t pbeg, in
         int rf = (r0 - g) % r_stride;
         if (rf < 0) rf += r_stride;
         for (int r = g + rf; r < gend; r += kHvPipe * r_stride) {
+          const int rl = r + (kHvPipe - 1) * r_stride;  // the group's last round
+          if (rl < gend && (rl + 1) * kWave <= total) {  // uniform: every lane of every round holds an element
+            int own_[kHvPipe];
+#pragma unroll
+            for (int u = 0; u < kHvPipe; u++) {
+              const int ru = r + u * r_stride;
+              const uint64_t m = sc.rmask[ru - g];
+              const int carry = __popcll(__ballot(ls > 0 && excl < ru * kWave));
+              own_[u] = carry + mbcnt(m) + (int)((m >> l) & 1ull) - 1;
+            }
+            SegInfo<VT> inf_[kHvPipe];
+#pragma unroll
+            for (int u = 0; u < kHvPipe; u++) inf_[u] = sc.info[own_[u]];
+            SlabEnt<VT> e_[kHvPipe];
+#pragma unroll
+            for (int u = 0; u < kHvPipe; u++) e_[u] = a.ent[inf_[u].offm + (uint32_t)((r + u * r_stride) * kWave + l)];
+#pragma unroll
+            for (int u = 0; u < kHvPipe; u++)
+              ins(opaque(e_[u].row), Mul::mul((double)opaque(e_[u].v), (double)inf_[u].b));
+            continue;
+          }
           int own_[kHvPipe];
 #pragma unroll
           for (int u = 0; u < kHvPipe; u++) {
@@ -1356,6 +1377,14 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t pbeg, in
       if (b0 < 0) b0 += r_stride;
       for (int blk = b0; blk < nblk; blk += r_stride) {
         const int e0 = blk * kHvBlk + l;
+        if ((blk + 1) * kHvBlk <= sn) {  // uniform: a whole block
+          SlabEnt<VT> ev[kHvVec];
+#pragma unroll
+          for (int t = 0; t < kHvVec; t++) ev[t] = a.ent[so + e0 + t * kWave];
+#pragma unroll
+          for (int t = 0; t < kHvVec; t++) ins(opaque(ev[t].row), Mul::mul((double)opaque(ev[t].v), sbv));
+          continue;
+        }
         SlabEnt<VT> ev[kHvVec];
 #pragma unroll
         for (int t = 0; t < kHvVec; t++) {
@@ -1426,7 +1455,11 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
   static_assert(kSlotsPerWave % kWave == 0, "hash slots split evenly over waves");
   static_assert(kWords <= kHvThreads, "one bitmap word per thread");
   static_assert(kHvSlots * 12 <= kSlabRows * 8, "hash table fits the dense array");
-  __shared__ __align__(16) unsigned char s_tab[kSlabRows * 8 + kSlabRows / 8];
+  // dense items: float64 rows, a spare row, the occupancy bitmap and a spare
+  // word (rows outside the slab go to the spares, so the insert needs no
+  // branch; the spares are never read out)
+  constexpr int kBitsOff = (int)kSlabRows * 8 + 16;
+  __shared__ __align__(16) unsigned char s_tab[kBitsOff + kSlabRows / 8 + 16];
   __shared__ typename Src::Scratch s_sc[NW];
   __shared__ int s_batch;
   __shared__ uint32_t s_e[kWave];
@@ -1442,7 +1475,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
   const int64_t nb = (hc + kWave - 1) / kWave;
   const int64_t nbatch = nb * P;
   double *acc = (double *)s_tab;
-  uint32_t *bits = (uint32_t *)(s_tab + kSlabRows * 8);
+  uint32_t *bits = (uint32_t *)(s_tab + kBitsOff);
   int32_t *keys = (int32_t *)s_tab;  // hash items: key = row + 1, 0 = free
   double *vals = (double *)(s_tab + kHvSlots * 4);
   // The table is all zero between items: cleared once here, and every
@@ -1524,13 +1557,12 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
       if (dense) {
         int outside = 0;
         bad = src.visit(lo, hi, t, sb0, w, NW, s_sc[w], pre, [&](int32_t row, double v) {
-          const uint32_t r = (uint32_t)row - rb;
-          if (r < (uint32_t)kSlabRows) {
-            Src::Sr::acc(&acc[r], v);
-            atomicOr(&bits[r >> 5], 1u << (r & 31));
-          } else {
-            outside = 1;
-          }
+          const uint32_t r0 = (uint32_t)row - rb;
+          const bool in = r0 < (uint32_t)kSlabRows;
+          const uint32_t r = in ? r0 : (uint32_t)kSlabRows;  // the spare row
+          outside |= in ? 0 : 1;
+          Src::Sr::acc(&acc[r], v);
+          atomicOr(&bits[r >> 5], 1u << (r & 31));
         });
         bad |= outside;
         __syncthreads();
