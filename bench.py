@@ -54,8 +54,10 @@ def _parse():
     p.add_argument("--protein-n", type=int, default=2_000_000)
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--no-extras", action="store_true", help="skip the fwd_bwd, batched, layered, bsweep, prune and aat sections")
-    p.add_argument("--extras", default="fwd_bwd,batched,layered,bsweep,prune,aat", help="comma-separated extra sections to run")
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the fwd_bwd, batched, layered, bsweep, prune, aat and sorted sections")
+    p.add_argument("--extras", default="fwd_bwd,batched,layered,bsweep,prune,aat,sorted",
+                   help="comma-separated extra sections to run")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain device copy of known size (to scale HBM byte counters) and exit")
     return p.parse_args()
@@ -235,6 +237,21 @@ def fwd_bwd(args, torch, np, S, synth):
         bw.refresh_values(B)
         bw(dC)
 
+    # the differentiated form as autograd runs it: SpGEMMFn's forward (a new
+    # engine: symbolic pass, plan, numeric) and its backward, which forms the
+    # transposes of A's, B's and C's patterns on every call
+    a_vals = A.values.clone().requires_grad_(True)
+    b_vals = B.values.clone().requires_grad_(True)
+    Ap = S.CSC(A.nrows, A.ncols, A.colptr, A.rowidx, None)
+    Bp = S.CSC(B.nrows, B.ncols, B.colptr, B.rowidx, None)
+
+    def fwdbwd_autograd():
+        c_vals, _, _ = S.SpGEMMFn.apply(a_vals, b_vals, Ap, Bp)
+        loss = 0.5 * ((c_vals - T) ** 2).sum()
+        a_vals.grad = None
+        b_vals.grad = None
+        loss.backward()
+
     import paper_2010_08526_amd.batched as Bt
     be = Bt.BatchedEngine(A, B, backward=True)
     be.forward()
@@ -246,11 +263,12 @@ def fwd_bwd(args, torch, np, S, synth):
         be.forward()
         be.backward((be.values[:be.nnz_c] - Tf).contiguous())
 
-    fwd(); fwdbwd(); fwd_fused()
+    fwd(); fwdbwd(); fwd_fused(); fwdbwd_autograd()
     reps = max(3, args.steps)
     t_f = _timed(fwd, reps, torch)
     t_fb = _timed(fwdbwd, reps, torch)
     t_ff = _timed(fwd_fused, reps, torch)
+    t_fa = _timed(fwdbwd_autograd, reps, torch)
     bw.check()
     be.check()
     out = {"workload": f"er{args.er_n}: A, B independent Erdos-Renyi n={args.er_n}, 16 per column, fp32 N(0,1); "
@@ -259,10 +277,16 @@ def fwd_bwd(args, torch, np, S, synth):
            "forward_ms": round(t_f * 1e3, 3), "forward_GFLOPs": round(2 * flops / t_f / 1e9, 2),
            "fwd_bwd_ms": round(t_fb * 1e3, 3), "fwd_bwd_GFLOPs": round(6 * flops / t_fb / 1e9, 2),
            "fwd_bwd_fused_ms": round(t_ff * 1e3, 3), "fwd_bwd_fused_GFLOPs": round(6 * flops / t_ff / 1e9, 2),
+           "fwd_bwd_autograd_ms": round(t_fa * 1e3, 3), "fwd_bwd_autograd_GFLOPs": round(6 * flops / t_fa / 1e9, 2),
            "fwd_bwd_over_fwd_time": round(t_fb / t_f, 3),
-           "note": "fwd_bwd = forward + transpose-based backward (dA via B^T, dC^T); fused = graph-capturable "
-                   "forward + one-pass backward (float64 atomics for dA); GFLOP/s counts 3x forward flops"}
-    log(f"fwd_bwd: fwd {t_f * 1e3:.2f} ms, fwd+bwd {t_fb * 1e3:.2f} ms, fused {t_ff * 1e3:.2f} ms")
+           "fwd_bwd_autograd_over_fwd_time": round(t_fa / t_f, 3),
+           "note": "fwd_bwd = forward + transpose-based backward (dA via B^T, dC^T) with the pattern transposes of "
+                   "A, B and C made once per structure (outside the step); fwd_bwd_autograd = SpGEMMFn forward + "
+                   "loss + backward through torch.autograd, every transpose (A, B, C patterns) and permutation "
+                   "formed inside the step; fused = graph-capturable forward + one-pass backward (float64 atomics "
+                   "for dA, no transposes); GFLOP/s counts 3x forward flops"}
+    log(f"fwd_bwd: fwd {t_f * 1e3:.2f} ms, fwd+bwd {t_fb * 1e3:.2f} ms, autograd {t_fa * 1e3:.2f} ms, "
+        f"fused {t_ff * 1e3:.2f} ms")
     return out
 
 
@@ -320,7 +344,14 @@ def layered(args, torch, np, S, synth):
            "phases_ms": {k: round(v, 3) for k, v in ph.items()},
            "kernels_ms": {k: round(v[0], 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
            "numeric_GBps_compulsory": round(num_bytes / (ph["numeric"] / 1e3) / 1e9, 2),
-           "merge_GBps_compulsory": round(merge_bytes / (ph["merge"] / 1e3) / 1e9, 2)}
+           "merge_GBps_compulsory": round(merge_bytes / (ph["merge"] / 1e3) / 1e9, 2),
+           "roofline_merge": {"bound": "hbm", "phase": "merge (all batches)",
+                              "achieved": round(merge_bytes / (ph["merge"] / 1e3) / 1e9, 2), "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s",
+                              "frac": round(merge_bytes / (ph["merge"] / 1e3) / 1e9 / HBM_PEAK_GBS, 5),
+                              "bytes": merge_bytes,
+                              "bytes_unit": "r*(sum of the partials' entries) read + r*nnz(C) written + 8 per column "
+                                            "per partial and output (compulsory)"}}
     log(f"layered: {pl.nbatches} batches, {t_total * 1e3:.1f} ms, phases " +
         ", ".join(f"{k}={v:.1f}ms" for k, v in ph.items()) + "; kernels " +
         ", ".join(f"{k}={v[0]:.1f}ms" for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])[:12]))
@@ -383,6 +414,16 @@ def batched(args, torch, np, S, synth):
            "fwd_bwd_over_fwd_time": round(t_graph_fb / t_graph, 3),
            "fwd_bwd_note": "graph of forward + fused backward with dC = C; GFLOP/s counts 3x forward flops",
            "autotuned_caps": tune["caps"]}
+    # compulsory bytes of one replay of the forward: the symbolic and the
+    # numeric pass each read the stored inputs once (r bytes per entry of A
+    # and B), the numeric pass writes C (r per entry) and its column pointers
+    r = 8
+    fwd_bytes = 2 * r * (A.nnz + B.nnz) + r * nnz_c + 8 * (B.ncols + 1)
+    out["roofline_forward"] = {"bound": "hbm", "phase": "batched forward (one graph replay)",
+                               "achieved": round(fwd_bytes / t_graph / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(fwd_bytes / t_graph / 1e9 / HBM_PEAK_GBS, 5), "bytes": fwd_bytes,
+                               "bytes_unit": "symbolic and numeric passes each reading A and B once (r per entry), "
+                                             "C written once (r per entry) and its column pointers (compulsory)"}
     log(f"batched: graph {t_graph * 1e3:.1f} ms vs plain loop {t_plain * 1e3:.1f} ms; fwd+bwd graph "
         f"{t_graph_fb * 1e3:.1f} ms")
     return out
@@ -618,6 +659,56 @@ def prune(args, torch, np, S, synth):
             "frac_of_hbm_peak": None if gbs is None else round(gbs / 8000.0, 4)}
 
 
+def sorted_output(args, torch, np, S, synth):
+    """Row-sorted output columns (the paper keeps its final Merge-Fiber
+    output sorted): the headline product in 16 column batches with every
+    batch sorted into a second buffer, against the unsorted product; and the
+    sort pass alone on each batch (kernel time from the library's HIP
+    events, compulsory bytes: every entry read and written once, r bytes)."""
+    dev = torch.device("cuda:0")
+    A = synth.rmat(args.scale, 16, synth.WORKLOADS["rmat20"].seed, dtype=torch.float32, device=dev)
+    res = {}
+    for sorted_flag in (False, True):
+        eng = S.Engine(A, A, 1, budget_bytes=1 << 62, sorted_output=sorted_flag)
+        plan = eng.plan()
+        bounds = np.linspace(0, A.ncols, 16 + 1).astype(np.int64)
+        # the same column ranges in both runs: 16 even column ranges (the
+        # sorted run holds each batch twice, so batches are kept small)
+        plan.bounds = bounds.tolist()
+        plan.batch_nnz = np.stack([plan.nnz_host[:, a:b].sum(1) for a, b in zip(bounds[:-1], bounds[1:])])
+
+        def step():
+            for i in range(plan.nbatches):
+                eng.run_batch(plan, i)
+
+        step()
+        torch.cuda.synchronize()
+        eng.check()
+        S.profile_enable(True)
+        t = _timed(step, 1, torch)
+        prof = S.profile_report()
+        S.profile_enable(False)
+        eng.check()
+        res["sorted" if sorted_flag else "unsorted"] = (t, prof.get("sort_columns", (0.0, 0))[0], plan)
+        del eng
+        torch.cuda.empty_cache()
+    t_u, _, pl = res["unsorted"]
+    t_s, sort_ms, _ = res["sorted"]
+    nnz_c = int(pl.nnz_host[0].sum())
+    sort_bytes = 2 * 8 * nnz_c + 8 * (A.ncols + pl.nbatches)
+    gbs = sort_bytes / (sort_ms * 1e-3) / 1e9 if sort_ms > 0 else None
+    log(f"sorted: numeric unsorted {t_u * 1e3:.1f} ms, sorted {t_s * 1e3:.1f} ms (sort pass {sort_ms:.1f} ms, "
+        f"{gbs:.0f} GB/s compulsory)")
+    return {"workload": "rmat20 headline product, numeric phase over 16 even column batches, with and without the "
+                        "row-sorting pass after each batch",
+            "batches": pl.nbatches, "nnz_C": nnz_c,
+            "numeric_unsorted_ms": round(t_u * 1e3, 3), "numeric_sorted_ms": round(t_s * 1e3, 3),
+            "sort_pass_ms": round(sort_ms, 3), "sorted_over_unsorted_time": round(t_s / t_u, 3),
+            "sort_compulsory_bytes": sort_bytes,
+            "sort_achieved_GBps": None if gbs is None else round(gbs, 1),
+            "sort_frac_of_hbm_peak": None if gbs is None else round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def main():
     args = _parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -638,7 +729,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_extras:
         for name, fn in (("fwd_bwd", fwd_bwd), ("batched", batched), ("layered", layered), ("bsweep", bsweep),
-                         ("prune", prune), ("aat", aat)):
+                         ("prune", prune), ("aat", aat), ("sorted", sorted_output)):
             if name in args.extras.split(","):
                 res[name] = fn(args, torch, np, S, synth)
                 torch.cuda.empty_cache()

@@ -170,9 +170,11 @@ int spgemm_colptr(const int64_t *counts, int64_t n, int64_t *colptr_out, void *w
  * which must come from the matching symbolic counts (spgemm_colptr of the
  * layer's row).  c_colptr has c1-c0+1 entries and may start at any offset.
  * Rows within each output column are in hash-table order.  `flops` is the
- * symbolic flops_out of the same columns (may be NULL).  Synchronizes
- * `stream` to read the per-bin column counts (and, for heavy columns, their
- * count) that size the launches.  With n_layers > 1 the layer's share of
+ * symbolic flops_out of the same columns (may be NULL).  Every kernel takes
+ * its column counts from the device, so the call does not synchronize
+ * `stream`, except for A with more than 8,388,608 rows, where the count of
+ * columns above 5120 rows (formed on global accumulators) is read back to
+ * size their launches.  With n_layers > 1 the layer's share of
  * B(:, c0:c1) is first compacted into the workspace.  A mismatch between
  * counts and the product sets the workspace status (spgemm_ws_status).
  * `semiring` is a spgemm_semiring (SPGEMM_E_INVAL otherwise). */

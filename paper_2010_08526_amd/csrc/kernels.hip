@@ -30,9 +30,9 @@ namespace spg {
 // Per-wave scratch for the load-balanced traversal.
 // ============================================================================
 struct SegScratch {
-  int mark[kWave];
-  int64_t off[kWave];   // element base of the lane's segment minus its exclusive prefix
-  double scale[kWave];  // B(k,j) of the lane's segment
+  int mark[kWave];      // start masks of 32 rounds (flatten_rounds)
+  int64_t off[kWave];   // element base of the o-th nonempty short segment minus its exclusive prefix
+  double scale[kWave];  // B(k,j) of that segment
 };
 
 struct PartDesc {  // one merge input, stored in the workspace
@@ -42,9 +42,9 @@ struct PartDesc {  // one merge input, stored in the workspace
 };
 
 struct MergeScratch {
-  int mark[kWave];
-  const int32_t *ri[kWave];
-  const void *v[kWave];
+  int mark[kWave];           // start masks of 32 rounds (flatten_rounds)
+  const int32_t *ri[kWave];  // rows of the o-th nonempty short segment, minus its exclusive prefix
+  const void *v[kWave];      // its values, likewise
 };
 
 template <class VT>
@@ -58,72 +58,80 @@ struct ProductArgs {
   int64_t klo, khi, kdim, m, nnzA;
 };
 
-// Traversal of the rounds of one chunk of segments.  Rounds r with
-// (r + r_base) % r_stride == r_rank are processed, so that a group of
-// r_stride waves can share one column; r_stride = 1 processes every round.
-// The owner of round fb's first element comes from a ballot (the highest
-// lane whose segment starts at or before fb), so rounds are independent.
-// Rounds are taken kPipe at a time in three phases: owners, then every
-// gather (load(o, e, row, raw) issues the loads of element e of segment o and
-// must not use their results), then every insert (ins(row, value(o, raw))),
-// so that a wavefront keeps kPipe independent global loads in flight.
+// Traversal of the rounds of one chunk of segments.  The caller lists the
+// chunk's nonempty segments in lane order (the ordinal of a segment is the
+// number of nonempty segments in lower lanes) and load/value take that
+// ordinal.  Rounds r with (r + r_base) % r_stride == r_rank are processed,
+// so that a group of r_stride waves can share one column; r_stride = 1
+// processes every round.  One 64-bit word per round marks where segments
+// start (32 rounds per refill of the words, in the caller's mark array), so
+// the owner of element e is (segments starting before the round) + (starts
+// in the round at or below e) - 1: a ballot, a population count and a mask
+// count.  Rounds are taken kPipe at a time in three phases: owners, then
+// every gather (load(o, e, row, raw) issues the loads of element e of
+// segment o and must not use their results), then every insert
+// (ins(row, value(o, raw))), so that a wavefront keeps kPipe independent
+// global loads in flight.
 constexpr int kPipe = 8;
 
 template <class RawT, class Load, class Value, class Ins>
 __device__ __forceinline__ void flatten_rounds(int len, int excl, int total, int *mark, int64_t r_base,
                                                int64_t r_rank, int64_t r_stride, uint32_t m, int32_t *status,
                                                Load &&load, Value &&value, Ins &&ins) {
+  constexpr int kGroup = kWave / 2;  // rounds per refill of the start masks (mark holds 32 words)
   const int l = lane();
-  int64_t r0 = (r_rank - r_base) % r_stride;
-  if (r0 < 0) r0 += r_stride;
-  for (int64_t r = r0; r * kWave < total; r += kPipe * r_stride) {
-    int own_[kPipe], e_[kPipe];
+  uint64_t *rmask = reinterpret_cast<uint64_t *>(mark);
+  const int rs = (int)r_stride;
+  int r0 = (int)((r_rank - r_base) % r_stride);
+  if (r0 < 0) r0 += rs;
+  const int nround = (total + kWave - 1) / kWave;
+  for (int g = 0; g < nround; g += kGroup) {
+    if (l < kGroup) rmask[l] = 0ull;
+    wave_sync();
+    const int rr = (excl >> 6) - g;
+    if (len > 0 && rr >= 0 && rr < kGroup) atomicOr((unsigned long long *)&rmask[rr], 1ull << (excl & 63));
+    wave_sync();
+    const int gend = min(nround, g + kGroup);
+    int rf = (r0 - g) % rs;
+    if (rf < 0) rf += rs;
+    for (int r = g + rf; r < gend; r += kPipe * rs) {
+      int own_[kPipe], e_[kPipe];
 #pragma unroll
-    for (int u = 0; u < kPipe; u++) {
-      const int64_t rr = r + u * r_stride;
-      own_[u] = -1;
-      e_[u] = 0;
-      if (rr * kWave < total) {
-        const int fb = (int)(rr * kWave);
-        const int last = min(fb + kWave - 1, total - 1);
-        const uint64_t started = __ballot(len > 0 && excl <= fb);
-        const int carry = started ? 64 - __clzll((long long)started) : 0;
-        int own;
-        if (__ballot(len > 0 && excl <= last) == started) {
-          own = carry;  // no segment starts inside this round: one owner
-        } else {
-          if (len > 0 && excl > fb && excl < fb + kWave) mark[excl - fb] = l + 1;
-          wave_sync();
-          const int mk = mark[l];
-          mark[l] = 0;
-          own = max(wave_incl_max(mk), carry);
-          wave_sync();
+      for (int u = 0; u < kPipe; u++) {
+        const int ru = r + u * rs;
+        own_[u] = -1;
+        e_[u] = 0;
+        if (ru < gend) {
+          const int fb = ru * kWave;
+          const uint64_t mm = rmask[ru - g];
+          const int carry = __popcll(__ballot(len > 0 && excl < fb));
+          const int e = fb + l;
+          if (e < total) {
+            own_[u] = carry + mbcnt(mm) + (int)((mm >> l) & 1ull) - 1;
+            e_[u] = e;
+          }
         }
-        const int e = fb + l;
-        if (e < total) {
-          own_[u] = own - 1;
-          e_[u] = e;
+      }
+      int32_t row_[kPipe];
+      RawT raw_[kPipe];
+#pragma unroll
+      for (int u = 0; u < kPipe; u++) {
+        row_[u] = -1;
+        raw_[u] = RawT(0);
+        if (own_[u] >= 0) load(own_[u], e_[u], row_[u], raw_[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < kPipe; u++) {
+        if (own_[u] >= 0) {
+          const int32_t row = opaque(row_[u]);
+          if ((uint32_t)row < m)
+            ins(row, value(own_[u], opaque(raw_[u])));
+          else
+            flag_error(status, 3);
         }
       }
     }
-    int32_t row_[kPipe];
-    RawT raw_[kPipe];
-#pragma unroll
-    for (int u = 0; u < kPipe; u++) {
-      row_[u] = -1;
-      raw_[u] = RawT(0);
-      if (own_[u] >= 0) load(own_[u], e_[u], row_[u], raw_[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < kPipe; u++) {
-      if (own_[u] >= 0) {
-        const int32_t row = opaque(row_[u]);
-        if ((uint32_t)row < m)
-          ins(row, value(own_[u], opaque(raw_[u])));
-        else
-          flag_error(status, 3);
-      }
-    }
+    wave_sync();  // every lane has read the masks before they are rewritten
   }
 }
 
@@ -147,6 +155,24 @@ __device__ __forceinline__ void stream_segment(const int32_t *__restrict__ ri, c
   if (b0 < 0) b0 += r_stride;
   for (int64_t blk = b0; blk < nblk; blk += r_stride) {
     const int e0 = (int)blk * kBlk + l;
+    if ((blk + 1) * kBlk <= len) {  // uniform: a whole block, no lane conditions on the loads
+      int32_t row[kVec];
+      VT raw[kVec];
+#pragma unroll
+      for (int t = 0; t < kVec; t++) {
+        row[t] = ld_global(ri + e0 + t * kWave);
+        raw[t] = VALUES ? ld_global(v + e0 + t * kWave) : VT(0);
+      }
+#pragma unroll
+      for (int t = 0; t < kVec; t++) {
+        const int32_t r = opaque(row[t]);
+        if ((uint32_t)r < m)
+          ins(r, VALUES ? Mul::mul((double)opaque(raw[t]), scale) : 0.0);
+        else
+          flag_error(status, 3);
+      }
+      continue;
+    }
     int32_t row[kVec];
     VT raw[kVec];
 #pragma unroll
@@ -290,8 +316,12 @@ __device__ __forceinline__ void traverse_product(const ProductArgs<VT> &a, int64
     const int excl = incl - ls;
     const int total = readlane(incl, 63);
     if (total > 0) {
-      sc.off[l] = off - excl;
-      if (VALUES) sc.scale[l] = b;
+      const uint64_t nz = __ballot(ls > 0);
+      if (ls > 0) {  // the nonempty short segments in lane order
+        const int o = mbcnt(nz);
+        sc.off[o] = off - excl;
+        if (VALUES) sc.scale[o] = b;
+      }
       wave_sync();
       int oob = 0;
       flatten_rounds<VT>(
@@ -375,8 +405,12 @@ __device__ __forceinline__ void traverse_merge(const PartDesc *P, int nparts, in
     const int excl = incl - ls;
     const int total = readlane(incl, 63);
     if (total > 0) {
-      sc.ri[l] = ri - excl;
-      sc.v[l] = (const void *)(v - excl);
+      const uint64_t nz = __ballot(ls > 0);
+      if (ls > 0) {  // the nonempty short segments in lane order
+        const int o = mbcnt(nz);
+        sc.ri[o] = ri - excl;
+        sc.v[o] = (const void *)(v - excl);
+      }
       wave_sync();
       flatten_rounds<VT>(
           ls, excl, total, sc.mark, rounds_before, r_rank, r_stride, (uint32_t)m, status,
@@ -2829,22 +2863,27 @@ static int numeric_dispatch(const spgemm_csc *A, const spgemm_csc *B, int64_t c0
                             int64_t khi, const int64_t *c_colptr, int32_t *c_rowidx, void *c_values, int32_t semiring,
                             const WsLayout &L, char *ws, hipStream_t s, bool keep_status) {
   const bool f32 = A->dtype == SPGEMM_F32;
+  // The bin counts are read back only when heavy columns may need the
+  // global accumulators (their launches are sized on the host); otherwise
+  // every kernel takes its count from the device and the call does not
+  // synchronize the stream.
+  const bool sync = L.slots > 0;
   switch (semiring) {
     case SPGEMM_SR_MIN_PLUS:
       return f32 ? numeric_typed<float, SrMinPlus>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, ws, s,
-                                                   true, keep_status)
+                                                   sync, keep_status)
                  : numeric_typed<double, SrMinPlus>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, ws, s,
-                                                    true, keep_status);
+                                                    sync, keep_status);
     case SPGEMM_SR_OR_AND:
       return f32 ? numeric_typed<float, SrOrAnd>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, ws, s,
-                                                 true, keep_status)
+                                                 sync, keep_status)
                  : numeric_typed<double, SrOrAnd>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, ws, s,
-                                                  true, keep_status);
+                                                  sync, keep_status);
     default:
       return f32 ? numeric_typed<float, SrPlusTimes>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, ws,
-                                                     s, true, keep_status)
+                                                     s, sync, keep_status)
                  : numeric_typed<double, SrPlusTimes>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, ws,
-                                                      s, true, keep_status);
+                                                      s, sync, keep_status);
   }
 }
 }  // namespace spg
