@@ -55,8 +55,8 @@ def _parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extras", action="store_true",
-                   help="skip the fwd_bwd, batched, layered, bsweep, prune, aat and sorted sections")
-    p.add_argument("--extras", default="fwd_bwd,batched,layered,bsweep,prune,aat,sorted",
+                   help="skip the fwd_bwd, batched, layered, bsweep, prune, aat and sorted_output sections")
+    p.add_argument("--extras", default="fwd_bwd,batched,layered,bsweep,prune,aat,sorted_output",
                    help="comma-separated extra sections to run")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain device copy of known size (to scale HBM byte counters) and exit")
@@ -729,7 +729,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_extras:
         for name, fn in (("fwd_bwd", fwd_bwd), ("batched", batched), ("layered", layered), ("bsweep", bsweep),
-                         ("prune", prune), ("aat", aat), ("sorted", sorted_output)):
+                         ("prune", prune), ("aat", aat), ("sorted_output", sorted_output)):
             if name in args.extras.split(","):
                 res[name] = fn(args, torch, np, S, synth)
                 torch.cuda.empty_cache()

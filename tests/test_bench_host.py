@@ -58,6 +58,6 @@ def test_default_run_covers_every_section():
     finally:
         sys.argv = argv
     assert args.gpus == 1 and not args.no_extras
-    assert set(args.extras.split(",")) == {"fwd_bwd", "batched", "layered", "bsweep", "prune", "aat", "sorted"}
+    assert set(args.extras.split(",")) == {"fwd_bwd", "batched", "layered", "bsweep", "prune", "aat", "sorted_output"}
     for name in args.extras.split(","):
         assert callable(getattr(b, name))
