@@ -466,21 +466,30 @@ def bsweep(args, torch, np, S, synth):
             continue
         eng.budget_bytes = eng.input_bytes + eng.reserve_bytes + avail
         times = []
-        for _ in range(2):
+        for rep in range(3):  # warm-up, timed, then one with per-kernel events
             torch.cuda.synchronize()
+            if rep == 2:
+                S.profile_enable(True)
             t0 = time.perf_counter()
             pl = eng.plan()
             for i in range(pl.nbatches):
                 eng.run_batch(pl, i)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
+        prof = S.profile_report()
+        S.profile_enable(False)
         eng.check()
-        t = times[-1]
+        t = times[1]
+        top = sorted(prof.items(), key=lambda kv: -kv[1][0])[:8]
         rows.append({"b": pl.nbatches, "budget_bytes": eng.budget_bytes, "ms": round(t * 1e3, 2),
-                     "GFLOPs": round(2 * flops / t / 1e9, 2)})
-        log(f"bsweep: b={pl.nbatches} {t * 1e3:.1f} ms ({2 * flops / t / 1e9:.1f} GFLOP/s)")
+                     "GFLOPs": round(2 * flops / t / 1e9, 2),
+                     "kernels_ms": {k: round(v[0], 2) for k, v in top},
+                     "launches": int(sum(v[1] for v in prof.values()))})
+        log(f"bsweep: b={pl.nbatches} {t * 1e3:.1f} ms ({2 * flops / t / 1e9:.1f} GFLOP/s); " +
+            ", ".join(f"{k}={v[0]:.1f}" for k, v in top[:5]))
     del eng
-    return {"workload": "rmat20 headline product at several batch counts (one warm-up, one timed product each)",
+    return {"workload": "rmat20 headline product at several batch counts (one warm-up, one timed product, then one "
+                        "with per-kernel HIP events for kernels_ms)",
             "flops": flops, "runs": rows}
 
 
