@@ -413,7 +413,9 @@ def batched(args, torch, np, S, synth):
            "batched_fwd_bwd_GFLOPs": round(6 * flops / t_graph_fb / 1e9, 2),
            "fwd_bwd_over_fwd_time": round(t_graph_fb / t_graph, 3),
            "fwd_bwd_note": "graph of forward + fused backward with dC = C; GFLOP/s counts 3x forward flops",
-           "autotuned_caps": tune["caps"]}
+           "autotuned_caps": tune["caps"], "autotuned_num_bpc": tune["num_bpc"],
+           "autotuned_sym_bpc": tune["sym_bpc"], "autotune_default_ms": round(tune["default_ms"], 3),
+           "autotune_best_ms": round(tune["ms"], 3)}
     # compulsory bytes of one replay of the forward: the symbolic and the
     # numeric pass each read the stored inputs once (r bytes per entry of A
     # and B), the numeric pass writes C (r per entry) and its column pointers

@@ -355,7 +355,12 @@ int spgemm_sort_columns(const spgemm_csc *C, int32_t *rowidx_out, void *values_o
  * heavy path.  They must be nondecreasing and at most each table's capacity
  * (32, 128, 512, 2048, 16384 symbolic; 32, 128, 512, 2048, 5120 numeric),
  * which are also the defaults (caps_host = NULL restores them).  Thresholds
- * change speed, never results.  SPGEMM_E_INVAL otherwise. */
+ * change speed, never results.  SPGEMM_E_INVAL otherwise.
+ * which = 2 (numeric, merge) and 3 (symbolic) set instead the launch shape
+ * of the five bin kernels: caps_host[5] workgroups per compute unit of
+ * their persistent grids, each in [1, 32] (defaults 8, 8, 4, 4, 1 numeric;
+ * 8, 8, 8, 8, 1 symbolic; NULL restores them).  Launch shapes change speed,
+ * never results. */
 int spgemm_set_bin_caps(int32_t which, const int64_t *caps_host);
 
 /* Per-kernel timing (process-wide, off by default; not under graph

@@ -30,8 +30,9 @@ NUM_TABLE_CAP = (32, 128, 512, 2048, 5120)
 
 
 def set_bin_caps(which: int, caps=None):
-    """Bin thresholds for the symbolic (0) or numeric/masked (1) kernels;
-    None restores the defaults."""
+    """Bin thresholds for the symbolic (0) or numeric/masked (1) kernels, or
+    workgroups per compute unit of the numeric (2) or symbolic (3) bin
+    kernels; None restores the defaults."""
     arr = None if caps is None else np.ascontiguousarray(np.asarray(caps, dtype=np.int64))
     _check(_lib.spgemm_set_bin_caps(which, None if arr is None else arr.ctypes.data), "spgemm_set_bin_caps")
 
@@ -205,9 +206,30 @@ def workload_key(A, B) -> str:
     return f"{arch}|{A.values.dtype}|flops_per_col_2^{cls}"
 
 
+NUM_BPC = (8, 8, 4, 4, 1)  # workgroups per CU of the numeric bin kernels (library defaults)
+SYM_BPC = (8, 8, 8, 8, 1)  # the same for the symbolic bin kernels
+
+
+def _bpc_candidates(default):
+    """Launch shapes of the five bin kernels: the defaults, half as many and
+    twice as many workgroups per compute unit (at least 1, at most 32)."""
+    half = tuple(max(1, x // 2) for x in default)
+    double = tuple(min(32, 2 * x) for x in default)
+    return [tuple(default), half, double]
+
+
+def _apply(setting):
+    set_bin_caps(1, setting["caps"])
+    set_bin_caps(2, setting["num_bpc"])
+    set_bin_caps(3, setting["sym_bpc"])
+
+
 def autotune(eng: BatchedEngine, reps: int = 3, use_cache: bool = True, verbose: bool = False):
-    """Times forward replays under each threshold candidate, keeps the
-    fastest and records it per (arch, dtype, workload class)."""
+    """Times forward replays while it searches, one knob at a time, the
+    numeric bin thresholds (hash-table load factor), then the workgroups per
+    compute unit of the numeric bin kernels, then those of the symbolic bin
+    kernels; keeps the fastest setting and records it per (arch, dtype,
+    workload class).  Settings change speed, never results."""
     key = workload_key(eng.A, eng.B)
     path = _cache_path()
     cache = {}
@@ -216,27 +238,40 @@ def autotune(eng: BatchedEngine, reps: int = 3, use_cache: bool = True, verbose:
             cache = json.load(open(path))
         except (OSError, ValueError):
             cache = {}
-    if use_cache and key in cache:
-        set_bin_caps(1, cache[key]["caps"])
+    if use_cache and key in cache and "num_bpc" in cache[key]:
+        _apply(cache[key])
         return cache[key]
-    best = None
-    results = []
-    for caps in _candidates():
-        set_bin_caps(1, caps)
+
+    def timed(setting):
+        _apply(setting)
         eng.forward()
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(reps):
             eng.forward()
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t) / reps
-        results.append({"caps": list(caps), "ms": dt * 1e3})
-        if verbose:
-            print(f"# autotune caps={caps} {dt * 1e3:.3f} ms", flush=True)
-        if best is None or dt < best[1]:
-            best = (caps, dt)
-    set_bin_caps(1, best[0])
-    entry = {"caps": list(best[0]), "ms": best[1] * 1e3, "tried": results}
+        return (time.perf_counter() - t) / reps
+
+    best = {"caps": tuple(NUM_TABLE_CAP), "num_bpc": NUM_BPC, "sym_bpc": SYM_BPC}
+    best_t = timed(best)
+    results = [{**{k: list(v) for k, v in best.items()}, "ms": best_t * 1e3}]
+    default_ms = best_t * 1e3
+    for knob, cands in (("caps", _candidates()), ("num_bpc", _bpc_candidates(NUM_BPC)),
+                        ("sym_bpc", _bpc_candidates(SYM_BPC))):
+        for c in cands:
+            if tuple(c) == tuple(best[knob]):
+                continue
+            trial = dict(best)
+            trial[knob] = tuple(c)
+            dt = timed(trial)
+            results.append({**{k: list(v) for k, v in trial.items()}, "ms": dt * 1e3})
+            if verbose:
+                print(f"# autotune {knob}={c} {dt * 1e3:.3f} ms", flush=True)
+            if dt < best_t:
+                best, best_t = trial, dt
+    _apply(best)
+    entry = {**{k: list(v) for k, v in best.items()}, "ms": best_t * 1e3, "default_ms": default_ms,
+             "tried": results}
     cache[key] = entry
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)

@@ -2296,6 +2296,10 @@ static int g_min_bin = 0;
 // Bin thresholds in use (symbolic, numeric); tunable within the table sizes.
 static BinCaps g_caps[2] = {BinCaps{{kSymCap[0], kSymCap[1], kSymCap[2], kSymCap[3], kSymCap[4]}},
                             BinCaps{{kNumCap[0], kNumCap[1], kNumCap[2], kNumCap[3], kNumCap[4]}}};
+// Workgroups per compute unit of the persistent bin kernels' grids
+// (symbolic, numeric and merge); tunable, never changing results.
+constexpr int kBpcDefault[2][kNumBins - 1] = {{8, 8, 8, 8, 1}, {8, 8, 4, 4, 1}};
+static int g_bpc[2][kNumBins - 1] = {{8, 8, 8, 8, 1}, {8, 8, 4, 4, 1}};
 
 int read_header(WsHeader *dev, hipStream_t st, WsHeader *out) {
   if (!g_pin.hdr) HIPCHK(hipHostMalloc((void **)&g_pin.hdr, sizeof(WsHeader), hipHostMallocDefault));
@@ -2551,11 +2555,11 @@ static int symbolic_pass(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
     const int32_t *list = bins + (int64_t)b * ncol;
     const int32_t *cp = &hdr->bin_count[b];
     switch (b) {
-      case 0: hipLaunchKernelGGL(k_sym_wave<64>, dim3(bin_grid(cnt[b], true, 8)), dim3(256), 0, st, a, c0, list, cp, nnz_row, status); break;
-      case 1: hipLaunchKernelGGL(k_sym_wave<256>, dim3(bin_grid(cnt[b], true, 8)), dim3(256), 0, st, a, c0, list, cp, nnz_row, status); break;
-      case 2: hipLaunchKernelGGL(k_sym_wave<1024>, dim3(bin_grid(cnt[b], true, 8)), dim3(256), 0, st, a, c0, list, cp, nnz_row, status); break;
-      case 3: hipLaunchKernelGGL((k_sym_block<4096, 256>), dim3(bin_grid(cnt[b], false, 8)), dim3(256), 0, st, a, c0, list, cp, nnz_row, status); break;
-      case 4: hipLaunchKernelGGL((k_sym_block<32768, 1024>), dim3(bin_grid(cnt[b], false, 1)), dim3(1024), 0, st, a, c0, list, cp, nnz_row, status); break;
+      case 0: hipLaunchKernelGGL(k_sym_wave<64>, dim3(bin_grid(cnt[b], true, g_bpc[0][0])), dim3(256), 0, st, a, c0, list, cp, nnz_row, status); break;
+      case 1: hipLaunchKernelGGL(k_sym_wave<256>, dim3(bin_grid(cnt[b], true, g_bpc[0][1])), dim3(256), 0, st, a, c0, list, cp, nnz_row, status); break;
+      case 2: hipLaunchKernelGGL(k_sym_wave<1024>, dim3(bin_grid(cnt[b], true, g_bpc[0][2])), dim3(256), 0, st, a, c0, list, cp, nnz_row, status); break;
+      case 3: hipLaunchKernelGGL((k_sym_block<4096, 256>), dim3(bin_grid(cnt[b], false, g_bpc[0][3])), dim3(256), 0, st, a, c0, list, cp, nnz_row, status); break;
+      case 4: hipLaunchKernelGGL((k_sym_block<32768, 1024>), dim3(bin_grid(cnt[b], false, g_bpc[0][4])), dim3(1024), 0, st, a, c0, list, cp, nnz_row, status); break;
       default: hipLaunchKernelGGL(k_sym_bitmap, dim3(bin_grid(cnt[b], false, 1)), dim3(1024), 0, st, a, c0, list, cp, &hdr->cursor[b], nnz_row, status); break;
     }
     LAUNCHCHK();
@@ -2587,11 +2591,11 @@ static int accumulate_pass(const Src &src, const int *cnt, const WsHeader &h, co
     const int32_t *list = bins + (int64_t)b * ncol;
     const int32_t *cp = &hdr->bin_count[b];
     switch (b) {
-      case 0: hipLaunchKernelGGL((k_num_wave<64, VT, Src>), dim3(bin_grid(cnt[b], true, 8)), dim3(256), 0, st, src, list, cp, c_colptr, out_ri, out_v, status); break;
-      case 1: hipLaunchKernelGGL((k_num_wave<256, VT, Src>), dim3(bin_grid(cnt[b], true, 8)), dim3(256), 0, st, src, list, cp, c_colptr, out_ri, out_v, status); break;
-      case 2: hipLaunchKernelGGL((k_num_wave<1024, VT, Src>), dim3(bin_grid(cnt[b], true, 4)), dim3(256), 0, st, src, list, cp, c_colptr, out_ri, out_v, status); break;
-      case 3: hipLaunchKernelGGL((k_num_block<4096, 256, VT, Src>), dim3(bin_grid(cnt[b], false, 4)), dim3(256), 0, st, src, list, cp, c_colptr, out_ri, out_v, status); break;
-      default: hipLaunchKernelGGL((k_num_block<10240, 1024, VT, Src>), dim3(bin_grid(cnt[b], false, 1)), dim3(1024), 0, st, src, list, cp, c_colptr, out_ri, out_v, status); break;
+      case 0: hipLaunchKernelGGL((k_num_wave<64, VT, Src>), dim3(bin_grid(cnt[b], true, g_bpc[1][0])), dim3(256), 0, st, src, list, cp, c_colptr, out_ri, out_v, status); break;
+      case 1: hipLaunchKernelGGL((k_num_wave<256, VT, Src>), dim3(bin_grid(cnt[b], true, g_bpc[1][1])), dim3(256), 0, st, src, list, cp, c_colptr, out_ri, out_v, status); break;
+      case 2: hipLaunchKernelGGL((k_num_wave<1024, VT, Src>), dim3(bin_grid(cnt[b], true, g_bpc[1][2])), dim3(256), 0, st, src, list, cp, c_colptr, out_ri, out_v, status); break;
+      case 3: hipLaunchKernelGGL((k_num_block<4096, 256, VT, Src>), dim3(bin_grid(cnt[b], false, g_bpc[1][3])), dim3(256), 0, st, src, list, cp, c_colptr, out_ri, out_v, status); break;
+      default: hipLaunchKernelGGL((k_num_block<10240, 1024, VT, Src>), dim3(bin_grid(cnt[b], false, g_bpc[1][4])), dim3(1024), 0, st, src, list, cp, c_colptr, out_ri, out_v, status); break;
     }
     LAUNCHCHK();
   }
@@ -3078,6 +3082,17 @@ int spgemm_batched_forward_noalloc(const spgemm_csc *A, const spgemm_csc *B, int
 }
 
 int spgemm_set_bin_caps(int32_t which, const int64_t *caps_host) {
+  if (which == 2 || which == 3) {  // workgroups per compute unit of the bin kernels
+    const int t = which - 2;
+    int v[kNumBins - 1];
+    for (int b = 0; b < kNumBins - 1; b++) {
+      const int64_t x = caps_host ? caps_host[b] : kBpcDefault[t][b];
+      if (x < 1 || x > 32) return SPGEMM_E_INVAL;
+      v[b] = (int)x;
+    }
+    for (int b = 0; b < kNumBins - 1; b++) g_bpc[t][b] = v[b];
+    return SPGEMM_OK;
+  }
   if (which != 0 && which != 1) return SPGEMM_E_INVAL;
   const int64_t *table = which == 0 ? kSymTableCap : kNumTableCap;
   BinCaps c;

@@ -217,10 +217,17 @@ def test_bin_caps_validation():
     assert lib.spgemm_set_bin_caps(1, too_big.ctypes.data) == S.E_INVAL
     not_monotone = _np.array([32, 16, 512, 2048, 5120], _np.int64)
     assert lib.spgemm_set_bin_caps(1, not_monotone.ctypes.data) == S.E_INVAL
-    assert lib.spgemm_set_bin_caps(2, good.ctypes.data) == S.E_INVAL
+    assert lib.spgemm_set_bin_caps(2, good.ctypes.data) == S.E_INVAL  # launch shapes: at most 32 per CU
     sym = _np.array([32, 128, 512, 2048, 16384], _np.int64)
     assert lib.spgemm_set_bin_caps(0, sym.ctypes.data) == S.OK
     assert lib.spgemm_set_bin_caps(0, None) == S.OK
+    for which in (2, 3):  # workgroups per compute unit of the bin kernels
+        ok = _np.array([4, 4, 2, 2, 1], _np.int64)
+        assert lib.spgemm_set_bin_caps(which, ok.ctypes.data) == S.OK
+        assert lib.spgemm_set_bin_caps(which, _np.array([4, 4, 0, 2, 1], _np.int64).ctypes.data) == S.E_INVAL
+        assert lib.spgemm_set_bin_caps(which, _np.array([4, 4, 33, 2, 1], _np.int64).ctypes.data) == S.E_INVAL
+        assert lib.spgemm_set_bin_caps(which, None) == S.OK
+    assert lib.spgemm_set_bin_caps(4, None) == S.E_INVAL
 
 
 def _prune(C, k=3, cap=None, thr=0.0, cp=0x5000, ri=0x6000, v=0x7000, ws=None, ws_bytes=1 << 30):

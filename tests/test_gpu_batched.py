@@ -24,8 +24,8 @@ def setup_module(module):
 def teardown_function(fn):
     if S is not None:
         S._lib.spgemm_debug_min_bin(0)
-        Bt.set_bin_caps(0, None)
-        Bt.set_bin_caps(1, None)
+        for which in range(4):
+            Bt.set_bin_caps(which, None)
 
 
 def _instance(M, off, i):
@@ -151,8 +151,11 @@ def test_autotune_changes_speed_not_results():
     ref = host_sorted(eng.C)
     res = Bt.autotune(eng, reps=1, use_cache=False)
     assert tuple(res["caps"]) in Bt._candidates()
-    for caps in Bt._candidates():
-        Bt.set_bin_caps(1, caps)
+    assert tuple(res["num_bpc"]) in Bt._bpc_candidates(Bt.NUM_BPC)
+    assert tuple(res["sym_bpc"]) in Bt._bpc_candidates(Bt.SYM_BPC)
+    assert len(res["tried"]) >= 5
+    for t in res["tried"]:
+        Bt._apply({"caps": t["caps"], "num_bpc": t["num_bpc"], "sym_bpc": t["sym_bpc"]})
         eng.forward()
         got = host_sorted(eng.C)
         assert np.array_equal(got[1], ref[1]) and np.allclose(got[2], ref[2], rtol=1e-6, atol=0)
