@@ -672,50 +672,68 @@ def prune(args, torch, np, S, synth):
 
 def sorted_output(args, torch, np, S, synth):
     """Row-sorted output columns (the paper keeps its final Merge-Fiber
-    output sorted): the headline product in 16 column batches with every
-    batch sorted into a second buffer, against the unsorted product; and the
-    sort pass alone on each batch (kernel time from the library's HIP
-    events, compulsory bytes: every entry read and written once, r bytes)."""
+    output sorted) on the headline product in 16 even column batches, one
+    layer: the unsorted product; every column hashed then sorted into a
+    second buffer; and the hybrid, where columns of at most 4096 terms and
+    compression ratio up to cf are formed in row order by expand-sort-compress
+    (the paper finds its CPU hybrid ahead at one layer and low compression
+    ratio), at several cf.  Kernel times from the library's HIP events; the
+    sort pass's compulsory bytes: every entry it sorts read and written once
+    (r bytes each)."""
     dev = torch.device("cuda:0")
     A = synth.rmat(args.scale, 16, synth.WORKLOADS["rmat20"].seed, dtype=torch.float32, device=dev)
-    res = {}
+    bounds = np.linspace(0, A.ncols, 16 + 1).astype(np.int64)
+    runs = {}
+    nnz_c = 0
     for sorted_flag in (False, True):
         eng = S.Engine(A, A, 1, budget_bytes=1 << 62, sorted_output=sorted_flag)
         plan = eng.plan()
-        bounds = np.linspace(0, A.ncols, 16 + 1).astype(np.int64)
-        # the same column ranges in both runs: 16 even column ranges (the
-        # sorted run holds each batch twice, so batches are kept small)
+        # the same column ranges in every run (the sorted runs hold each
+        # batch twice, so batches are kept small)
         plan.bounds = bounds.tolist()
         plan.batch_nnz = np.stack([plan.nnz_host[:, a:b].sum(1) for a, b in zip(bounds[:-1], bounds[1:])])
+        nnz_c = int(plan.nnz_host[0].sum())
 
         def step():
             for i in range(plan.nbatches):
                 eng.run_batch(plan, i)
 
-        step()
-        torch.cuda.synchronize()
-        eng.check()
-        S.profile_enable(True)
-        t = _timed(step, 1, torch)
-        prof = S.profile_report()
-        S.profile_enable(False)
-        eng.check()
-        res["sorted" if sorted_flag else "unsorted"] = (t, prof.get("sort_columns", (0.0, 0))[0], plan)
+        for cf in ((None,) if not sorted_flag else (0.0, 1.25, 2.0, 4.0, 1e9)):
+            if cf is not None:
+                eng.esc_cf = cf
+            step()
+            torch.cuda.synchronize()
+            eng.check()
+            S.profile_enable(True)
+            t = _timed(step, 1, torch)
+            prof = S.profile_report()
+            S.profile_enable(False)
+            eng.check()
+            name = "unsorted" if cf is None else ("sorted_hash_all" if cf == 0 else
+                                                 ("sorted_hybrid_all_small" if cf >= 1e9 else f"sorted_hybrid_cf{cf:g}"))
+            runs[name] = {"ms": round(t * 1e3, 3),
+                          "kernels_ms": {k: round(v[0], 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])
+                                         if v[0] >= 0.05}}
+            if cf is not None:
+                runs[name]["esc_cf"] = cf
         del eng
         torch.cuda.empty_cache()
-    t_u, _, pl = res["unsorted"]
-    t_s, sort_ms, _ = res["sorted"]
-    nnz_c = int(pl.nnz_host[0].sum())
-    sort_bytes = 2 * 8 * nnz_c + 8 * (A.ncols + pl.nbatches)
+    t_u = runs["unsorted"]["ms"]
+    h = runs["sorted_hash_all"]
+    sort_ms = h["kernels_ms"].get("sort_columns", 0.0)
+    sort_bytes = 2 * 8 * nnz_c + 8 * (A.ncols + len(bounds))
     gbs = sort_bytes / (sort_ms * 1e-3) / 1e9 if sort_ms > 0 else None
-    log(f"sorted: numeric unsorted {t_u * 1e3:.1f} ms, sorted {t_s * 1e3:.1f} ms (sort pass {sort_ms:.1f} ms, "
-        f"{gbs:.0f} GB/s compulsory)")
-    return {"workload": "rmat20 headline product, numeric phase over 16 even column batches, with and without the "
-                        "row-sorting pass after each batch",
-            "batches": pl.nbatches, "nnz_C": nnz_c,
-            "numeric_unsorted_ms": round(t_u * 1e3, 3), "numeric_sorted_ms": round(t_s * 1e3, 3),
-            "sort_pass_ms": round(sort_ms, 3), "sorted_over_unsorted_time": round(t_s / t_u, 3),
-            "sort_compulsory_bytes": sort_bytes,
+    best = min((k for k in runs if k.startswith("sorted_hybrid")), key=lambda k: runs[k]["ms"])
+    log(f"sorted: unsorted {t_u:.1f} ms, hash+sort {h['ms']:.1f} ms (sort pass {sort_ms:.1f} ms, "
+        f"{gbs or 0:.0f} GB/s compulsory), best hybrid {best} {runs[best]['ms']:.1f} ms; "
+        + ", ".join(f"{k}={v['ms']:.1f}" for k, v in runs.items()))
+    return {"workload": "rmat20 headline product, one layer, 16 even column batches: unsorted, row-sorted with "
+                        "every column hashed then sorted, and row-sorted by the hybrid at several cf",
+            "batches": len(bounds) - 1, "nnz_C": nnz_c, "runs": runs,
+            "numeric_unsorted_ms": t_u, "numeric_sorted_ms": h["ms"],
+            "sorted_over_unsorted_time": round(h["ms"] / t_u, 3),
+            "best_hybrid": best, "best_hybrid_over_hash_sort_time": round(runs[best]["ms"] / h["ms"], 3),
+            "sort_pass_ms": sort_ms, "sort_compulsory_bytes": sort_bytes,
             "sort_achieved_GBps": None if gbs is None else round(gbs, 1),
             "sort_frac_of_hbm_peak": None if gbs is None else round(gbs / HBM_PEAK_GBS, 4)}
 

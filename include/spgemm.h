@@ -347,6 +347,34 @@ int spgemm_prune_topk(const spgemm_csc *C, double threshold, int64_t k, int64_t 
 int spgemm_sort_columns(const spgemm_csc *C, int32_t *rowidx_out, void *values_out, void *ws, size_t ws_bytes,
                         void *stream);
 
+/* Row-sorted numeric pass with a per-column choice of kernel (the hybrid of
+ * Sec. V, discussion of Table VII: a column whose compression ratio
+ * flops/nnz is low is formed in row order directly, which beats hashing it
+ * and sorting it afterwards; Sec. IV-D keeps the final output sorted within
+ * each column).  Forms columns [c0,c1) of A*B (one layer: the full product)
+ * with each column in ascending row order, at c_colptr as spgemm_numeric
+ * does (`flops` and `c_colptr` from the symbolic pass of the same columns).
+ *   - a column with flops_j <= 4096 and flops_j <= esc_cf_max * nnz_j is
+ *     formed by expand-sort-compress: every product term placed in LDS,
+ *     sorted by row, runs of equal rows combined in row order (one
+ *     wavefront per column up to 64 terms, one workgroup up to 4096), and
+ *     written straight to c_rowidx / c_values;
+ *   - every other column is formed by the hash kernels of spgemm_numeric
+ *     into tmp_rowidx / tmp_values (device arrays addressed by the same
+ *     column pointers, distinct from the outputs) and then sorted into
+ *     c_rowidx / c_values by the kernels of spgemm_sort_columns.
+ * esc_cf_max = 0 hashes every column (then `flops` may be NULL); it must be
+ * >= 0 (SPGEMM_E_INVAL otherwise).  The choice changes speed only: values
+ * equal the hashed ones up to the order in which a run's terms are
+ * combined (plus-times), exactly otherwise.  `semiring` as in
+ * spgemm_numeric.  Synchronizes the stream only where spgemm_numeric does.
+ * A count mismatch sets the workspace status (code 4), as in
+ * spgemm_numeric.  Workspace: SPGEMM_OP_NUMERIC with n_layers = 1. */
+int spgemm_numeric_sorted(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t c1, const int64_t *flops,
+                          const int64_t *c_colptr, int32_t *c_rowidx, void *c_values, int32_t *tmp_rowidx,
+                          void *tmp_values, double esc_cf_max, int32_t semiring, void *ws, size_t ws_bytes,
+                          void *stream);
+
 /* Bin thresholds (process-wide; used by calls launched afterwards): which = 0
  * for the symbolic pass, 1 for numeric, merge and masked products.
  * caps_host[5] are the largest bounds on distinct rows that go to bins 0..4

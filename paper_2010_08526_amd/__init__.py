@@ -194,6 +194,24 @@ def numeric(A, B, c0: int, c1: int, layer: int, n_layers: int, flops, c_colptr, 
                                ws.numel(), _stream(stream)), "spgemm_numeric")
 
 
+_lib.spgemm_numeric_sorted.argtypes = [_P, _P, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_double, _i32, _vp,
+                                       _sz, _vp]
+
+# Compression ratio up to which a column of at most 4096 product terms is
+# formed in row order by expand-sort-compress rather than hashed and sorted.
+ESC_CF_DEFAULT = 2.0
+
+
+def numeric_sorted(A, B, c0: int, c1: int, flops, c_colptr, c_rowidx, c_values, tmp_rowidx, tmp_values,
+                   ws: torch.Tensor, stream=None, semiring=PLUS_TIMES, esc_cf: float = ESC_CF_DEFAULT):
+    """Columns [c0, c1) of A*B in row order: low-compression columns by
+    expand-sort-compress, the others hashed into tmp_* and sorted."""
+    _check(_lib.spgemm_numeric_sorted(ctypes.byref(desc(A)), ctypes.byref(desc(B)), c0, c1, _ptr(flops),
+                                      _ptr(c_colptr), _ptr(c_rowidx), _ptr(c_values), _ptr(tmp_rowidx),
+                                      _ptr(tmp_values), float(esc_cf), semiring_id(semiring), _ptr(ws), ws.numel(),
+                                      _stream(stream)), "spgemm_numeric_sorted")
+
+
 def merge(parts, c_colptr, c_rowidx, c_values, ws: torch.Tensor, stream=None, semiring=PLUS_TIMES):
     arr = (spgemm_csc * len(parts))(*[desc(p) for p in parts])
     _check(_lib.spgemm_merge(arr, len(parts), _ptr(c_colptr), _ptr(c_rowidx), _ptr(c_values), semiring_id(semiring),
@@ -280,14 +298,17 @@ class Engine:
     """
 
     def __init__(self, A, B, n_layers: int = 1, budget_bytes: int | None = None, max_batches: int = 1 << 16,
-                 device="cuda", semiring=PLUS_TIMES, sorted_output: bool = False):
+                 device="cuda", semiring=PLUS_TIMES, sorted_output: bool = False, esc_cf: float = ESC_CF_DEFAULT):
         if A.ncols != B.nrows:
             raise SpgemmError(E_SHAPE, "Engine")
         self.A, self.B, self.L = A, B, int(n_layers)
         self.semiring = semiring_id(semiring)
         # row-sorted output columns: each batch is formed, then sorted into a
-        # second buffer of the same size (counted by the planner)
+        # second buffer of the same size (counted by the planner); with one
+        # layer, columns of compression ratio up to esc_cf (and at most 4096
+        # terms) are formed in row order directly (0: every column hashed)
         self.sorted_output = bool(sorted_output)
+        self.esc_cf = float(esc_cf)
         self.device = device
         self.max_batches = max_batches
         self.vbytes = 4 if A.values is None or A.values.dtype == torch.float32 else 8
@@ -300,7 +321,7 @@ class Engine:
             if self.L > 1 else None
         self.ws_scan = alloc_workspace(workspace_size(OP_COLPTR, None, None, 0, n + 1), device)
         self.ws_sort = alloc_workspace(workspace_size(OP_SORT, CSC(A.nrows, n, B.colptr, B.rowidx, B.values)), device) \
-            if self.sorted_output else None
+            if self.sorted_output and self.L > 1 else None
         rows = self.L + 1 if self.L > 1 else 1
         self.flops = torch.empty(n, dtype=torch.int64, device=device)
         self.nnz = torch.empty((rows, n), dtype=torch.int64, device=device)
@@ -380,10 +401,16 @@ class Engine:
         if L == 1:
             e0 = mark()
             colptr(self.nnz[0, c0:c1], ccp, self.ws_scan, stream)
+            nnzc = int(plan.batch_nnz[i, 0])
+            if self.sorted_output:  # formed in row order (hashed columns staged in cri / cv)
+                numeric_sorted(A, B, c0, c1, self.flops[c0:c1], ccp, bufs["sri"], bufs["sv"], cri, cv, self.ws_num,
+                               stream, self.semiring, self.esc_cf)
+                if marks is not None:
+                    marks.append(("numeric_sorted", e0, mark()))
+                return CSC(A.nrows, w, ccp, bufs["sri"][:nnzc], bufs["sv"][:nnzc])
             numeric(A, B, c0, c1, 0, 1, self.flops[c0:c1], ccp, cri, cv, self.ws_num, stream, self.semiring)
             if marks is not None:
                 marks.append(("numeric", e0, mark()))
-            nnzc = int(plan.batch_nnz[i, 0])
         else:
             parts = []
             off = 0
@@ -447,12 +474,12 @@ def _concat(batches, nrows):
 
 
 def spgemm(A, B, *, layers: int = 1, budget_bytes: int | None = None, consume=None, stream=None,
-           semiring=PLUS_TIMES, sorted_output: bool = False):
+           semiring=PLUS_TIMES, sorted_output: bool = False, esc_cf: float = ESC_CF_DEFAULT):
     """C = A B over ``semiring`` ('plus_times', 'min_plus', 'or_and'), rows of
     each column in hash-table order or, with ``sorted_output``, ascending.
     With ``consume`` the batches are handed to it and discarded; otherwise C
     is returned (all batches concatenated)."""
-    eng = Engine(A, B, layers, budget_bytes, semiring=semiring, sorted_output=sorted_output)
+    eng = Engine(A, B, layers, budget_bytes, semiring=semiring, sorted_output=sorted_output, esc_cf=esc_cf)
     res = eng.run(consume, stream)
     return res if consume is not None else res[0]
 

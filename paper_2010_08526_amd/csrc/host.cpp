@@ -84,7 +84,9 @@ int ws_layout(int op, const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int6
         off = align_up(off + kSlabEntBytes[A->dtype == SPGEMM_F64 ? 1 : 0] * (size_t)A->nnz);
       }
       L->bins = off;
-      off = align_up(off + sizeof(int32_t) * kNumBins * (size_t)ncol);
+      // numeric: two more lists, for the row-sorted product's columns formed
+      // by expand-sort-compress
+      off = align_up(off + sizeof(int32_t) * (kNumBins + (op == SPGEMM_OP_NUMERIC ? 2 : 0)) * (size_t)ncol);
       if (op == SPGEMM_OP_MERGE) {
         L->parts = off;
         off = align_up(off + kPartDescBytes * (size_t)n_layers);

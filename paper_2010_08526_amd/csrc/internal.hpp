@@ -38,6 +38,19 @@ struct BinCaps {
 };
 
 constexpr int kMaxParts = 4096;  // merge: parts per call
+
+// Row-sorted product (spgemm_numeric_sorted): a column with at most
+// kEscBlockTerms product terms whose compression ratio flops / nnz is at
+// most cf_max is formed by expand-sort-compress (every term placed in LDS,
+// sorted by row, equal rows combined in order), one wavefront per column up
+// to kEscWaveTerms terms, one workgroup above; every other column is hashed
+// and sorted afterwards.  Returns the kernel class (0, 1) or -1 (hashed).
+constexpr int64_t kEscWaveTerms = 64;
+constexpr int64_t kEscBlockTerms = 4096;
+constexpr int esc_class(int64_t flops, int64_t nnz, double cf_max) {
+  return (nnz <= 0 || flops > kEscBlockTerms || (double)flops > cf_max * (double)nnz) ? -1
+         : (flops <= kEscWaveTerms ? 0 : 1);
+}
 constexpr size_t kPartDescBytes = 24;  // device-side copy of one part's pointers
 constexpr int64_t kBitmapRows = 1 << 20;  // heavy symbolic: rows per LDS bitmap window (128 KiB)
 constexpr int64_t kHeavySeg = 16384;  // global heavy path: rows per compaction segment
@@ -87,6 +100,7 @@ struct WsHeader {
   int32_t wide_cursor;  // work-queue position over their items
   uint64_t left_tag;    // fingerprint (| 1) of the source of the slabbed copy of A in the workspace; 0 = none
   uint64_t left_new;    // fingerprint of the current call's left operand (summed by k_left_sum)
+  int32_t esc_count[2];  // row-sorted product: columns listed for the two expand-sort-compress kernels
 };
 constexpr size_t kHeaderBytes = 4096;
 

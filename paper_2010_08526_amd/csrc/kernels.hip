@@ -445,6 +445,7 @@ __global__ void k_init_header(WsHeader *h, uint64_t keep_tag, int keep_status = 
     h->left_new = 0;
     for (int b = 0; b < kNumBins; b++) h->bin_count[b] = 0;
     for (int b = 0; b < kNumBins; b++) h->cursor[b] = 0;
+    h->esc_count[0] = h->esc_count[1] = 0;
     h->items = 0;
     h->item_cursor = 0;
     h->nwide = 0;
@@ -496,13 +497,16 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t *Acp, const int64_t *
                                              int64_t c0, int64_t ncol, int64_t klo, int64_t khi, int64_t kdim,
                                              int64_t m, const int64_t *c_colptr, int64_t *flops_out,
                                              int64_t *nnz_out, int32_t *bins, WsHeader *hdr, int min_bin,
-                                             BinCaps caps) {
-  __shared__ int s_cnt[kNumBins];
-  __shared__ int s_base[kNumBins];
+                                             BinCaps caps, const int64_t *esc_flops, double esc_cf) {
+  // lists kNumBins and kNumBins + 1: the row-sorted product's
+  // expand-sort-compress columns (numeric only, when esc_flops is given)
+  constexpr int NL = kNumBins + 2;
+  __shared__ int s_cnt[NL];
+  __shared__ int s_base[NL];
   __shared__ int s_bin[4 * kBinColsPerWave];
   __shared__ int s_pos[4 * kBinColsPerWave];
   const int w = threadIdx.x / kWave, l = lane();
-  if (threadIdx.x < kNumBins) s_cnt[threadIdx.x] = 0;
+  if (threadIdx.x < NL) s_cnt[threadIdx.x] = 0;
   __syncthreads();
   for (int t = 0; t < kBinColsPerWave; t++) {
     const int slot = w * kBinColsPerWave + t;
@@ -529,6 +533,10 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t *Acp, const int64_t *
         bound = c_colptr[jj + 1] - c_colptr[jj];
       }
       if (bound > 0) bin = max(bin_of(bound, caps), min_bin);
+      if (!SYM && esc_flops && bound > 0) {
+        const int e = esc_class(esc_flops[jj], bound, esc_cf);
+        if (e >= 0) bin = kNumBins + e;
+      }
     }
     if (l == 0) {
       s_bin[slot] = bin;
@@ -536,9 +544,10 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t *Acp, const int64_t *
     }
   }
   __syncthreads();
-  if (threadIdx.x < kNumBins) {
-    const int c = s_cnt[threadIdx.x];
-    s_base[threadIdx.x] = c ? atomicAdd(&hdr->bin_count[threadIdx.x], c) : 0;
+  if (threadIdx.x < NL) {
+    const int b = threadIdx.x;
+    const int c = s_cnt[b];
+    s_base[b] = c ? atomicAdd(b < kNumBins ? &hdr->bin_count[b] : &hdr->esc_count[b - kNumBins], c) : 0;
   }
   __syncthreads();
   if (threadIdx.x < 4 * kBinColsPerWave) {
@@ -926,6 +935,235 @@ __global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *l
     if (more) src.pre_a(pre);
     if (threadIdx.x == 0 && total != cap) flag_error(status, 4);
     __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Row-sorted product, columns of low compression ratio: expand-sort-compress.
+// Every product term of the column is placed in LDS as (row, float64 term),
+// the terms are sorted by row with a bitonic network, and each run of equal
+// rows is combined in sorted order and written at its rank among the runs:
+// the column comes out in ascending row order with no hash table and no
+// second pass over the output.  Where nearly every term has a row of its own
+// (flops close to nnz) this is the cheaper way to a sorted column, the role
+// the heap kernel plays in the CPU hybrid (Sec. V); columns with many
+// repeated rows are cheaper to hash and sort afterwards.  Placement is
+// deterministic (terms in B-entry order, each A column in storage order),
+// and so is the order in which a run is combined.
+// ----------------------------------------------------------------------------
+// Bitonic sort of (key, val) across the 64 lanes, ascending by key.
+__device__ __forceinline__ void wave_bitonic(int32_t &key, double &val) {
+  const int l = lane();
+#pragma unroll
+  for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+    for (int s = k >> 1; s > 0; s >>= 1) {
+      const int32_t ok = __shfl_xor(key, s, kWave);
+      const double ov = __shfl_xor(val, s, kWave);
+      const bool up = (l & k) == 0;   // this block of k lanes sorts ascending
+      const bool low = (l & s) == 0;  // the lower lane of the pair keeps the smaller key when ascending
+      if (low == up ? ok < key : ok > key) {
+        key = ok;
+        val = ov;
+      }
+    }
+  }
+}
+
+// One wavefront per column of at most kEscWaveTerms terms.
+template <class VT, class SR>
+__global__ __launch_bounds__(256) void k_esc_wave(ProductArgs<VT> a, int64_t c0, const int32_t *list,
+                                                  const int32_t *count_p, const int64_t *c_colptr, int32_t *out_ri,
+                                                  VT *out_v, int32_t *status) {
+  __shared__ int s_mark[4][kWave];
+  __shared__ int32_t s_row[4][kWave];
+  __shared__ double s_val[4][kWave];
+  const int w = threadIdx.x / kWave, l = lane();
+  const int count = *count_p;
+  s_mark[w][l] = 0;
+  wave_sync();
+  for (int64_t idx = (int64_t)blockIdx.x * 4 + w; idx < count; idx += (int64_t)gridDim.x * 4) {
+    const int64_t jj = list[idx];
+    const int64_t bb = a.Bcp[c0 + jj], be = a.Bcp[c0 + jj + 1];
+    const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
+    int n = 0;  // terms placed (uniform)
+    bool bad = false;
+    for (int64_t p0 = bb; p0 < be; p0 += kWave) {
+      const int64_t p = p0 + l;
+      int len = 0;
+      int64_t ab = 0;
+      double bv = 0.0;
+      if (p < be) {
+        const int32_t k = a.Bri[p];
+        if (k >= a.klo && k < a.khi) {
+          ab = a.Acp[k];
+          len = (int)min<int64_t>(a.Acp[k + 1] - ab, kEscWaveTerms + 1);
+          bv = (double)a.Bv[p];
+        }
+      }
+      const int incl = wave_incl_add(len), excl = incl - len;
+      const int tot = readlane(incl, kWave - 1);
+      if (n + tot > kEscWaveTerms) {  // more terms than the flops the column was listed with
+        bad = true;
+        break;
+      }
+      if (tot == 0) continue;
+      // owner of term e of this chunk: the last lane whose segment starts at or below e
+      if (len > 0) s_mark[w][excl] = l + 1;
+      wave_sync();
+      const int mk = s_mark[w][l];
+      s_mark[w][l] = 0;
+      const int own = max(wave_incl_max(mk) - 1, 0);
+      const int64_t oab = __shfl(ab, own, kWave);
+      const int oex = __shfl(excl, own, kWave);
+      const double obv = __shfl(bv, own, kWave);
+      if (l < tot) {
+        const int64_t q = oab + (l - oex);
+        s_row[w][n + l] = a.Ari[q];
+        s_val[w][n + l] = SR::mul((double)a.Av[q], obv);
+      }
+      n += tot;
+      wave_sync();
+    }
+    if (bad) {
+      if (l == 0) flag_error(status, 4);
+      continue;
+    }
+    int32_t key = l < n ? s_row[w][l] : INT32_MAX;  // padding sorts last (rows are below INT32_MAX)
+    double val = l < n ? s_val[w][l] : 0.0;
+    wave_bitonic(key, val);
+    wave_sync();
+    s_row[w][l] = key;
+    s_val[w][l] = val;
+    wave_sync();
+    const bool head = l < n && (l == 0 || s_row[w][l - 1] != key);
+    double acc = 0.0;  // all-zero slot: no term yet
+    if (head) {
+      SR::acc_plain(acc, val);
+      for (int t = l + 1; t < n && s_row[w][t] == key; t++) SR::acc_plain(acc, s_val[w][t]);
+    }
+    const uint64_t hm = __ballot(head);
+    const int r = mbcnt(hm);
+    if (head && r < cap) {
+      out_ri[base + r] = key;
+      out_v[base + r] = (VT)SR::out(acc);
+    }
+    if (l == 0 && __popcll(hm) != cap) flag_error(status, 4);
+    wave_sync();  // the next column overwrites s_row, s_val
+  }
+}
+
+// One workgroup per column of up to kEscBlockTerms terms: B(:,j) in chunks
+// of 256 entries, each chunk's terms placed by all threads (the owner of a
+// term found by binary search over the chunk's exclusive prefix), then a
+// bitonic sort in LDS and the runs combined tile by tile.
+template <class VT, class SR>
+__global__ __launch_bounds__(256) void k_esc_block(ProductArgs<VT> a, int64_t c0, const int32_t *list,
+                                                   const int32_t *count_p, const int64_t *c_colptr, int32_t *out_ri,
+                                                   VT *out_v, int32_t *status) {
+  constexpr int T = 256, NW = T / kWave, N = (int)kEscBlockTerms;
+  __shared__ int32_t s_row[N];
+  __shared__ double s_val[N];
+  __shared__ int s_ex[T];
+  __shared__ int64_t s_ab[T];
+  __shared__ double s_bv[T];
+  __shared__ int s_w[NW];
+  const int tid = threadIdx.x;
+  const int count = *count_p;
+  for (int64_t item = blockIdx.x; item < count; item += gridDim.x) {
+    const int64_t jj = list[item];
+    const int64_t bb = a.Bcp[c0 + jj], be = a.Bcp[c0 + jj + 1];
+    const int64_t base = c_colptr[jj], cap = c_colptr[jj + 1] - base;
+    int n = 0;  // terms placed (uniform)
+    bool bad = false;
+    for (int64_t p0 = bb; p0 < be; p0 += T) {
+      const int64_t p = p0 + tid;
+      int len = 0;
+      int64_t ab = 0;
+      double bv = 0.0;
+      if (p < be) {
+        const int32_t k = a.Bri[p];
+        if (k >= a.klo && k < a.khi) {
+          ab = a.Acp[k];
+          len = (int)min<int64_t>(a.Acp[k + 1] - ab, N + 1);
+          bv = (double)a.Bv[p];
+        }
+      }
+      int tot;
+      const int ex = block_excl<NW>(len, s_w, tot);
+      if (n + tot > N) {  // more terms than the flops the column was listed with
+        bad = true;
+        break;
+      }
+      s_ex[tid] = ex;
+      s_ab[tid] = ab;
+      s_bv[tid] = bv;
+      __syncthreads();
+      const int np = (int)min<int64_t>(T, be - p0);
+      for (int q = tid; q < tot; q += T) {
+        int lo = 0, hi = np - 1;  // the last entry whose segment starts at or below q
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_ex[mid] <= q) lo = mid;
+          else hi = mid - 1;
+        }
+        const int64_t qa = s_ab[lo] + (q - s_ex[lo]);
+        s_row[n + q] = a.Ari[qa];
+        s_val[n + q] = SR::mul((double)a.Av[qa], s_bv[lo]);
+      }
+      n += tot;
+      __syncthreads();  // s_ex, s_ab, s_bv, s_w are reused by the next chunk
+    }
+    if (bad) {
+      if (tid == 0) flag_error(status, 4);
+      __syncthreads();
+      continue;
+    }
+    int M = 128;
+    while (M < n) M <<= 1;
+    for (int t = n + tid; t < M; t += T) {
+      s_row[t] = INT32_MAX;  // padding sorts last
+      s_val[t] = 0.0;
+    }
+    __syncthreads();
+    for (int k = 2; k <= M; k <<= 1) {
+      for (int s = k >> 1; s > 0; s >>= 1) {
+        for (int t = tid; t < M / 2; t += T) {
+          const int lo = ((t & ~(s - 1)) << 1) | (t & (s - 1));  // lower element of pair t at distance s
+          const int hi = lo + s;
+          const bool up = (lo & k) == 0;
+          const int32_t kl = s_row[lo], kh = s_row[hi];
+          if ((kl > kh) == up) {
+            const double vl = s_val[lo];
+            s_row[lo] = kh;
+            s_row[hi] = kl;
+            s_val[lo] = s_val[hi];
+            s_val[hi] = vl;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    int done = 0;  // runs written so far (uniform)
+    for (int t0 = 0; t0 < n; t0 += T) {
+      const int t = t0 + tid;
+      const int32_t key = t < n ? s_row[t] : INT32_MAX;
+      const bool head = t < n && (t == 0 || s_row[t - 1] != key);
+      int tot;
+      const int r = done + block_excl<NW>(head ? 1 : 0, s_w, tot);
+      if (head) {
+        double acc = 0.0;  // all-zero slot: no term yet
+        for (int u = t; u < n && s_row[u] == key; u++) SR::acc_plain(acc, s_val[u]);
+        if (r < cap) {
+          out_ri[base + r] = key;
+          out_v[base + r] = (VT)SR::out(acc);
+        }
+      }
+      done += tot;
+      __syncthreads();  // s_w is reused by the next tile
+    }
+    if (tid == 0 && done != cap) flag_error(status, 4);
+    __syncthreads();  // the next column overwrites s_row, s_val
   }
 }
 
@@ -2330,6 +2568,12 @@ int launch_set_tag(WsHeader *h, uint64_t tag, hipStream_t st) {
   return SPGEMM_OK;
 }
 
+int launch_reset_counters(WsHeader *h, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, h, kKeepAnyTag, 1, 1);
+  LAUNCHCHK();
+  return SPGEMM_OK;
+}
+
 int launch_init_header(WsHeader *h, uint64_t keep_tag, hipStream_t st) {
   hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, h, keep_tag, 0);
   LAUNCHCHK();
@@ -2538,7 +2782,7 @@ static int symbolic_pass(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
     ProfScope prof_bin("bin_symbolic", st);
     hipLaunchKernelGGL(k_bin<true>, dim3(grid_of(ncol, per_block)), dim3(256), 0, st, A->colptr, B->colptr,
                        B->rowidx, c0, ncol, klo, khi, (int64_t)A->ncols, A->nrows, (const int64_t *)nullptr,
-                       flops_out, nnz_row, bins, hdr, g_min_bin, g_caps[0]);
+                       flops_out, nnz_row, bins, hdr, g_min_bin, g_caps[0], (const int64_t *)nullptr, 0.0);
     LAUNCHCHK();
   }
   int cnt[kNumBins];
@@ -2636,10 +2880,21 @@ static int accumulate_pass(const Src &src, const int *cnt, const WsHeader &h, co
   return SPGEMM_OK;
 }
 
+// Row-sorted product: the columns that expand-sort-compress forms (chosen
+// by esc_class from the symbolic flops of the batch's columns and cf) are
+// written in row order to ri / v; the others go to the numeric pass's output.
+struct EscOut {
+  const int64_t *flops;
+  double cf;
+  int32_t *ri;
+  void *v;
+};
+
 template <class VT, class SR>
 static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t ncol, int64_t klo,
                          int64_t khi, const int64_t *c_colptr, int32_t *c_rowidx, void *c_values, const WsLayout &L,
-                         char *ws, hipStream_t st, bool sync, bool keep_status = false) {
+                         char *ws, hipStream_t st, bool sync, bool keep_status = false,
+                         const EscOut *esc = nullptr) {
   WsHeader *hdr = (WsHeader *)ws;
   int32_t *bins = (int32_t *)(ws + L.bins);
   hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, hdr, zero_region_tag(kTagProduct, L),
@@ -2647,7 +2902,8 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
   LAUNCHCHK();
   hipLaunchKernelGGL(k_bin<false>, dim3(grid_of(ncol, 4 * kBinColsPerWave)), dim3(256), 0, st, A->colptr, B->colptr,
                      B->rowidx, c0, ncol, klo, khi, (int64_t)A->ncols, A->nrows, c_colptr, (int64_t *)nullptr,
-                     (int64_t *)nullptr, bins, hdr, g_min_bin, g_caps[1]);
+                     (int64_t *)nullptr, bins, hdr, g_min_bin, g_caps[1], esc ? esc->flops : (const int64_t *)nullptr,
+                     esc ? esc->cf : 0.0);
   LAUNCHCHK();
   int cnt[kNumBins];
   WsHeader h;
@@ -2656,6 +2912,23 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
   ProductSrc<VT, SR> src;
   src.a = product_args<VT>(A, B, klo, khi);
   src.c0 = c0;
+  if (esc) {
+    int32_t *status = &hdr->status;
+    for (int e = 0; e < 2; e++) {
+      const int ce = sync ? h.esc_count[e] : -1;
+      if (ce == 0) continue;
+      const int32_t *list = bins + (int64_t)(kNumBins + e) * ncol;
+      const int32_t *cp = &hdr->esc_count[e];
+      ProfScope prof(e == 0 ? "esc_wave" : "esc_block", st);
+      if (e == 0)
+        hipLaunchKernelGGL((k_esc_wave<VT, SR>), dim3(bin_grid(ce, true, 8)), dim3(256), 0, st, src.a, c0, list, cp,
+                           c_colptr, esc->ri, (VT *)esc->v, status);
+      else
+        hipLaunchKernelGGL((k_esc_block<VT, SR>), dim3(bin_grid(ce, false, 3)), dim3(256), 0, st, src.a, c0, list,
+                           cp, c_colptr, esc->ri, (VT *)esc->v, status);
+      LAUNCHCHK();
+    }
+  }
   const bool slabs = L.P > 0;
   rc = accumulate_pass<VT>(src, cnt, h, L, ws, c_colptr, c_rowidx, (VT *)c_values, st, !slabs);
   if (rc) return rc;
@@ -2756,7 +3029,7 @@ static int merge_typed(const spgemm_csc *parts, int32_t n_parts, const int64_t *
   hipLaunchKernelGGL(k_bin<false>, dim3(grid_of(L.ncol, 4 * kBinColsPerWave)), dim3(256), 0, st,
                      (const int64_t *)nullptr, (const int64_t *)nullptr, (const int32_t *)nullptr, (int64_t)0, L.ncol,
                      (int64_t)0, (int64_t)0, (int64_t)0, L.m, c_colptr, (int64_t *)nullptr, (int64_t *)nullptr, bins,
-                     hdr, g_min_bin, g_caps[1]);
+                     hdr, g_min_bin, g_caps[1], (const int64_t *)nullptr, 0.0);
   LAUNCHCHK();
   int cnt[kNumBins];
   WsHeader h;
@@ -2865,7 +3138,8 @@ namespace spg {
 // layer's call keeps the status its share of B may have set).
 static int numeric_dispatch(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t ncol, int64_t klo,
                             int64_t khi, const int64_t *c_colptr, int32_t *c_rowidx, void *c_values, int32_t semiring,
-                            const WsLayout &L, char *ws, hipStream_t s, bool keep_status) {
+                            const WsLayout &L, char *ws, hipStream_t s, bool keep_status,
+                            const EscOut *esc = nullptr) {
   const bool f32 = A->dtype == SPGEMM_F32;
   // The bin counts are read back only when heavy columns may need the
   // global accumulators (their launches are sized on the host); otherwise
@@ -2875,19 +3149,19 @@ static int numeric_dispatch(const spgemm_csc *A, const spgemm_csc *B, int64_t c0
   switch (semiring) {
     case SPGEMM_SR_MIN_PLUS:
       return f32 ? numeric_typed<float, SrMinPlus>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, ws, s,
-                                                   sync, keep_status)
+                                                   sync, keep_status, esc)
                  : numeric_typed<double, SrMinPlus>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, ws, s,
-                                                    sync, keep_status);
+                                                    sync, keep_status, esc);
     case SPGEMM_SR_OR_AND:
       return f32 ? numeric_typed<float, SrOrAnd>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, ws, s,
-                                                 sync, keep_status)
+                                                 sync, keep_status, esc)
                  : numeric_typed<double, SrOrAnd>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, ws, s,
-                                                  sync, keep_status);
+                                                  sync, keep_status, esc);
     default:
       return f32 ? numeric_typed<float, SrPlusTimes>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, ws,
-                                                     s, sync, keep_status)
+                                                     s, sync, keep_status, esc)
                  : numeric_typed<double, SrPlusTimes>(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, L, ws,
-                                                      s, sync, keep_status);
+                                                      s, sync, keep_status, esc);
   }
 }
 }  // namespace spg
@@ -2972,6 +3246,51 @@ int spgemm_numeric(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t
                             true);
   }
   return numeric_dispatch(A, B, c0, ncol, klo, khi, c_colptr, c_rowidx, c_values, semiring, L, (char *)ws, s, false);
+}
+
+int spgemm_numeric_sorted(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, int64_t c1, const int64_t *flops,
+                          const int64_t *c_colptr, int32_t *c_rowidx, void *c_values, int32_t *tmp_rowidx,
+                          void *tmp_values, double esc_cf_max, int32_t semiring, void *ws, size_t ws_bytes,
+                          void *stream) {
+  if (semiring < SPGEMM_SR_PLUS_TIMES || semiring > SPGEMM_SR_OR_AND) return SPGEMM_E_INVAL;
+  if (!(esc_cf_max >= 0.0)) return SPGEMM_E_INVAL;  // NaN included
+  int st = check_csc(A, true);
+  if (!st) st = check_csc(B, true);
+  if (st) return st;
+  if (A->dtype != B->dtype) return SPGEMM_E_DTYPE;
+  if (A->ncols != B->nrows) return SPGEMM_E_SHAPE;
+  if (c0 < 0 || c1 < c0 || c1 > B->ncols) return SPGEMM_E_INVAL;
+  WsLayout L;
+  st = ws_layout(SPGEMM_OP_NUMERIC, A, B, c0, c1, 1, &L);
+  if (st) return st;
+  st = check_ws(ws, ws_bytes, L.total);
+  if (st) return st;
+  const int64_t ncol = c1 - c0;
+  hipStream_t s = (hipStream_t)stream;
+  if (ncol == 0) {
+    hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, s, (WsHeader *)ws, kKeepAnyTag, 0);
+    LAUNCHCHK();
+    return SPGEMM_OK;
+  }
+  if (!c_colptr || !c_rowidx || !c_values || !tmp_rowidx || !tmp_values) return SPGEMM_E_INVAL;
+  if ((void *)tmp_rowidx == (void *)c_rowidx || tmp_values == c_values) return SPGEMM_E_INVAL;  // out of place
+  const bool use_esc = esc_cf_max > 0.0;
+  if (use_esc && !flops) return SPGEMM_E_INVAL;
+  const EscOut esc{flops, esc_cf_max, c_rowidx, c_values};
+  st = numeric_dispatch(A, B, c0, ncol, 0, A->ncols, c_colptr, tmp_rowidx, tmp_values, semiring, L, (char *)ws, s,
+                        false, use_esc ? &esc : nullptr);
+  if (st) return st;
+  // the hashed columns, from the staging arrays into row order (the bin
+  // lists are free again: the sort pass lists its columns there)
+  st = launch_reset_counters((WsHeader *)ws, s);
+  if (st) return st;
+  spgemm_csc T = *A;
+  T.ncols = ncol;
+  T.colptr = c_colptr;
+  T.rowidx = tmp_rowidx;
+  T.values = tmp_values;
+  return sort_column_lists(&T, c_rowidx, c_values, (int32_t *)((char *)ws + L.bins), (WsHeader *)ws,
+                           use_esc ? flops : nullptr, esc_cf_max, s);
 }
 
 int spgemm_merge(const spgemm_csc *parts, int32_t n_parts, const int64_t *c_colptr, int32_t *c_rowidx,

@@ -26,6 +26,8 @@ struct SrPlusTimes {
   static constexpr int kId = SPGEMM_SR_PLUS_TIMES;
   __device__ static __forceinline__ double mul(double a, double b) { return a * b; }
   __device__ static __forceinline__ void acc(double *slot, double t) { atomicAdd(slot, t); }
+  // the same combination by one thread, on a slot in a register
+  __device__ static __forceinline__ void acc_plain(double &slot, double t) { slot += t; }
   __device__ static __forceinline__ double out(double slot) { return slot; }
 };
 
@@ -46,6 +48,10 @@ struct SrMinPlus {
   __device__ static __forceinline__ void acc(double *slot, double t) {
     atomicMax((unsigned long long *)slot, (unsigned long long)~ord_key(t));
   }
+  __device__ static __forceinline__ void acc_plain(double &slot, double t) {
+    const uint64_t s = (uint64_t)__double_as_longlong(slot), k = ~ord_key(t);
+    slot = __longlong_as_double((long long)(k > s ? k : s));
+  }
   __device__ static __forceinline__ double out(double slot) {
     return ord_val(~(uint64_t)__double_as_longlong(slot));
   }
@@ -55,6 +61,7 @@ struct SrOrAnd {
   static constexpr int kId = SPGEMM_SR_OR_AND;
   __device__ static __forceinline__ double mul(double, double) { return 1.0; }
   __device__ static __forceinline__ void acc(double *, double) {}
+  __device__ static __forceinline__ void acc_plain(double &, double) {}
   __device__ static __forceinline__ double out(double) { return 1.0; }
 };
 

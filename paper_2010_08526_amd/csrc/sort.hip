@@ -39,12 +39,16 @@ constexpr int kSortDupCode = 11;  // status code: a row twice in one column, or 
 
 // Column lists per length class: lists[c * ncols + i], counts in the
 // header's first three bin counters.
-__global__ __launch_bounds__(256) void k_sort_bin(const int64_t *cp, int64_t n, int32_t *lists, WsHeader *hdr) {
+// Columns formed in row order by expand-sort-compress (skip_flops given) are
+// left out.
+__global__ __launch_bounds__(256) void k_sort_bin(const int64_t *cp, int64_t n, int32_t *lists, WsHeader *hdr,
+                                                  const int64_t *skip_flops, double skip_cf) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   int cls = -1;
   if (j < n) {
     const int64_t len = cp[j + 1] - cp[j];
     cls = len <= 0 ? -1 : (len <= kSortWaveLen ? 0 : (len <= kSortBlockLen ? 1 : 2));
+    if (skip_flops && esc_class(skip_flops[j], len, skip_cf) >= 0) cls = -1;
   }
   for (int c = 0; c < 3; c++) {
     const uint64_t mask = __ballot(cls == c);
@@ -242,14 +246,12 @@ __global__ __launch_bounds__(kSortHeavyThreads) void k_sort_heavy(const int64_t 
 }
 
 template <class VT>
-int sort_typed(const spgemm_csc *C, int32_t *ro, void *vo, const WsLayout &L, char *ws, hipStream_t st) {
-  WsHeader *hdr = (WsHeader *)ws;
-  int rc = launch_init_header(hdr, (uint64_t)0, st);
-  if (rc) return rc;
+int sort_typed(const spgemm_csc *C, int32_t *ro, void *vo, int32_t *lists, WsHeader *hdr,
+               const int64_t *skip_flops, double skip_cf, hipStream_t st) {
   const int64_t n = C->ncols;
-  int32_t *lists = (int32_t *)(ws + L.bins);
   ProfScope prof("sort_columns", st);
-  hipLaunchKernelGGL(k_sort_bin, dim3(grid_of(n, 256)), dim3(256), 0, st, C->colptr, n, lists, hdr);
+  hipLaunchKernelGGL(k_sort_bin, dim3(grid_of(n, 256)), dim3(256), 0, st, C->colptr, n, lists, hdr, skip_flops,
+                     skip_cf);
   LAUNCHCHK();
   const VT *v = (const VT *)C->values;
   const int cus = device_cus();
@@ -266,6 +268,13 @@ int sort_typed(const spgemm_csc *C, int32_t *ro, void *vo, const WsLayout &L, ch
 }
 
 }  // namespace
+
+int sort_column_lists(const spgemm_csc *C, int32_t *ro, void *vo, int32_t *lists, WsHeader *hdr,
+                      const int64_t *skip_flops, double skip_cf, hipStream_t st) {
+  if (C->dtype == SPGEMM_F32) return sort_typed<float>(C, ro, vo, lists, hdr, skip_flops, skip_cf, st);
+  return sort_typed<double>(C, ro, vo, lists, hdr, skip_flops, skip_cf, st);
+}
+
 }  // namespace spg
 
 using namespace spg;
@@ -287,8 +296,10 @@ int spgemm_sort_columns(const spgemm_csc *C, int32_t *rowidx_out, void *values_o
   if (st) return st;
   if (C->ncols == 0) return launch_init_header((WsHeader *)ws, (uint64_t)0, (hipStream_t)stream);
   hipStream_t s = (hipStream_t)stream;
-  if (C->dtype == SPGEMM_F32) return sort_typed<float>(C, rowidx_out, values_out, L, (char *)ws, s);
-  return sort_typed<double>(C, rowidx_out, values_out, L, (char *)ws, s);
+  st = launch_init_header((WsHeader *)ws, (uint64_t)0, s);
+  if (st) return st;
+  return sort_column_lists(C, rowidx_out, values_out, (int32_t *)((char *)ws + L.bins), (WsHeader *)ws, nullptr, 0.0,
+                           s);
 }
 
 }  // extern "C"

@@ -338,3 +338,32 @@ def test_sort_validation_before_launch():
     assert lib.spgemm_sort_columns(ctypes.byref(C.d), 0x8000, 0x9000, 0x10000, 16, None) == S.E_WORKSPACE
     assert lib.spgemm_sort_columns(ctypes.byref(FakeCSC(100, 10, 5, values=False).d), 0x8000, 0x9000, 0x10000,
                                    1 << 20, None) == S.E_INVAL
+
+
+def test_numeric_sorted_validation_before_launch():
+    lib = S._lib
+    A, B = FakeCSC(10, 8, 5), FakeCSC(8, 7, 5)
+    a, b = ctypes.byref(A.d), ctypes.byref(B.d)
+    big = 1 << 30
+
+    def call(cf=2.0, sr=0, flops=0x100, tri=0x5000, tv=0x6000, ri=0x2000, v=0x3000, c0=0, c1=7, aa=a, bb=b):
+        return lib.spgemm_numeric_sorted(aa, bb, c0, c1, flops, 0x1000, ri, v, tri, tv, cf, sr, 0x10000, big, None)
+
+    for sr in (-1, 3):
+        assert call(sr=sr) == S.E_INVAL
+    for cf in (-1.0, float("nan")):
+        assert call(cf=cf) == S.E_INVAL
+    assert call(tri=0x2000) == S.E_INVAL  # staging arrays must differ from the outputs
+    assert call(tv=0x3000) == S.E_INVAL
+    assert call(tri=None) == S.E_INVAL
+    assert call(flops=None) == S.E_INVAL  # the choice needs the flops
+    assert call(c1=8) == S.E_INVAL
+    assert call(bb=ctypes.byref(FakeCSC(8, 7, 5, dtype=S.F64).d)) == S.E_DTYPE
+    assert call(bb=ctypes.byref(FakeCSC(9, 7, 5).d)) == S.E_SHAPE
+    assert call(aa=ctypes.byref(FakeCSC(10, 8, 5, values=False).d)) == S.E_INVAL
+    assert lib.spgemm_numeric_sorted(a, b, 0, 7, 0x100, 0x1000, 0x2000, 0x3000, 0x5000, 0x6000, 2.0, 0, 0x10000, 16,
+                                     None) == S.E_WORKSPACE
+    # a numeric workspace holds the two extra column lists of the sorted pass
+    need = ctypes.c_size_t()
+    assert lib.spgemm_workspace_size(S.OP_NUMERIC, a, b, 0, 7, 1, ctypes.byref(need)) == S.OK
+    assert need.value >= 4096 + 8 * 4 * 7
