@@ -73,7 +73,7 @@ constexpr int kHvCap = kHvSlots / 2;
 constexpr int64_t kHvWideT = 1024;
 constexpr uint64_t kHvItemBytes = uint64_t(64) << 20;  // item list of one chunk of heavy columns
 constexpr size_t kSlabEntBytes[2] = {8, 16};  // one slabbed entry of A (row and value): float32, float64
-constexpr int64_t kMbBucket = int64_t(1) << 28;  // merge: entries bucketed at once (heavy columns)
+constexpr int64_t kMbBucket = int64_t(1) << 29;  // merge: entries bucketed at once (heavy columns)
 
 inline int64_t num_slabs(int64_t m) { return (m + kSlabRows - 1) / kSlabRows; }
 
@@ -98,6 +98,7 @@ struct WsHeader {
   int32_t cursor[kNumBins];  // work-queue positions of the persistent kernels
   int32_t nwide;        // wide heavy columns listed for the current chunk
   int32_t wide_cursor;  // work-queue position over their items
+  int32_t mb_cursor;    // merge: work-queue position over the chunk's heavy columns (bucketing)
   uint64_t left_tag;    // fingerprint (| 1) of the source of the slabbed copy of A in the workspace; 0 = none
   uint64_t left_new;    // fingerprint of the current call's left operand (summed by k_left_sum)
   int32_t esc_count[2];  // row-sorted product: columns listed for the two expand-sort-compress kernels

@@ -13,6 +13,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <type_traits>
 #include <vector>
@@ -1333,6 +1334,7 @@ __global__ void k_hv_reset(WsHeader *h) {
     h->item_cursor = 0;
     h->nwide = 0;
     h->wide_cursor = 0;
+    h->mb_cursor = 0;
   }
 }
 
@@ -2011,7 +2013,8 @@ __device__ __forceinline__ int mb_part_of(const MbParts &mp, int n, int q) {
 template <class VT>
 __global__ __launch_bounds__(kMbThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_mb_bucket(const PartDesc *parts, int nparts, int64_t m, int P,
                                                           const int32_t *list, const int32_t *count_p, int64_t h0,
-                                                          int64_t h1, const int64_t *base, int64_t ecap,
+                                                          int64_t h1, const int32_t *ord, int32_t *queue,
+                                                          const int64_t *base, int64_t ecap,
                                                           int32_t *soff, int32_t *brow, VT *bval, uint32_t *slots,
                                                           int32_t *status) {
   constexpr int NW = kMbThreads / kWave;
@@ -2025,9 +2028,17 @@ __global__ __launch_bounds__(kMbThreads) __attribute__((amdgpu_waves_per_eu(8)))
   __shared__ int s_w[NW];
   __shared__ MbParts s_mp;
   const int w = threadIdx.x / kWave, l = lane();
+  __shared__ int s_next;
   const int64_t count = min((int64_t)*count_p, h1);
   const int64_t b0 = base[h0];
-  for (int64_t h = h0 + blockIdx.x; h < count; h += gridDim.x) {
+  // columns from a work queue over ord[h0, h1), the chunk's columns longest
+  // first: a long column never starts late and holds the launch open
+  for (;;) {
+    if (threadIdx.x == 0) s_next = atomicAdd(queue, 1);
+    __syncthreads();
+    const int64_t h = h0 + s_next < count ? (int64_t)ord[h0 + s_next] : count;
+    __syncthreads();  // s_next is written again for the next column
+    if (h >= count) break;
     const int64_t jj = list[h];
     const int64_t bb = base[h] - b0, elen = base[h + 1] - base[h];
     for (int t = threadIdx.x; t < kMaxSlabs; t += kMbThreads) {
@@ -3067,6 +3078,10 @@ static int merge_typed(const spgemm_csc *parts, int32_t n_parts, const int64_t *
   LAUNCHCHK();
   const int64_t hcap = std::max<int64_t>(1, hv_item_cap(L.ncol, L.P) / L.P);
   const int64_t ecap = L.mb_cap;
+  // chunks of the heavy list whose entries fit the bucket region, and in
+  // each chunk the columns by decreasing entry count (the bucketing order)
+  std::vector<int64_t> cuts{0};
+  std::vector<int32_t> ord((size_t)heavy);
   for (int64_t h0 = 0; h0 < heavy;) {
     int64_t h1 = h0 + 1;
     while (h1 < heavy && h1 - h0 < hcap && hb[h1 + 1] - hb[h0] <= ecap) h1++;
@@ -3075,13 +3090,25 @@ static int merge_typed(const spgemm_csc *parts, int32_t n_parts, const int64_t *
       LAUNCHCHK();
       return SPGEMM_OK;
     }
+    for (int64_t h = h0; h < h1; h++) ord[h] = (int32_t)h;
+    std::stable_sort(ord.begin() + h0, ord.begin() + h1,
+                     [&](int32_t x, int32_t y) { return hb[x + 1] - hb[x] > hb[y + 1] - hb[y]; });
+    cuts.push_back(h1);
+    h0 = h1;
+  }
+  int32_t *ord_d = (int32_t *)len;  // the lengths are no longer needed once scanned
+  HIPCHK(hipMemcpyAsync(ord_d, ord.data(), sizeof(int32_t) * (size_t)heavy, hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));  // `ord` is host memory freed on return
+  for (size_t c = 0; c + 1 < cuts.size(); c++) {
+    const int64_t h0 = cuts[c], h1 = cuts[c + 1];
     hipLaunchKernelGGL(k_hv_reset, dim3(1), dim3(64), 0, st, hdr);
     LAUNCHCHK();
     {
       ProfScope prof("merge_bucket", st);
-      const unsigned g = (unsigned)std::min<int64_t>(h1 - h0, 16 * (int64_t)device_cus());
+      const unsigned g = (unsigned)std::min<int64_t>(h1 - h0, 4 * (int64_t)device_cus());
       hipLaunchKernelGGL(k_mb_bucket<VT>, dim3(g), dim3(kMbThreads), 0, st, (const PartDesc *)pd, n_parts, L.m,
-                         (int)L.P, list, hcnt, h0, h1, (const int64_t *)base, ecap, soff, brow, bval, slots, status);
+                         (int)L.P, list, hcnt, h0, h1, (const int32_t *)ord_d, &hdr->mb_cursor,
+                         (const int64_t *)base, ecap, soff, brow, bval, slots, status);
       LAUNCHCHK();
     }
     ProfScope prof("merge_items", st);
@@ -3089,7 +3116,6 @@ static int merge_typed(const spgemm_csc *parts, int32_t n_parts, const int64_t *
     hipLaunchKernelGGL((k_hv_items<VT, MbSrc<VT, SR>>), dim3(4 * device_cus()), dim3(kHvThreads), 0, st, msrc, list,
                        (const uint32_t *)slots, h0, h1 - h0, hdr, c_colptr, hv_cur, c_rowidx, (VT *)c_values);
     LAUNCHCHK();
-    h0 = h1;
   }
   hipLaunchKernelGGL(k_hv_check, dim3(grid_of(heavy, 256)), dim3(256), 0, st, list, hcnt, c_colptr,
                      (const int32_t *)hv_cur, status);
