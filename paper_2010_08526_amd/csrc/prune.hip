@@ -86,6 +86,39 @@ __device__ __forceinline__ void hist_add(int *s_hist, bool act, int dig) {
   if (act && !same) atomicAdd(&s_hist[dig], 1);
 }
 
+// Wide first digit: the top kWideBits of the value key (sign, exponent and
+// the top mantissa bits of a float32), a 4096-bucket histogram; the bucket
+// holding the k-th largest key is then resolved in LDS when it holds at most
+// kStage candidates (gathered by a second pass, sorted by key), so most
+// columns are read twice whatever their length.
+constexpr int kWideBits = 12;
+constexpr int kWideBuckets = 1 << kWideBits;
+constexpr int kStage = 2048;
+
+// Bitonic sort of s_v / s_r (n a power of two), descending by (value key,
+// row key).  Contains barriers.
+__device__ __forceinline__ void stage_sort_desc(uint64_t *s_v, uint32_t *s_r, int n) {
+  for (int k = 2; k <= n; k <<= 1) {
+    for (int s = k >> 1; s > 0; s >>= 1) {
+      for (int t = threadIdx.x; t < n / 2; t += kPrThreads) {
+        const int a = ((t & ~(s - 1)) << 1) | (t & (s - 1));  // lower element of pair t at distance s
+        const int c = a + s;
+        const bool down = (a & k) == 0;  // this block of k sorts descending
+        const uint64_t va = s_v[a], vc = s_v[c];
+        const uint32_t ra = s_r[a], rc = s_r[c];
+        const bool lt = va < vc || (va == vc && ra < rc);  // key a below key c
+        if (lt == down) {
+          s_v[a] = vc;
+          s_v[c] = va;
+          s_r[a] = rc;
+          s_r[c] = ra;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // cnt[j]: entries column j keeps; (cutv[j], cutr[j]): the smallest kept key
 // ((0, 0) keeps every candidate).  The histogram of the first digit also
 // counts the candidates, so a column that keeps all of them is read once.
@@ -97,8 +130,14 @@ __global__ __launch_bounds__(kPrThreads) void k_prune_select(const int64_t *__re
                                                              uint64_t *__restrict__ cutv, uint32_t *__restrict__ cutr,
                                                              int32_t *status) {
   constexpr int VD = (int)sizeof(VT), ND = VD + 4;
+  constexpr int kShift = 8 * VD - kWideBits;  // value key bits below the wide digit
   __shared__ int s_hist[256];
   __shared__ int s_sel[4];  // chosen digit, entries still needed inside it, selection complete, candidates
+  // the wide histogram, then (same memory) the staged value keys of its chosen bucket
+  __shared__ __align__(16) uint64_t s_wide[kWideBuckets / 2];
+  __shared__ uint32_t s_srow[kStage];
+  __shared__ int s_n;
+  int *s_whist = reinterpret_cast<int *>(s_wide);
   const int t = threadIdx.x;
   for (int64_t j = blockIdx.x; j < ncols; j += gridDim.x) {
     int64_t b = colptr[j], e = colptr[j + 1];
@@ -111,7 +150,102 @@ __global__ __launch_bounds__(kPrThreads) void k_prune_select(const int64_t *__re
     int need = k >= 0 && k < INT32_MAX ? (int)k : INT32_MAX, above = 0, last = 0, kept = -1;
     uint64_t pv = 0;
     uint32_t pr = 0;
-    for (int d = 0; d < ND; d++) {
+    bool fast = k > 0 && k < INT32_MAX;  // the wide digit first; cleared when the digit loop must run
+    if (fast) {
+      for (int i = t; i < kWideBuckets; i += kPrThreads) s_whist[i] = 0;
+      __syncthreads();
+      for (int64_t c0 = b; c0 < e; c0 += kSelUnroll * kPrThreads) {
+        VT vq[kSelUnroll];
+#pragma unroll
+        for (int q = 0; q < kSelUnroll; q++) {
+          const int64_t p = c0 + q * kPrThreads + t;
+          vq[q] = p < e ? vals[p] : VT(0);
+        }
+#pragma unroll
+        for (int q = 0; q < kSelUnroll; q++) {
+          const int64_t p = c0 + q * kPrThreads + t;
+          const bool act = p < e && candidate(vq[q], thr);
+          hist_add(s_whist, act, act ? (int)(order_key(vq[q]) >> kShift) : 0);
+        }
+      }
+      __syncthreads();
+      if (t < kWave) {
+        // lane l owns buckets 4095 - 64l ... 4032 - 64l, scanned from the top
+        constexpr int PER = kWideBuckets / kWave;
+        int sum = 0;
+        for (int q = 0; q < PER; q++) sum += s_whist[kWideBuckets - 1 - PER * t - q];
+        const int incl = wave_incl_add(sum);
+        if (t == kWave - 1) s_sel[3] = incl;
+        int acc = incl - sum;
+        if (acc < need && need <= incl) {
+          for (int q = 0; q < PER; q++) {
+            const int h = s_whist[kWideBuckets - 1 - PER * t - q];
+            if (acc + h >= need) {
+              s_sel[0] = kWideBuckets - 1 - PER * t - q;
+              s_sel[1] = need - acc;
+              s_sel[2] = h;
+              break;
+            }
+            acc += h;
+          }
+        }
+      }
+      __syncthreads();
+      const int ncand = s_sel[3];
+      if (ncand <= need) {  // every candidate is kept
+        kept = ncand;
+      } else if (s_sel[2] <= kStage) {
+        // gather the chosen bucket's candidates, sort them, take the need-th largest
+        const uint64_t bucket = (uint64_t)s_sel[0];
+        const int rest = s_sel[1], nb = s_sel[2];
+        __syncthreads();  // s_sel and the histogram are read; the stage reuses its memory
+        if (t == 0) s_n = 0;
+        __syncthreads();
+        for (int64_t c0 = b; c0 < e; c0 += kSelUnroll * kPrThreads) {
+          VT vq[kSelUnroll];
+#pragma unroll
+          for (int q = 0; q < kSelUnroll; q++) {
+            const int64_t p = c0 + q * kPrThreads + t;
+            vq[q] = p < e ? vals[p] : VT(0);
+          }
+#pragma unroll
+          for (int q = 0; q < kSelUnroll; q++) {
+            const int64_t p = c0 + q * kPrThreads + t;
+            const uint64_t vk = order_key(vq[q]);
+            const bool in = p < e && candidate(vq[q], thr) && (vk >> kShift) == bucket;
+            const uint64_t m = __ballot(in);
+            if (m == 0) continue;  // uniform
+            int base = 0;
+            if (lane() == 0) base = atomicAdd(&s_n, __popcll(m));
+            base = readlane(base, 0);
+            const int pos = base + mbcnt(m);
+            if (in && pos < kStage) {
+              s_wide[pos] = vk;
+              s_srow[pos] = row_key(rowidx[p]);
+            }
+          }
+        }
+        __syncthreads();
+        int n2 = kWave;
+        while (n2 < nb) n2 <<= 1;
+        for (int i = nb + t; i < n2; i += kPrThreads) {  // padding sorts last
+          s_wide[i] = 0ull;
+          s_srow[i] = 0u;
+        }
+        __syncthreads();
+        stage_sort_desc(s_wide, s_srow, n2);
+        above = need - rest;
+        need = rest;
+        pv = s_wide[rest - 1];
+        pr = s_srow[rest - 1];
+        kept = (int)k;
+        __syncthreads();  // the stage is rewritten by the next column
+      } else {
+        fast = false;  // the bucket is too full to stage: the digit loop decides
+        __syncthreads();
+      }
+    }
+    for (int d = 0; d < ND && !fast; d++) {
       for (int i = t; i < 256; i += kPrThreads) s_hist[i] = 0;
       if (t == 0) {
         s_sel[0] = 0;

@@ -61,6 +61,27 @@ def test_prune_long_columns(dtype, k):
         _assert_exact(G, oracle.prune_topk(M, thr, k), f"long {thr} {k}")
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_prune_continuous_values(dtype):
+    """Few ties: values spread over many binades (the first, 12-bit digit
+    splits them finely and the chosen bucket is resolved in LDS) and values
+    packed into one binade (the bucket holds too many candidates for LDS and
+    the byte digits decide), in columns of 10 ... 120,000 entries."""
+    print(f"case: prune continuous {dtype}", flush=True)
+    rng = np.random.default_rng(23)
+    lens = [10, 150, 2047, 2049, 5000, 40000, 120000, 70000, 3000]
+    m = 200_000
+    cp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    ri = np.concatenate([rng.choice(m, n, replace=False) for n in lens]).astype(np.int32)
+    wide = np.exp(rng.uniform(-30, 5, ri.size)) * rng.choice([-1.0, 1.0], ri.size, p=[0.1, 0.9])
+    narrow = 1.0 + rng.random(ri.size)  # one binade: [1, 2)
+    for name, v in (("wide", wide), ("narrow", narrow)):
+        M = synth.CSC(m, len(lens), torch.from_numpy(cp), torch.from_numpy(ri), torch.from_numpy(v).to(dtype))
+        for thr, k in ((-np.inf, 1), (0.0, 100), (-np.inf, 1000), (1e-6, 3000)):
+            G = S.prune_topk(M.to("cuda"), thr, k)
+            _assert_exact(G, oracle.prune_topk(M, thr, k), f"continuous {name} {thr} {k}")
+
+
 def test_prune_more_columns_than_workgroups():
     """70,000 columns: more than the grid, so workgroups take several columns."""
     print("case: prune 70000 columns", flush=True)
