@@ -99,6 +99,7 @@ struct WsHeader {
   int32_t nwide;        // wide heavy columns listed for the current chunk
   int32_t wide_cursor;  // work-queue position over their items
   int32_t mb_cursor;    // merge: work-queue position over the chunk's heavy columns (bucketing)
+  int32_t split_cursor; // numeric: work-queue position over the columns of A (slabbed copy)
   uint64_t left_tag;    // fingerprint (| 1) of the source of the slabbed copy of A in the workspace; 0 = none
   uint64_t left_new;    // fingerprint of the current call's left operand (summed by k_left_sum)
   int32_t esc_count[2];  // row-sorted product: columns listed for the two expand-sort-compress kernels

@@ -447,6 +447,7 @@ __global__ void k_init_header(WsHeader *h, uint64_t keep_tag, int keep_status = 
     for (int b = 0; b < kNumBins; b++) h->bin_count[b] = 0;
     for (int b = 0; b < kNumBins; b++) h->cursor[b] = 0;
     h->esc_count[0] = h->esc_count[1] = 0;
+    h->split_cursor = 0;
     h->items = 0;
     h->item_cursor = 0;
     h->nwide = 0;
@@ -1237,50 +1238,64 @@ struct __align__(16) SlabEnt<double> {
   double v;
 };
 
+constexpr int kSplitCols = 16;  // columns of A a wave takes from the work queue at once
+
 template <class VT>
 __global__ __launch_bounds__(256) void k_slab_split(const int64_t *Acp, const int32_t *Ari, const VT *Av,
                                                     int64_t klo, int64_t khi, int64_t m, int P, int32_t *soff,
                                                     SlabEnt<VT> *s_ent, const int32_t *heavy_count,
-                                                    int32_t *status, const WsHeader *hdr) {
+                                                    int32_t *status, WsHeader *hdr) {
   __shared__ int s_hist[4][kMaxSlabs + 1];
   const int w = threadIdx.x / kWave, l = lane();
-  const int64_t k = klo + (int64_t)blockIdx.x * 4 + w;
-  if (k >= khi || *heavy_count == 0 || left_is_current(hdr)) return;
+  // a resident grid whose waves take columns from a work queue (column
+  // lengths are uneven): a call whose copy is current, or that has no heavy
+  // column, returns from a small grid
+  if (*heavy_count == 0 || left_is_current(hdr)) return;
   int *h = s_hist[w];
-  for (int t = l; t <= P; t += kWave) h[t] = 0;
-  wave_sync();
-  const int64_t a0 = Acp[k], a1 = Acp[k + 1];
-  bool bad = false;
-  for (int64_t p = a0 + l; p < a1; p += kWave) {
-    const int32_t row = Ari[p];
-    bad |= row < 0 || row >= m;
-    const uint32_t sl = min((uint32_t)row >> kSlabShift, (uint32_t)(P - 1));
-    atomicAdd(&h[sl], 1);
-  }
-  if (__ballot(bad) && l == 0) flag_error(status, 3);
-  wave_sync();
-  int32_t *o = soff + (k - klo) * (int64_t)(P + 1);
-  int carry = 0;
-  for (int t0 = 0; t0 < P; t0 += kWave) {
-    const int t = t0 + l;
-    const int c = t < P ? h[t] : 0;
-    const int incl = wave_incl_add(c);
-    if (t < P) {
-      o[t] = carry + incl - c;
-      h[t] = carry + incl - c;
+  for (;;) {
+    int q = 0;
+    if (l == 0) q = atomicAdd(&hdr->split_cursor, kSplitCols);
+    const int64_t kq = klo + readlane(q, 0);
+    if (kq >= khi) break;
+    const int64_t kend = min(khi, kq + kSplitCols);
+    for (int64_t k = kq; k < kend; k++) {
+      for (int t = l; t <= P; t += kWave) h[t] = 0;
+      wave_sync();
+      const int64_t a0 = Acp[k], a1 = Acp[k + 1];
+      bool bad = false;
+      for (int64_t p = a0 + l; p < a1; p += kWave) {
+        const int32_t row = Ari[p];
+        bad |= row < 0 || row >= m;
+        const uint32_t sl = min((uint32_t)row >> kSlabShift, (uint32_t)(P - 1));
+        atomicAdd(&h[sl], 1);
+      }
+      if (__ballot(bad) && l == 0) flag_error(status, 3);
+      wave_sync();
+      int32_t *o = soff + (k - klo) * (int64_t)(P + 1);
+      int carry = 0;
+      for (int t0 = 0; t0 < P; t0 += kWave) {
+        const int t = t0 + l;
+        const int c = t < P ? h[t] : 0;
+        const int incl = wave_incl_add(c);
+        if (t < P) {
+          o[t] = carry + incl - c;
+          h[t] = carry + incl - c;
+        }
+        carry += readlane(incl, 63);
+      }
+      if (l == 0) o[P] = carry;
+      wave_sync();
+      for (int64_t p = a0 + l; p < a1; p += kWave) {
+        const int32_t row = Ari[p];
+        const uint32_t sl = min((uint32_t)row >> kSlabShift, (uint32_t)(P - 1));
+        const int pos = atomicAdd(&h[sl], 1);
+        SlabEnt<VT> e;
+        e.row = row;
+        e.v = Av[p];
+        s_ent[a0 + pos] = e;
+      }
+      wave_sync();  // the next column clears h
     }
-    carry += readlane(incl, 63);
-  }
-  if (l == 0) o[P] = carry;
-  wave_sync();
-  for (int64_t p = a0 + l; p < a1; p += kWave) {
-    const int32_t row = Ari[p];
-    const uint32_t sl = min((uint32_t)row >> kSlabShift, (uint32_t)(P - 1));
-    const int pos = atomicAdd(&h[sl], 1);
-    SlabEnt<VT> e;
-    e.row = row;
-    e.v = Av[p];
-    s_ent[a0 + pos] = e;
   }
 }
 
@@ -1294,26 +1309,31 @@ __global__ __launch_bounds__(256) void k_seg_pack(const int32_t *off, const int6
   __shared__ int32_t tile[64][66];
   __shared__ int64_t s_a0[64];
   if (*heavy_count == 0 || left_is_current(hdr)) return;
-  const int64_t k0 = (int64_t)blockIdx.x * 64;
-  const int s0 = (int)blockIdx.y * 64;
-  const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
-  for (int r = ty; r < 64; r += 4) {  // rows k, columns s (65 of them: s0 .. s0 + 64)
-    const int64_t k = k0 + r;
-    if (k < kc) {
-      const int sl = s0 + tx;
-      if (sl <= P) tile[r][tx] = off[k * (P + 1) + sl];
-      if (tx == 0 && s0 + 64 <= P) tile[r][64] = off[k * (P + 1) + s0 + 64];
+  // a persistent grid over the 64 x 64 tiles (k tiles fastest)
+  const int64_t nkt = (kc + 63) / 64, ntile = nkt * ((P + 63) / 64);
+  for (int64_t ti = blockIdx.x; ti < ntile; ti += gridDim.x) {
+    const int64_t k0 = (ti % nkt) * 64;
+    const int s0 = (int)(ti / nkt) * 64;
+    const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
+    for (int r = ty; r < 64; r += 4) {  // rows k, columns s (65 of them: s0 .. s0 + 64)
+      const int64_t k = k0 + r;
+      if (k < kc) {
+        const int sl = s0 + tx;
+        if (sl <= P) tile[r][tx] = off[k * (P + 1) + sl];
+        if (tx == 0 && s0 + 64 <= P) tile[r][64] = off[k * (P + 1) + s0 + 64];
+      }
     }
-  }
-  if (threadIdx.x < 64 && k0 + threadIdx.x < kc) s_a0[threadIdx.x] = Acp[klo + k0 + threadIdx.x];
-  __syncthreads();
-  for (int r = ty; r < 64; r += 4) {  // rows s, columns k
-    const int sl = s0 + r;
-    const int64_t k = k0 + tx;
-    if (sl < P && k < kc) {
-      const int32_t b0 = tile[tx][r], b1 = tile[tx][r + 1];
-      pack[(int64_t)sl * kc + k] = ((uint64_t)(s_a0[tx] + b0) << kSegLenBits) | (uint64_t)(uint32_t)(b1 - b0);
+    if (threadIdx.x < 64 && k0 + threadIdx.x < kc) s_a0[threadIdx.x] = Acp[klo + k0 + threadIdx.x];
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {  // rows s, columns k
+      const int sl = s0 + r;
+      const int64_t k = k0 + tx;
+      if (sl < P && k < kc) {
+        const int32_t b0 = tile[tx][r], b1 = tile[tx][r + 1];
+        pack[(int64_t)sl * kc + k] = ((uint64_t)(s_a0[tx] + b0) << kSegLenBits) | (uint64_t)(uint32_t)(b1 - b0);
+      }
     }
+    __syncthreads();  // the next tile rewrites tile and s_a0
   }
 }
 
@@ -1715,6 +1735,11 @@ struct HvProductSrc {
   }
 };
 
+// Items are taken from the work queue in batches: the items starting at one
+// slab in kItemCols consecutive heavy columns (one wave reads their slots).
+constexpr int kItemCols = 64;
+static_assert(kItemCols <= kWave, "one slot per lane");
+
 template <class VT, class Src>
 __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t *list,
                                                          const uint32_t *slots, int64_t h0, int64_t hc,
@@ -1746,7 +1771,7 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
   const int P = src.P;
   const int64_t nheavy = hdr->bin_count[kNumBins - 1];
   hc = min(hc, max(nheavy - h0, (int64_t)0));  // the device count bounds a chunk sized on the host
-  const int64_t nb = (hc + kWave - 1) / kWave;
+  const int64_t nb = (hc + kItemCols - 1) / kItemCols;
   const int64_t nbatch = nb * P;
   double *acc = (double *)s_tab;
   uint32_t *bits = (uint32_t *)(s_tab + kBitsOff);
@@ -1764,12 +1789,12 @@ __global__ __launch_bounds__(kHvThreads) void k_hv_items(Src src, const int32_t 
     const int64_t bi = s_batch;
     if (bi >= nbatch) break;
     const int t = (int)(bi / nb);
-    const int64_t hb = (bi % nb) * kWave;
+    const int64_t hb = (bi % nb) * kItemCols;
     if (w == 0) {  // the batch's items: slot, column, input range and output column, one per lane
       const int64_t hl = hb + l;
       uint32_t e = 0u;
       int32_t jj = 0;
-      if (hl < hc && h0 + hl < nheavy) {
+      if (l < kItemCols && hl < hc && h0 + hl < nheavy) {
         e = slots[hl * P + t];
         jj = list[h0 + hl];
       }
@@ -2958,11 +2983,12 @@ static int numeric_typed(const spgemm_csc *A, const spgemm_csc *B, int64_t c0, i
       hipLaunchKernelGGL(k_left_sum<VT>, dim3((unsigned)(4 * device_cus())), dim3(256), 0, st, A->colptr, A->rowidx,
                          (const VT *)A->values, klo, khi, seed, hdr, hc);
       LAUNCHCHK();
-      hipLaunchKernelGGL(k_slab_split<VT>, dim3(grid_of(khi - klo, 4)), dim3(256), 0, st, A->colptr, A->rowidx,
-                         (const VT *)A->values, klo, khi, A->nrows, (int)L.P, soff, s_ent, hc, &hdr->status,
-                         (const WsHeader *)hdr);
+      const unsigned pgrid = (unsigned)(8 * device_cus());
+      hipLaunchKernelGGL(k_slab_split<VT>, dim3(std::min(grid_of(khi - klo, 4), (unsigned)(4 * device_cus()))),
+                         dim3(256), 0, st, A->colptr, A->rowidx, (const VT *)A->values, klo, khi, A->nrows, (int)L.P,
+                         soff, s_ent, hc, &hdr->status, hdr);
       LAUNCHCHK();
-      hipLaunchKernelGGL(k_seg_pack, dim3(grid_of(khi - klo, 64), (unsigned)((L.P + 63) / 64)), dim3(256), 0, st,
+      hipLaunchKernelGGL(k_seg_pack, dim3(std::min(grid_of(khi - klo, 64) * (unsigned)((L.P + 63) / 64), pgrid)), dim3(256), 0, st,
                          (const int32_t *)soff, A->colptr, klo, khi - klo, (int)L.P, (uint64_t *)(ws + L.slab_pack), hc,
                          (const WsHeader *)hdr);
       LAUNCHCHK();
