@@ -98,3 +98,42 @@ def budget_for_batches(S, eng, plan, nb: int) -> int:
             best, hi = mid, mid - 1
     assert best is not None
     return eng.input_bytes + eng.reserve_bytes + best
+
+
+def weighted_column_sums_expected(A, B, w):
+    """For every column j of C = A B: e_j = sum_i w_i C(i,j), formed as
+    (w^T A) B(:,j), and b_j = sum over product terms of |w_i A(i,k) B(k,j)|,
+    in float64 on the host.  A property of the product that holds at any
+    size: a wrong, missing or repeated row, or a wrong value, in column j
+    moves sum_i w_i C(i,j) away from e_j (weights are distinct per row)."""
+    A, B = oracle.as_mat(A), oracle.as_mat(B)
+    acol = np.repeat(np.arange(A.ncols, dtype=np.int32), np.diff(A.colptr))
+    bcol = np.repeat(np.arange(B.ncols, dtype=np.int32), np.diff(B.colptr))
+    t = w[A.rowidx] * A.values.astype(np.float64)
+    wa = np.bincount(acol, weights=t, minlength=A.ncols)
+    wabs = np.bincount(acol, weights=np.abs(t), minlength=A.ncols)
+    bv = B.values.astype(np.float64)
+    e = np.bincount(bcol, weights=wa[B.rowidx] * bv, minlength=B.ncols)
+    b = np.bincount(bcol, weights=wabs[B.rowidx] * np.abs(bv), minlength=B.ncols)
+    return e, b
+
+
+def weighted_column_sums(C, values, w_dev, chunk=1 << 27):
+    """sum_i w_i C(i,j) for every column of a device CSC (float64, device
+    segment sums over column chunks of at most `chunk` entries)."""
+    cp_h = C.colptr.cpu().numpy().astype(np.int64)
+    cp_h = cp_h - cp_h[0]
+    base = int(C.colptr[0])
+    out = torch.zeros(C.ncols, dtype=torch.float64, device=C.rowidx.device)
+    lens = (C.colptr[1:] - C.colptr[:-1])
+    a = 0
+    while a < C.ncols:
+        b = a + 1
+        hi = np.searchsorted(cp_h, cp_h[a] + chunk, side="right") - 1
+        b = max(b, min(C.ncols, int(hi)))
+        s, e = base + int(cp_h[a]), base + int(cp_h[b])
+        if e > s:
+            x = w_dev[C.rowidx[s:e].long()] * values[s:e].double()
+            out[a:b] = torch.segment_reduce(x, "sum", lengths=lens[a:b])
+        a = b
+    return out.cpu().numpy()

@@ -3,7 +3,9 @@ configuration the benchmark times.  The products are too large for the
 oracle as a whole, so sampled output columns (always including the heaviest
 ones) are computed by the oracle column by column and compared to the bar
 of the other parity tests: structure bit-exact, values within 1e-5 of
-sum |a*b| (float32 data)."""
+sum |a*b| (float32 data).  Every column is also checked through a property
+that holds at any size: its row-weighted sum sum_i w_i C(i,j) equals
+(w^T A) B(:,j) within the same bar (weights distinct per row)."""
 from __future__ import annotations
 
 import numpy as np
@@ -12,7 +14,8 @@ import torch
 
 import oracle
 import synth
-from tests.gpu_util import TOL, assert_matches, budget_for_batches, host_sorted
+from tests.gpu_util import (TOL, assert_matches, budget_for_batches, host_sorted, weighted_column_sums,
+                            weighted_column_sums_expected)
 
 pytestmark = pytest.mark.gpu
 
@@ -78,9 +81,21 @@ def test_rmat20_four_batches_sampled():
     eng.budget_bytes = budget_for_batches(S, eng, plan, 4)
     fl = plan.flops.cpu().numpy()
     smp = _Sampler(fl, top=3, rand=40, seed=20)
-    pl = eng.run(consume=smp)
+    w = np.random.default_rng(21).uniform(1.0, 2.0, A.nrows)
+    wd = torch.from_numpy(w).cuda()
+    got = np.zeros(A.ncols)
+
+    def consume(c0, c1, Cb):
+        smp(c0, c1, Cb)
+        got[c0:c1] = weighted_column_sums(Cb, Cb.values, wd)
+
+    pl = eng.run(consume=consume)
     assert pl.nbatches == 4
     Ah = oracle.as_mat(A.to("cpu"))
+    # every column of the product: its row-weighted sum (a property that holds at any size)
+    e, b = weighted_column_sums_expected(Ah, Ah, w)
+    bad = np.nonzero(np.abs(got - e) > TOL[torch.float32] * b)[0]
+    assert bad.size == 0, f"rmat20: {bad.size} columns off in their weighted sums, first {bad[:5]}"
     n = smp.check(Ah, Ah, torch.float32, "rmat20")
     assert n >= 4 * 40
     # the three heaviest columns of the whole product are among those checked
@@ -93,11 +108,15 @@ def test_protein2m_16_layers_64gb_sampled():
     A = synth.protein_like(2_000_000, w.seed, dtype=torch.float32, device="cuda")
     eng = S.Engine(A, A, 16, budget_bytes=64 * 10**9)
     fl_holder = {}
+    w = np.random.default_rng(31).uniform(1.0, 2.0, A.nrows)
+    wd = torch.from_numpy(w).cuda()
+    got = np.zeros(A.ncols)
 
     def consume(c0, c1, Cb):
         if "s" not in fl_holder:
             fl_holder["s"] = _Sampler(eng.flops.cpu().numpy(), top=2, rand=12, seed=30)
         fl_holder["s"](c0, c1, Cb)
+        got[c0:c1] = weighted_column_sums(Cb, Cb.values, wd)
 
     pl = eng.run(consume=consume)
     print(f"protein2m: {pl.nbatches} batches", flush=True)
@@ -105,6 +124,9 @@ def test_protein2m_16_layers_64gb_sampled():
     # partials of every layer are merged: the batch totals agree with the union counts
     assert int(pl.batch_nnz[:, 16].sum()) == int(pl.nnz_host[16].sum())
     Ah = oracle.as_mat(A.to("cpu"))
+    e, b = weighted_column_sums_expected(Ah, Ah, w)
+    bad = np.nonzero(np.abs(got - e) > TOL[torch.float32] * b)[0]
+    assert bad.size == 0, f"protein2m: {bad.size} columns off in their weighted sums, first {bad[:5]}"
     smp = fl_holder["s"]
     assert smp.check(Ah, Ah, torch.float32, "protein2m") >= pl.nbatches * 12
 
@@ -159,6 +181,12 @@ def test_batch4096_sampled_instances():
     eng = Bt.BatchedEngine(A, B, backward=True)
     eng.forward()
     eng.check()
+    # every column of every instance: its row-weighted sum (a property that holds at any size)
+    w = np.random.default_rng(41).uniform(1.0, 2.0, A.nrows)
+    got = weighted_column_sums(eng.C, eng.values, torch.from_numpy(w).cuda())
+    e, b = weighted_column_sums_expected(A.to("cpu"), B.to("cpu"), w)
+    bad = np.nonzero(np.abs(got - e) > TOL[torch.float32] * b)[0]
+    assert bad.size == 0, f"batch4096: {bad.size} columns off in their weighted sums, first {bad[:5]}"
     flops = np.asarray(spec.n * spec.dA * spec.dB, dtype=np.int64)
     rng = np.random.default_rng(40)
     pick = np.unique(np.concatenate([[int(np.argmax(flops)), int(np.argmin(flops))], rng.choice(4096, 6, replace=False)]))
