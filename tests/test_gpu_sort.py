@@ -174,7 +174,7 @@ def _chunky(dtype, seed):
     return A, B
 
 
-@pytest.mark.parametrize("case", ["er4096", "rmat14_batches", "chunky32", "chunky64"])
+@pytest.mark.parametrize("case", ["er4096", "rmat14_batches", "chunky32", "chunky64", "tall"])
 @pytest.mark.parametrize("cf", [0.0, 1.5, 4.0, 1e9])
 def test_hybrid_sorted_product(case, cf):
     """The row-sorted product with the per-column choice of kernel: every
@@ -189,10 +189,15 @@ def test_hybrid_sorted_product(case, cf):
     elif case == "rmat14_batches":
         A = synth.rmat(14, 16, 5, dtype=torch.float32)
         B, dtype, nb = A, torch.float32, 5
+    elif case == "tall":  # 9,000,000 rows: heavy columns on the global accumulators, the rest in LDS
+        from tests.test_gpu_global_heavy import COUNTS, _right, _tall_left
+        A = _tall_left(torch.float32, seed=91)
+        B = _right(A.ncols, COUNTS, torch.float32, seed=92)
+        dtype = torch.float32
     else:
         dtype = torch.float32 if case == "chunky32" else torch.float64
         A, B = _chunky(dtype, 61)
-    if cf == 4.0 and case != "er4096":  # (er4096's columns all hold 65-4096 terms)
+    if cf == 4.0 and case not in ("er4096", "tall"):  # (er4096's columns all hold 65-4096 terms)
         w, b, h = _esc_classes(A, B, cf)
         assert w > 0 and b > 0 and h > 0, (w, b, h)  # all three kernel classes reached
     eng = S.Engine(A.to("cuda"), B.to("cuda"), 1, sorted_output=True, esc_cf=cf)
