@@ -1461,9 +1461,12 @@ struct HvArgs {
 // one 64-bit word per round marks the positions where a segment starts, so
 // the owner of element e is (segments starting before the round) + (starts
 // in the round at or below e) - 1: a ballot, a population count and a mask
-// count, with no scan.  kHvPipe rounds' gathers are kept in flight;
-// segments of kLongSeg or more elements are streamed by the whole wave.
-constexpr int kHvPipe = 4;
+// count, with no scan.  Rounds are taken in blocks of PIPE consecutive ones
+// (dealt to the waves in turn when they share a chunk), whose gathers are
+// kept in flight together; segments of kLongSeg or more elements are
+// streamed by the whole wave.
+constexpr int kHvPipe = 4;      // the item kernel
+constexpr int kHvWidePipe = 8;  // the wide kernel (one workgroup per CU: deeper blocks pay)
 constexpr int kHvVec = 4;
 constexpr int kHvBlk = kWave * kHvVec;
 
@@ -1527,10 +1530,11 @@ struct HvScratch {
 
 // pre: the wave's first chunk loaded ahead (same pbeg, pend, sa, sb, w, nw,
 // cs_min), or nullptr.
-template <class VT, class Mul = SrPlusTimes, class Ins>
+template <class VT, class Mul = SrPlusTimes, int PIPE = kHvPipe, class Ins>
 __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t pbeg, int64_t pend, int sa, int sb, int w,
                                            int nw, int cs_min, HvScratch<VT> &sc, const HvPre<VT> *pre,
                                            Ins &&ins) {
+  static_assert(kWave % PIPE == 0, "round blocks do not straddle a start-mask refill");
   const int l = lane();
   const int nchunk = (int)((pend - pbeg + kWave - 1) / kWave);
   const bool csplit = nchunk >= cs_min * nw;
@@ -1602,34 +1606,35 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t pbeg, in
         if (ls > 0 && rr >= 0 && rr < kWave) atomicOr((unsigned long long *)&sc.rmask[rr], 1ull << (excl & 63));
         wave_sync();
         const int gend = min(nround, g + kWave);
-        int rf = (r0 - g) % r_stride;
+        // blocks of PIPE consecutive rounds, dealt to the waves in turn
+        int rf = (r0 - g / PIPE) % r_stride;
         if (rf < 0) rf += r_stride;
-        for (int r = g + rf; r < gend; r += kHvPipe * r_stride) {
-          const int rl = r + (kHvPipe - 1) * r_stride;  // the group's last round
+        for (int r = g + rf * PIPE; r < gend; r += PIPE * r_stride) {
+          const int rl = r + PIPE - 1;  // the block's last round
           if (rl < gend && (rl + 1) * kWave <= total) {  // uniform: every lane of every round holds an element
-            int own_[kHvPipe];
+            int own_[PIPE];
 #pragma unroll
-            for (int u = 0; u < kHvPipe; u++) {
-              const int ru = r + u * r_stride;
+            for (int u = 0; u < PIPE; u++) {
+              const int ru = r + u;
               const uint64_t m = sc.rmask[ru - g];
               const int carry = __popcll(__ballot(ls > 0 && excl < ru * kWave));
               own_[u] = carry + mbcnt(m) + (int)((m >> l) & 1ull) - 1;
             }
-            SegInfo<VT> inf_[kHvPipe];
+            SegInfo<VT> inf_[PIPE];
 #pragma unroll
-            for (int u = 0; u < kHvPipe; u++) inf_[u] = sc.info[own_[u]];
-            SlabEnt<VT> e_[kHvPipe];
+            for (int u = 0; u < PIPE; u++) inf_[u] = sc.info[own_[u]];
+            SlabEnt<VT> e_[PIPE];
 #pragma unroll
-            for (int u = 0; u < kHvPipe; u++) e_[u] = a.ent[inf_[u].offm + (uint32_t)((r + u * r_stride) * kWave + l)];
+            for (int u = 0; u < PIPE; u++) e_[u] = a.ent[inf_[u].offm + (uint32_t)((r + u) * kWave + l)];
 #pragma unroll
-            for (int u = 0; u < kHvPipe; u++)
+            for (int u = 0; u < PIPE; u++)
               ins(opaque(e_[u].row), Mul::mul((double)opaque(e_[u].v), (double)inf_[u].b));
             continue;
           }
-          int own_[kHvPipe];
+          int own_[PIPE];
 #pragma unroll
-          for (int u = 0; u < kHvPipe; u++) {
-            const int ru = r + u * r_stride;
+          for (int u = 0; u < PIPE; u++) {
+            const int ru = r + u;
             own_[u] = -1;
             if (ru < gend) {
               const int fb = ru * kWave;
@@ -1639,25 +1644,25 @@ __device__ __forceinline__ int hv_traverse(const HvArgs<VT> &a, int64_t pbeg, in
               if (fb + l < total) own_[u] = o;
             }
           }
-          SegInfo<VT> inf_[kHvPipe];
+          SegInfo<VT> inf_[PIPE];
 #pragma unroll
-          for (int u = 0; u < kHvPipe; u++)
+          for (int u = 0; u < PIPE; u++)
             if (own_[u] >= 0) inf_[u] = sc.info[own_[u]];
           // gathers only; the loaded values are used after every load is issued
-          SlabEnt<VT> e_[kHvPipe];
+          SlabEnt<VT> e_[PIPE];
 #pragma unroll
-          for (int u = 0; u < kHvPipe; u++) {
+          for (int u = 0; u < PIPE; u++) {
             e_[u].row = 0;
             e_[u].v = VT(0);
-            if (own_[u] >= 0) e_[u] = a.ent[inf_[u].offm + (uint32_t)((r + u * r_stride) * kWave + l)];
+            if (own_[u] >= 0) e_[u] = a.ent[inf_[u].offm + (uint32_t)((r + u) * kWave + l)];
           }
 #pragma unroll
-          for (int u = 0; u < kHvPipe; u++)
+          for (int u = 0; u < PIPE; u++)
             if (own_[u] >= 0) ins(opaque(e_[u].row), Mul::mul((double)opaque(e_[u].v), (double)inf_[u].b));
         }
         wave_sync();
       }
-      units += nround;
+      units += (nround + PIPE - 1) / PIPE;
     }
     uint64_t lm = __ballot(lg);
     while (lm) {
@@ -1722,7 +1727,7 @@ struct HvProductSrc {
     hi = a.Bcp[c0 + jj + 1];
   }
   using Pre = HvPre<VT>;
-  static constexpr int kCsMin = 2;
+  static constexpr int kCsMin = 1;
   __device__ __forceinline__ void pre_b(int64_t lo, int64_t hi, int w, int nw, Pre &pre) const {
     hv_pre_b<VT>(a, lo, hi, w, nw, kCsMin, pre);
   }
@@ -2320,7 +2325,7 @@ __global__ __launch_bounds__(kHvWideThreads) void k_hv_wide(HvArgs<VT> a, int64_
     if (threadIdx.x < kWords) s_bits[threadIdx.x] = 0u;
     __syncthreads();
     int outside = 0;
-    int bad = hv_traverse<VT, SR>(a, a.Bcp[col], a.Bcp[col + 1], sa, sb, w, NW, 1, s_sc[w], (const HvPre<VT> *)nullptr, [&](int32_t row, double v) {
+    int bad = hv_traverse<VT, SR, kHvWidePipe>(a, a.Bcp[col], a.Bcp[col + 1], sa, sb, w, NW, 1, s_sc[w], (const HvPre<VT> *)nullptr, [&](int32_t row, double v) {
       const uint32_t r = (uint32_t)row - rb;
       if (r < (uint32_t)kHvWideRows) {
         SR::acc(&s_acc[r], v);
