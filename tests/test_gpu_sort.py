@@ -262,3 +262,26 @@ def test_hybrid_raw_entry_matches_hash_path():
     got = v[off:tot].cpu().numpy()
     assert np.array_equal(ri[off:tot].cpu().numpy(), P.rowidx)
     assert np.all(np.abs(got - P.values) <= TOL[torch.float64] * P.absum)
+
+
+@pytest.mark.parametrize("min_bin", [0, 5])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_sorted_heavy_items(min_bin, dtype):
+    """Row-sorted product whose heavy columns take every item kind on 8 row
+    slabs: dense items (crowded slabs), hash items (sparse slabs), wide
+    columns (more than 1024 entries of B), and with every column forced onto
+    the heavy path (min_bin 5) light ones as hash items too; rows in order,
+    against the oracle."""
+    print(f"case: sorted heavy items {dtype} min_bin={min_bin}", flush=True)
+    from tests.test_gpu_global_heavy import _right
+    A = synth.erdos_renyi(30_000, 3000, 12, 101, dtype)
+    B = _right(3000, [1500, 2000, 700, 300, 50, 1100, 5, 0, 1024, 1025, 400, 650, 3000, 1], dtype, seed=102)
+    P = oracle.spgemm(A, B)
+    assert (np.diff(P.colptr) > 5120).sum() >= 6  # heavy columns, on 8 row slabs
+    try:
+        S._lib.spgemm_debug_min_bin(min_bin)
+        for cf in (0.0, 2.0):
+            C, _ = S.Engine(A.to("cuda"), B.to("cuda"), 1, sorted_output=True, esc_cf=cf).run()
+            _assert_sorted_matches(C, P, dtype, f"heavy items cf={cf}")
+    finally:
+        S._lib.spgemm_debug_min_bin(0)
