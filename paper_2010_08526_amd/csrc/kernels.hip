@@ -789,8 +789,10 @@ __device__ __forceinline__ void init_mark(void *scratch) {
 // Writes the occupied slots [s_lo, s_hi) of a table, in slot order, to
 // consecutive output positions from o on (one wave; positions at or beyond
 // `end` are not written).  Returns the position after the last entry.
+// The slots it reads are left empty (key kEmpty, value 0), so a table stays
+// clear between columns without a clearing pass.
 template <class VT, class SR>
-__device__ __forceinline__ int64_t compact_run(const int32_t *keys, const double *vals, int s_lo, int s_hi,
+__device__ __forceinline__ int64_t compact_run(int32_t *keys, double *vals, int s_lo, int s_hi,
                                                int64_t o, int64_t end, int32_t *out_ri, VT *out_v) {
   const int l = lane();
   for (int s0 = s_lo; s0 < s_hi; s0 += kWave) {
@@ -799,9 +801,14 @@ __device__ __forceinline__ int64_t compact_run(const int32_t *keys, const double
     const bool occ = key != kEmpty;
     const uint64_t mask = __ballot(occ);
     const int64_t q = o + mbcnt(mask);
-    if (occ && q < end) {
-      out_ri[q] = key;
-      out_v[q] = (VT)SR::out(vals[s]);
+    if (occ) {
+      const double x = vals[s];
+      keys[s] = kEmpty;
+      vals[s] = 0.0;
+      if (q < end) {
+        out_ri[q] = key;
+        out_v[q] = (VT)SR::out(x);
+      }
     }
     o += __popcll(mask);
   }
@@ -832,6 +839,9 @@ __global__ __launch_bounds__(256) void k_num_wave(Src src, const int32_t *list, 
   int32_t *keys = s_keys[w];
   double *vals = s_vals[w];
   init_mark<VT>(s_sc[w]);
+  // cleared once: every compaction leaves the table empty again
+  for (int s = l; s < TBL / 4; s += kWave) reinterpret_cast<int4 *>(keys)[s] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
+  for (int s = l; s < TBL / 2; s += kWave) reinterpret_cast<double2 *>(vals)[s] = make_double2(0.0, 0.0);
   // columns idx, idx + stride, ...: while one is processed, the next one's
   // output range, B range and first chunk are loaded (Src::pre_*), and the
   // list entry of the one after
@@ -862,8 +872,6 @@ __global__ __launch_bounds__(256) void k_num_wave(Src src, const int32_t *list, 
       ce = ld_global(c_colptr + jn + 1 + z);
       jn2 = idx + 2 * stride < count ? ld_global(list + idx + 2 * stride + z) : 0;
     }
-    for (int s = l; s < TBL / 4; s += kWave) reinterpret_cast<int4 *>(keys)[s] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
-    for (int s = l; s < TBL / 2; s += kWave) reinterpret_cast<double2 *>(vals)[s] = make_double2(0.0, 0.0);
     wave_sync();
     src.visit_pre(jj, cur, s_sc[w], status,
                   [&](int32_t row, double v) { ht_accumulate_sr<typename Src::Sr>(keys, vals, TBL, row, v); });
@@ -890,6 +898,10 @@ __global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *l
   const int w = threadIdx.x / kWave, l = lane();
   const int count = *count_p;
   init_mark<VT>(s_sc[w]);
+  // cleared once: every compaction leaves the table empty again
+  for (int s = threadIdx.x; s < TBL / 4; s += THREADS)
+    reinterpret_cast<int4 *>(s_keys)[s] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
+  for (int s = threadIdx.x; s < TBL / 2; s += THREADS) reinterpret_cast<double2 *>(s_vals)[s] = make_double2(0.0, 0.0);
   // columns item, item + gridDim.x, ...: the next column's output range, B
   // range and each wave's first chunk are loaded while one is processed
   const int64_t z = opaque((int64_t)0);  // per-lane addresses: vector loads
@@ -918,9 +930,6 @@ __global__ __launch_bounds__(THREADS) void k_num_block(Src src, const int32_t *l
       ce = ld_global(c_colptr + jn + 1 + z);
       jn2 = item + 2 * (int64_t)gridDim.x < count ? ld_global(list + item + 2 * (int64_t)gridDim.x + z) : 0;
     }
-    for (int s = threadIdx.x; s < TBL / 4; s += THREADS)
-      reinterpret_cast<int4 *>(s_keys)[s] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
-    for (int s = threadIdx.x; s < TBL / 2; s += THREADS) reinterpret_cast<double2 *>(s_vals)[s] = make_double2(0.0, 0.0);
     __syncthreads();
     src.visit_pre_block(jj, cur, w, NW, s_sc[w], status,
                         [&](int32_t row, double v) { ht_accumulate_sr<typename Src::Sr>(s_keys, s_vals, TBL, row, v); });
