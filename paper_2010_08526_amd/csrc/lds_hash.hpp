@@ -47,6 +47,27 @@ __device__ __forceinline__ void ht_accumulate_sr(int32_t *keys, double *vals, ui
   }
 }
 
+// As ht_accumulate_sr, and a call that claims a free slot appends the slot
+// to `slots` (at most `cap` of them; *n counts every claim), so the table can
+// be read out, and cleared, by walking the claimed slots only.
+template <class SR>
+__device__ __forceinline__ void ht_accumulate_list(int32_t *keys, double *vals, uint32_t T, int32_t key, double v,
+                                                   uint16_t *slots, int *n, int cap) {
+  uint32_t h = hash_slot(key, T);
+  for (uint32_t probe = 0; probe < T; probe++) {
+    const int32_t old = atomicCAS(&keys[h], kEmpty, key);
+    if (old == kEmpty || old == key) {
+      if (old == kEmpty) {
+        const int q = atomicAdd(n, 1);
+        if (q < cap) slots[q] = (uint16_t)h;
+      }
+      SR::acc(&vals[h], v);
+      return;
+    }
+    h = (h + 1 == T) ? 0 : h + 1;
+  }
+}
+
 // As ht_accumulate_sr on a table whose free slots hold 0: keys are stored
 // as key + 1 (key < INT32_MAX), so an all-zero table is empty and a pass
 // that reads the table out can leave it empty by writing zeros.
