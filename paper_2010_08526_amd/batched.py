@@ -190,11 +190,15 @@ def _cache_path() -> str:
 
 def _candidates():
     """Threshold sets for the numeric kernels: the defaults (load factor up
-    to 1/2), lighter tables (up to 3/8 and 1/4 full) and heavier use of the
-    wave tables."""
+    to 1/2), lighter tables (up to 3/8 and 1/4 full), and columns of more than
+    256 or 128 rows moved from the 1024-slot wave tables to the workgroup
+    tables."""
     out = [tuple(NUM_TABLE_CAP)]
     for lf in (0.375, 0.25):
         out.append(tuple(max(1, int(c * 2 * lf)) for c in NUM_TABLE_CAP))
+    c = list(NUM_TABLE_CAP)
+    for cap2 in (256, 128):
+        out.append(tuple([c[0], min(c[1], cap2), cap2] + c[3:]))
     return out
 
 
