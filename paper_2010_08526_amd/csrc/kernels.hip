@@ -786,24 +786,48 @@ __device__ __forceinline__ void init_mark(void *scratch) {
   ((int *)scratch)[lane()] = 0;  // both scratch layouts start with mark[64]
 }
 
+// Writes the occupied slots [s_lo, s_hi) of a table, in slot order, to
+// consecutive output positions from o on (one wave; positions at or beyond
+// `end` are not written), and leaves the slots it reads empty (key kEmpty,
+// value 0), so a table stays clear between columns without a clearing pass.
+// Returns the position after the last entry.
+template <class VT, class SR>
+__device__ __forceinline__ int64_t compact_run(int32_t *keys, double *vals, int s_lo, int s_hi, int64_t o,
+                                               int64_t end, int32_t *out_ri, VT *out_v) {
+  const int l = lane();
+  for (int s0 = s_lo; s0 < s_hi; s0 += kWave) {
+    const int s = s0 + l;
+    const int32_t key = s < s_hi ? keys[s] : kEmpty;
+    const bool occ = key != kEmpty;
+    const uint64_t mask = __ballot(occ);
+    const int64_t q = o + mbcnt(mask);
+    if (occ) {
+      const double x = vals[s];
+      keys[s] = kEmpty;
+      vals[s] = 0.0;
+      if (q < end) {
+        out_ri[q] = key;
+        out_v[q] = (VT)SR::out(x);
+      }
+    }
+    o += __popcll(mask);
+  }
+  return o;
+}
+
 template <int TBL, class VT, class Src>
 __global__ __launch_bounds__(256) void k_num_wave(Src src, const int32_t *list, const int32_t *count_p,
                                                   const int64_t *c_colptr, int32_t *out_ri, VT *out_v,
                                                   int32_t *status) {
   static_assert(TBL % 4 == 0, "tables cleared 16 bytes at a time");
-  static_assert(TBL <= 65536, "slot numbers fit 16 bits");
   __shared__ __align__(16) int32_t s_keys[4][TBL];
   __shared__ __align__(16) double s_vals[4][TBL];
   __shared__ __align__(16) char s_sc[4][kScratchBytes];
-  __shared__ uint16_t s_list[4][TBL / 2];  // claimed slots, in claim order
-  __shared__ int s_n[4];
   const int w = threadIdx.x / kWave, l = lane();
   const int count = *count_p;
   int32_t *keys = s_keys[w];
   double *vals = s_vals[w];
-  uint16_t *lst = s_list[w];
   init_mark<VT>(s_sc[w]);
-  if (l == 0) s_n[w] = 0;
   // cleared once: every compaction leaves the table empty again
   for (int s = l; s < TBL / 4; s += kWave) reinterpret_cast<int4 *>(keys)[s] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
   for (int s = l; s < TBL / 2; s += kWave) reinterpret_cast<double2 *>(vals)[s] = make_double2(0.0, 0.0);
@@ -838,30 +862,16 @@ __global__ __launch_bounds__(256) void k_num_wave(Src src, const int32_t *list, 
       jn2 = idx + 2 * stride < count ? ld_global(list + idx + 2 * stride + z) : 0;
     }
     wave_sync();
-    src.visit_pre(jj, cur, s_sc[w], status, [&](int32_t row, double v) {
-      ht_accumulate_list<typename Src::Sr>(keys, vals, TBL, row, v, lst, &s_n[w], TBL / 2);
-    });
+    src.visit_pre(jj, cur, s_sc[w], status,
+                  [&](int32_t row, double v) { ht_accumulate_sr<typename Src::Sr>(keys, vals, TBL, row, v); });
     if (more) src.pre_b(pre, 0, 1);
     wave_sync();
-    // the claimed slots, in claim order, to consecutive output positions;
-    // each slot is left empty again
-    const int n = s_n[w];
-    const int nl = min(n, TBL / 2);
-    for (int i = l; i < nl; i += kWave) {
-      const int sl = lst[i];
-      const int32_t key = keys[sl];
-      const double x = vals[sl];
-      keys[sl] = kEmpty;
-      vals[sl] = 0.0;
-      if (i < cap) {
-        out_ri[base + i] = key;
-        out_v[base + i] = (VT)Src::Sr::out(x);
-      }
-    }
+    // one wave owns the column: output positions follow a running count
+    // (a wave's table is small enough to scan; a list of claimed slots would
+    // cost a workgroup per CU)
+    const int64_t o = compact_run<VT, typename Src::Sr>(keys, vals, 0, TBL, base, base + cap, out_ri, out_v);
     if (more) src.pre_a(pre);
-    if (l == 0 && n != cap) flag_error(status, 4);
-    wave_sync();
-    if (l == 0) s_n[w] = 0;
+    if (l == 0 && o - base != cap) flag_error(status, 4);
     wave_sync();
   }
 }
