@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <utility>
 #include <mutex>
 #include <type_traits>
 #include <vector>
@@ -2055,8 +2056,8 @@ __device__ __forceinline__ int mb_part_of(const MbParts &mp, int n, int q) {
 template <class VT>
 __global__ __launch_bounds__(kMbThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_mb_bucket(const PartDesc *parts, int nparts, int64_t m, int P,
                                                           const int32_t *list, const int32_t *count_p, int64_t h0,
-                                                          int64_t h1, const int32_t *ord, int32_t *queue,
-                                                          const int64_t *base, int64_t ecap,
+                                                          int64_t h1, const int32_t *ord, int64_t t0, int64_t t1,
+                                                          int32_t *queue, const int64_t *base, int64_t ecap,
                                                           int32_t *soff, int32_t *brow, VT *bval, uint32_t *slots,
                                                           int32_t *status) {
   constexpr int NW = kMbThreads / kWave;
@@ -2073,14 +2074,23 @@ __global__ __launch_bounds__(kMbThreads) __attribute__((amdgpu_waves_per_eu(8)))
   __shared__ int s_next;
   const int64_t count = min((int64_t)*count_p, h1);
   const int64_t b0 = base[h0];
-  // columns from a work queue over ord[h0, h1), the chunk's columns longest
-  // first: a long column never starts late and holds the launch open
+  // tasks from a work queue over ord[t0, t1), the chunk's tasks largest
+  // first (a long task never starts late and holds the launch open).  A task
+  // is (h << 2) | mode: mode 0 takes column h whole; a long column is split
+  // into mode 1, its slabs below P / 2 placed from the start of its bucket
+  // range, and mode 2, the other slabs placed against the end of the range
+  // (the two halves need no count from each other).
+  const int mid = P / 2;
   for (;;) {
     if (threadIdx.x == 0) s_next = atomicAdd(queue, 1);
     __syncthreads();
-    const int64_t h = h0 + s_next < count ? (int64_t)ord[h0 + s_next] : count;
-    __syncthreads();  // s_next is written again for the next column
-    if (h >= count) break;
+    const int32_t task = t0 + s_next < t1 ? ord[t0 + s_next] : -1;
+    __syncthreads();  // s_next is written again for the next task
+    if (task < 0) break;
+    const int64_t h = task >> 2;
+    const int mode = task & 3;
+    if (h < h0 || h >= count) continue;  // uniform
+    const int slo = mode == 2 ? mid : 0, shi = mode == 1 ? mid : P;  // this task's slabs
     const int64_t jj = list[h];
     const int64_t bb = base[h] - b0, elen = base[h + 1] - base[h];
     for (int t = threadIdx.x; t < kMaxSlabs; t += kMbThreads) {
@@ -2116,10 +2126,12 @@ __global__ __launch_bounds__(kMbThreads) __attribute__((amdgpu_waves_per_eu(8)))
           const int32_t row = opaque(row_[u]);
           int sl = -1;
           if (ok_[u]) {
-            if (row >= 0 && (int64_t)row < m)
+            if (row >= 0 && (int64_t)row < m) {
               sl = row >> kSlabShift;
-            else
+              if (sl < slo || sl >= shi) sl = -1;  // the other half's slab
+            } else {
               bad = true;
+            }
           }
           int len;
           if (slab_run_head(sl, len)) atomicAdd(&s_cnt[sl], len);
@@ -2134,22 +2146,26 @@ __global__ __launch_bounds__(kMbThreads) __attribute__((amdgpu_waves_per_eu(8)))
     int total;
     int run = block_excl<NW>(loc, s_w, total);
     int32_t *so = soff + (h - h0) * (int64_t)(P + 1);
+    // the upper half is placed against the end of the column's range
+    const int64_t boff = mode == 2 ? elen - total : 0;
+    run += (int)boff;
     for (int i = 0; i < kPerT; i++) {
       const int t = threadIdx.x * kPerT + i;
       const int c = s_cnt[t];
       s_cur[t] = run;
-      if (t < P) so[t] = run;
+      if (t >= slo && t < shi) so[t] = run;
       run += c;
     }
-    if (threadIdx.x == 0) so[P] = total;
-    const bool fits = bb + total <= ecap && total <= elen;
+    if (threadIdx.x == 0 && mode != 1) so[P] = (int32_t)(boff + total);
+    const int64_t lim = boff + total;  // positions of this task stay below lim
+    const bool fits = bb + elen <= ecap && total <= elen;
     if (threadIdx.x == 0 && !fits) flag_error(status, 9);
     __syncthreads();
     if (w == 0) {  // items in slab order, formed by one wave 64 slabs at a time
-      int t = 0;
-      while (t < P) {
+      int t = slo;
+      while (t < shi) {
         const int u = t + l;
-        const int c = u < P ? s_cnt[u] : 0;
+        const int c = u < shi ? s_cnt[u] : 0;
         const uint64_t nz = __ballot(c > 0);
         if (nz == 0) {  // no entries in these slabs
           t += kWave;
@@ -2174,7 +2190,7 @@ __global__ __launch_bounds__(kMbThreads) __attribute__((amdgpu_waves_per_eu(8)))
         int t2 = t;
         for (;;) {
           const int v = t2 + l;
-          const bool ok = v < P && s_cur[v] + s_cnt[v] - e0 <= kHvCap;
+          const bool ok = v < shi && s_cur[v] + s_cnt[v] - e0 <= kHvCap;
           const uint64_t okm = __ballot(ok);  // a prefix of the lanes: the sums grow with v
           const int n = __popcll(okm);
           if (ok) s_map[v] = t;
@@ -2187,7 +2203,7 @@ __global__ __launch_bounds__(kMbThreads) __attribute__((amdgpu_waves_per_eu(8)))
     }
     __syncthreads();
     uint32_t *dst = slots + (h - h0) * (int64_t)P;
-    for (int t = threadIdx.x; t < P; t += kMbThreads) dst[t] = fits ? s_slot[t] : 0u;
+    for (int t = slo + threadIdx.x; t < shi; t += kMbThreads) dst[t] = fits ? s_slot[t] : 0u;
     // ---- scatter into the items' ranges
     if (fits) {
       for (int g0 = 0; g0 < nparts; g0 += kMbParts) {
@@ -2218,14 +2234,17 @@ __global__ __launch_bounds__(kMbThreads) __attribute__((amdgpu_waves_per_eu(8)))
             if (q0 + u * NW >= nch) break;  // uniform
             const int32_t row = opaque(row_[u]);
             int sl = -1;
-            if (ok_[u] && row >= 0 && (int64_t)row < m) sl = s_map[row >> kSlabShift];  // the item's range
+            if (ok_[u] && row >= 0 && (int64_t)row < m) {
+              const int rs = row >> kSlabShift;
+              if (rs >= slo && rs < shi) sl = s_map[rs];  // the item's range
+            }
             int len;
             int pos = 0;
             if (slab_run_head(sl, len)) pos = atomicAdd(&s_cur[sl], len);
             // every lane of a run takes the head's position plus its distance to the head
             const int head = run_head_lane(sl);
             pos = __shfl(pos, head, kWave) + (l - head);
-            if (sl >= 0 && pos < total) {  // positions stay inside the column's counted range
+            if (sl >= 0 && pos >= 0 && pos < lim) {  // positions stay inside the task's counted range
               brow[bb + pos] = row;
               bval[bb + pos] = opaque(val_[u]);
             }
@@ -3122,9 +3141,16 @@ static int merge_typed(const spgemm_csc *parts, int32_t n_parts, const int64_t *
   const int64_t hcap = std::max<int64_t>(1, hv_item_cap(L.ncol, L.P) / L.P);
   const int64_t ecap = L.mb_cap;
   // chunks of the heavy list whose entries fit the bucket region, and in
-  // each chunk the columns by decreasing entry count (the bucketing order)
-  std::vector<int64_t> cuts{0};
-  std::vector<int32_t> ord((size_t)heavy);
+  // each chunk its bucketing tasks by decreasing size: a column whole, or a
+  // long column as two tasks, one per half of its row slabs (task encoding
+  // (h << 2) | mode, see k_mb_bucket), so that no single column holds the
+  // launch open
+  if (heavy >= (int64_t(1) << 29)) return SPGEMM_E_OVERFLOW;
+  const int64_t split_min = std::max<int64_t>(int64_t(1) << 16, ecap / 2048);
+  std::vector<int64_t> cuts{0}, tcuts{0};
+  std::vector<int32_t> ord;
+  ord.reserve((size_t)heavy);
+  std::vector<std::pair<int64_t, int32_t>> tasks;
   for (int64_t h0 = 0; h0 < heavy;) {
     int64_t h1 = h0 + 1;
     while (h1 < heavy && h1 - h0 < hcap && hb[h1 + 1] - hb[h0] <= ecap) h1++;
@@ -3133,24 +3159,38 @@ static int merge_typed(const spgemm_csc *parts, int32_t n_parts, const int64_t *
       LAUNCHCHK();
       return SPGEMM_OK;
     }
-    for (int64_t h = h0; h < h1; h++) ord[h] = (int32_t)h;
-    std::stable_sort(ord.begin() + h0, ord.begin() + h1,
-                     [&](int32_t x, int32_t y) { return hb[x + 1] - hb[x] > hb[y + 1] - hb[y]; });
+    tasks.clear();
+    for (int64_t h = h0; h < h1; h++) {
+      const int64_t n = hb[h + 1] - hb[h];
+      if (n >= split_min && L.P >= 2) {
+        tasks.emplace_back((n + 1) / 2, (int32_t)((h << 2) | 1));
+        tasks.emplace_back(n / 2, (int32_t)((h << 2) | 2));
+      } else {
+        tasks.emplace_back(n, (int32_t)(h << 2));
+      }
+    }
+    std::stable_sort(tasks.begin(), tasks.end(), [](const std::pair<int64_t, int32_t> &x,
+                                                     const std::pair<int64_t, int32_t> &y) { return x.first > y.first; });
+    for (const auto &t : tasks) ord.push_back(t.second);
     cuts.push_back(h1);
+    tcuts.push_back((int64_t)ord.size());
     h0 = h1;
   }
-  int32_t *ord_d = (int32_t *)len;  // the lengths are no longer needed once scanned
-  HIPCHK(hipMemcpyAsync(ord_d, ord.data(), sizeof(int32_t) * (size_t)heavy, hipMemcpyHostToDevice, st));
+  // the lengths are no longer needed once scanned: their room (8 bytes per
+  // column) holds the tasks (at most two per heavy column, 4 bytes each)
+  int32_t *ord_d = (int32_t *)len;
+  HIPCHK(hipMemcpyAsync(ord_d, ord.data(), sizeof(int32_t) * ord.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));  // `ord` is host memory freed on return
   for (size_t c = 0; c + 1 < cuts.size(); c++) {
     const int64_t h0 = cuts[c], h1 = cuts[c + 1];
+    const int64_t t0 = tcuts[c], t1 = tcuts[c + 1];
     hipLaunchKernelGGL(k_hv_reset, dim3(1), dim3(64), 0, st, hdr);
     LAUNCHCHK();
     {
       ProfScope prof("merge_bucket", st);
-      const unsigned g = (unsigned)std::min<int64_t>(h1 - h0, 4 * (int64_t)device_cus());
+      const unsigned g = (unsigned)std::min<int64_t>(t1 - t0, 4 * (int64_t)device_cus());
       hipLaunchKernelGGL(k_mb_bucket<VT>, dim3(g), dim3(kMbThreads), 0, st, (const PartDesc *)pd, n_parts, L.m,
-                         (int)L.P, list, hcnt, h0, h1, (const int32_t *)ord_d, &hdr->mb_cursor,
+                         (int)L.P, list, hcnt, h0, h1, (const int32_t *)ord_d, t0, t1, &hdr->mb_cursor,
                          (const int64_t *)base, ecap, soff, brow, bval, slots, status);
       LAUNCHCHK();
     }

@@ -311,3 +311,22 @@ def test_one_column_per_batch():
     assert_matches(C, P, torch.float32, "b = ncols")
     cp, ri, v = host_sorted(C)
     assert np.array_equal(v, P.values)  # single-term products are exact
+
+
+@pytest.mark.parametrize("layers", [2, 6])
+def test_merge_long_columns_in_two_halves(layers):
+    """Merge columns of more than 65,536 partial entries are bucketed as two
+    tasks, one per half of the row slabs (the upper half placed against the
+    end of the column's bucket range): long columns beside short ones, over
+    an odd number of slabs, against the oracle."""
+    print(f"case: merge long columns, {layers} layers", flush=True)
+    from tests.test_gpu_global_heavy import _right
+    m = 300_000  # 74 slabs of 4096 rows
+    A = synth.erdos_renyi(m, 400, 400, 111, torch.float32)
+    B = _right(400, [400, 3, 350, 0, 200, 399, 60, 1, 380], torch.float32, seed=112)
+    P = oracle.spgemm(A, B)
+    parts = sum(np.diff(oracle.spgemm(A, B, klo=l * (400 // layers), khi=(l + 1) * (400 // layers)).colptr)
+                for l in range(layers))
+    assert int(parts.max()) >= 65536  # long columns exist
+    C, plan = S.Engine(A.to("cuda"), B.to("cuda"), layers, None).run()
+    assert_matches(C, P, torch.float32, f"merge long columns L={layers}")
