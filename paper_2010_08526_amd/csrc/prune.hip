@@ -137,6 +137,7 @@ __global__ __launch_bounds__(kPrThreads) void k_prune_select(const int64_t *__re
   __shared__ __align__(16) uint64_t s_wide[kWideBuckets / 2];
   __shared__ uint32_t s_srow[kStage];
   __shared__ int s_n;
+  __shared__ int s_ncw[kPrWaves];  // candidates counted by each wave
   int *s_whist = reinterpret_cast<int *>(s_wide);
   const int t = threadIdx.x;
   for (int64_t j = blockIdx.x; j < ncols; j += gridDim.x) {
@@ -152,8 +153,54 @@ __global__ __launch_bounds__(kPrThreads) void k_prune_select(const int64_t *__re
     uint32_t pr = 0;
     bool fast = k > 0 && k < INT32_MAX;  // the wide digit first; cleared when the digit loop must run
     if (fast) {
+      // A lower bound on the wide digit of the k-th largest key of a column
+      // longer than one step: the k-th largest of the per-thread maxima of
+      // the first step (k distinct entries at or above it), rounded down to
+      // its bucket.  Buckets below it cannot hold one of the k largest keys
+      // and are not counted (the candidates are counted apart).
+      int lo_dig = 0;
+      if (e - b > kSelUnroll * kPrThreads && k <= kPrThreads) {
+        uint64_t mk = 0;
+        bool has = false;
+#pragma unroll
+        for (int q = 0; q < kSelUnroll; q++) {
+          // (an opaque index: these loads stay apart from the histogram loop's)
+          const VT v = vals[opaque(b + q * kPrThreads + t)];
+          if (candidate(v, thr)) {
+            const uint64_t vk = order_key(v);
+            mk = vk > mk ? vk : mk;
+            has = true;
+          }
+        }
+        for (int i = t; i < kWideBuckets; i += kPrThreads) s_whist[i] = 0;
+        __syncthreads();
+        if (has) atomicAdd(&s_whist[(int)(mk >> kShift)], 1);
+        __syncthreads();
+        if (t < kWave) {
+          constexpr int PER = kWideBuckets / kWave;
+          int sum = 0;
+#pragma unroll 1
+          for (int q = 0; q < PER; q++) sum += s_whist[kWideBuckets - 1 - PER * t - q];
+          const int incl = wave_incl_add(sum);
+          if (t == kWave - 1 && incl < need) s_sel[0] = 0;  // fewer maxima than k: no bound
+          int acc = incl - sum;
+          if (acc < need && need <= incl) {
+#pragma unroll 1
+            for (int q = 0; q < PER; q++) {
+              acc += s_whist[kWideBuckets - 1 - PER * t - q];
+              if (acc >= need) {
+                s_sel[0] = kWideBuckets - 1 - PER * t - q;
+                break;
+              }
+            }
+          }
+        }
+        __syncthreads();
+        lo_dig = s_sel[0];
+      }
       for (int i = t; i < kWideBuckets; i += kPrThreads) s_whist[i] = 0;
       __syncthreads();
+      int nc = 0;  // this thread's candidates
       for (int64_t c0 = b; c0 < e; c0 += kSelUnroll * kPrThreads) {
         VT vq[kSelUnroll];
 #pragma unroll
@@ -164,10 +211,14 @@ __global__ __launch_bounds__(kPrThreads) void k_prune_select(const int64_t *__re
 #pragma unroll
         for (int q = 0; q < kSelUnroll; q++) {
           const int64_t p = c0 + q * kPrThreads + t;
-          const bool act = p < e && candidate(vq[q], thr);
-          hist_add(s_whist, act, act ? (int)(order_key(vq[q]) >> kShift) : 0);
+          const bool cand = p < e && candidate(vq[q], thr);
+          const int dig = cand ? (int)(order_key(vq[q]) >> kShift) : 0;
+          nc += cand ? 1 : 0;
+          hist_add(s_whist, cand && dig >= lo_dig, dig);
         }
       }
+      nc = wave_sum_i32(nc);
+      if (lane() == 0) s_ncw[t / kWave] = nc;
       __syncthreads();
       if (t < kWave) {
         // lane l owns buckets 4095 - 64l ... 4032 - 64l, scanned from the top
@@ -175,7 +226,12 @@ __global__ __launch_bounds__(kPrThreads) void k_prune_select(const int64_t *__re
         int sum = 0;
         for (int q = 0; q < PER; q++) sum += s_whist[kWideBuckets - 1 - PER * t - q];
         const int incl = wave_incl_add(sum);
-        if (t == kWave - 1) s_sel[3] = incl;
+        if (t == kWave - 1) {
+          int tot = 0;
+#pragma unroll
+          for (int z = 0; z < kPrWaves; z++) tot += s_ncw[z];
+          s_sel[3] = tot;
+        }
         int acc = incl - sum;
         if (acc < need && need <= incl) {
           for (int q = 0; q < PER; q++) {
@@ -364,7 +420,9 @@ __global__ __launch_bounds__(kPrThreads) void k_prune_fill(
     const int64_t *__restrict__ out_colptr, int32_t *__restrict__ out_rowidx, VT *__restrict__ out_vals,
     int32_t *status) {
   __shared__ int s_cnt[kFillUnroll][kPrWaves];
+  __shared__ int s_any[2][kPrWaves];
   const int t = threadIdx.x, w = t / kWave;
+  int par = 0;
   for (int64_t j = blockIdx.x; j < ncols; j += gridDim.x) {
     int64_t b = colptr[j], e = colptr[j + 1];
     if (b < 0 || e < b || e > nnz) b = e = 0;  // flagged by the select kernel
@@ -393,6 +451,19 @@ __global__ __launch_bounds__(kPrThreads) void k_prune_fill(
           if (vk > cv || (vk == cv && row_key(rowidx[p]) >= cr)) keep |= 1u << q;
         }
       }
+      // a step in which no wave keeps an entry (the common case: k is
+      // small against the column) only exchanges one flag per wave, through
+      // two alternating flag sets (a set is rewritten two steps later, after
+      // every wave has passed the barrier between)
+      const bool wkeep = __ballot(keep != 0u) != 0ull;
+      int *any_w = s_any[par];
+      par ^= 1;
+      if (lane() == 0) any_w[w] = wkeep ? 1 : 0;
+      __syncthreads();
+      bool any = false;
+#pragma unroll
+      for (int z = 0; z < kPrWaves; z++) any |= any_w[z] != 0;
+      if (!any) continue;
       int below[kFillUnroll];
 #pragma unroll
       for (int q = 0; q < kFillUnroll; q++) {
