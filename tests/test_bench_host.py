@@ -39,13 +39,28 @@ def test_measured_traffic_is_tied_to_the_device_sources(tmp_path, monkeypatch):
     assert b.measured_traffic("heavy_items", "rmat20") is None  # sources changed since the counters
 
 
-def test_source_digest_covers_every_device_source():
+def test_source_digest_covers_the_product_kernels(tmp_path, monkeypatch):
     b = _bench()
     d0 = b.source_digest()
     assert len(d0) == 64 and d0 == b.source_digest()
     csrc = os.path.join(ROOT, "paper_2010_08526_amd", "csrc")
     names = sorted(n for n in os.listdir(csrc) if n.endswith((".hip", ".hpp")))
-    assert "kernels.hip" in names and "backward.hip" in names
+    assert "kernels.hip" in names and "device.hpp" in names
+    # a copy of the sources: an edit to kernels.hip or a header changes the
+    # digest, an edit to another translation unit does not
+    pkg = tmp_path / "paper_2010_08526_amd" / "csrc"
+    pkg.mkdir(parents=True)
+    for n in names:
+        (pkg / n).write_bytes(open(os.path.join(csrc, n), "rb").read())
+    monkeypatch.setattr(b, "ROOT", str(tmp_path))
+    assert b.source_digest() == d0
+    (pkg / "prune.hip").write_text("// another translation unit\n")
+    assert b.source_digest() == d0
+    (pkg / "device.hpp").write_text("// a header\n")
+    d1 = b.source_digest()
+    assert d1 != d0
+    (pkg / "kernels.hip").write_text("// the product kernels\n")
+    assert b.source_digest() != d1
 
 
 
