@@ -166,3 +166,46 @@ def test_spgemm_topk_keeps_only_pruned_batches():
     order = np.lexsort((P.rowidx, col))
     assert np.array_equal(ri, P.rowidx[order]) and np.array_equal(v, P.values[order])
     assert G.nnz <= k * A.ncols
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_prune_first_step_bound(dtype):
+    """Columns longer than one select step (2048 entries), built against the
+    lower bound the select takes from its first step (the k-th largest of
+    the per-thread maxima of entries 0 ... 2047): the largest entries all
+    after the first step; the k largest all inside it, with later entries
+    tying the k-th at smaller rows; a first step holding fewer than k
+    candidates (NaN and values below the threshold); signed zeros and
+    negative values in the first step."""
+    print(f"case: prune first-step bound {dtype}", flush=True)
+    rng = np.random.default_rng(31)
+    m = 50_000
+    cols = []
+    n = 5000
+    # largest entries only after the first step
+    v = np.concatenate([rng.uniform(0.0, 1.0, 2048), rng.uniform(10.0, 20.0, n - 2048)])
+    cols.append(v)
+    # the 200 largest inside the first step (5.0, 5.25, ..., 54.75), later
+    # entries tying the smallest twelve of them (5.0 ... 7.75)
+    v = rng.uniform(0.0, 1.0, n)
+    top = rng.choice(2048, 200, replace=False)
+    v[top] = 5.0 + 0.25 * np.arange(200)[::-1]
+    v[2048 + rng.choice(n - 2048, 40, replace=False)] = 5.0 + (0.25 * np.arange(40)) % 3.0
+    cols.append(v)
+    # a first step of NaN and small values, candidates later
+    v = np.concatenate([np.full(2048, np.nan), rng.uniform(0.0, 1.0, n - 2048)])
+    v[rng.choice(2048, 30, replace=False)] = 0.75
+    cols.append(v)
+    # signed zeros and negatives up front, positives later
+    v = np.concatenate([rng.choice([-0.0, 0.0, -1.0, -2.5], 2048), rng.uniform(-1.0, 1.0, n - 2048)])
+    cols.append(v)
+    # every entry equal
+    cols.append(np.full(n, 0.5))
+    cp = np.concatenate([[0], np.cumsum([len(c) for c in cols])]).astype(np.int64)
+    ri = np.concatenate([rng.permutation(m)[:len(c)] for c in cols]).astype(np.int32)
+    vals = torch.from_numpy(np.concatenate(cols)).to(dtype)
+    M = synth.CSC(m, len(cols), torch.from_numpy(cp), torch.from_numpy(ri), vals)
+    for thr in (-np.inf, 0.5):
+        for k in (1, 100, 189, 190, 195, 200, 201, 255, 256, 257, 2047, 2048, 2049):
+            G = S.prune_topk(M.to("cuda"), thr, k)
+            _assert_exact(G, oracle.prune_topk(M, thr, k), f"first-step bound {thr} {k}")
