@@ -13,11 +13,15 @@
 // it as the selection does: the value mapped onto an unsigned integer in
 // numeric order (-0 folded onto +0), then the row mapped so that a smaller
 // row ranks higher.  Rows are unique inside a column, so keys are too, and
-// a most-significant-digit radix select (8-bit digits, a 256-bucket LDS
-// histogram per digit) ends with a cut key: an entry is kept iff it is a
-// candidate and its key is at least the cut.  A scan of the per-column
-// counts gives the output column pointers, and a second kernel compacts the
-// kept entries in order with one exchange of per-wave counts per 2048 entries.
+// a most-significant-digit radix select ends with a cut key: an entry is
+// kept iff it is a candidate and its key is at least the cut.  The first
+// digit is wide (12 bits, a 4096-bucket LDS histogram that skips entries
+// below a lower bound on the k-th largest key's digit) and its chosen bucket
+// is usually settled by sorting its candidates in LDS; otherwise 8-bit
+// digits (256-bucket histograms) follow.  A scan of the per-column counts
+// gives the output column pointers, and a second kernel compacts the kept
+// entries in order with one exchange of per-wave counts per 2048 entries
+// that keep any (one flag per wave for those that keep none).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
